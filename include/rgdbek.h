@@ -1,0 +1,204 @@
+/*
+ * rgdbek.h -- C-ABI of the MI355X (gfx950) RGDBEK solver.
+ *
+ * RGDBEK (randomized greedy double block extended Kaczmarz, arXiv 2509.19267)
+ * solves A x = b for A in R^{m x n}, consistent or in the least-squares sense
+ * (the paper's problem statement, eq. (1) of Section 1).  Each iteration
+ * (Section 2, Algorithm 1):
+ *   column phase: eps^z_j = (A_(j)^T z)^2 / ||A_(j)||^2, draw a block U of
+ *                 k_col columns with probability proportional to eps^z,
+ *                 z <- z - A_U A_U^+ z;
+ *   row phase:    r = b - z - A x, eps^x_i = r_i^2 / ||A^(i)||^2, draw a block
+ *                 J of k_row rows the same way, x <- x + (A^J)^+ r^J,
+ * starting from x_0 = 0 and z_0 = b.  Block draws are without replacement
+ * (successive weighted sampling through exponential keys driven by a
+ * counter-based Philox4x64-10 generator keyed by the seed), so a solve is a
+ * pure function of (A, b, parameters, seed).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named "device" are HIP device pointers; everything else is host.
+ *  - Work is enqueued on the HIP stream given to rgdbek_create (NULL = the
+ *    default stream); entry points that return results to the host
+ *    synchronise that stream before returning.
+ *  - Status codes only: no C++ exception crosses this interface.  On an error
+ *    the handle's message (rgdbek_last_error) says what was wrong.
+ *  - A handle is not thread-safe: use one handle per host thread and stream.
+ */
+#ifndef RGDBEK_H
+#define RGDBEK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rgdbek_ctx *rgdbek_handle;
+
+typedef enum {
+  RGDBEK_OK = 0,
+  RGDBEK_ERR_INVALID_ARG = 1,   /* bad size, pointer, structure or option   */
+  RGDBEK_ERR_NUMERIC = 2,       /* NaN/Inf in A or b, or a NaN weight       */
+  RGDBEK_ERR_NOT_CONVERGED = 3, /* max_iter reached before the stop test    */
+  RGDBEK_ERR_OUT_OF_MEMORY = 4, /* a device allocation failed               */
+  RGDBEK_ERR_DEVICE = 5,        /* a HIP call failed (message has details)  */
+  RGDBEK_ERR_UNSUPPORTED = 6    /* valid request this build does not serve  */
+} rgdbek_status;
+
+/* Matrix storage (rgdbek_matrix.layout). */
+enum { RGDBEK_DENSE_ROW_MAJOR = 0, RGDBEK_CSR = 1 };
+/* Value type of the matrix values given to rgdbek_create. */
+enum { RGDBEK_F64 = 0, RGDBEK_F32 = 1 };
+/* Stopping tests (rgdbek_params.stop):
+ *  NONE     run exactly max_iter iterations;
+ *  ERR_REF  ||x_k - x_ref|| <= tol ||x_ref||, tested at the top of iteration k
+ *           (needs x_ref: the planted solution of a benchmark);
+ *  RSE      ||b - A x_k||^2 <= tol ||b||^2, the paper's squared relative
+ *           residual (Sections 3 and 5), tested when A x_k is formed;
+ *  RES_EXT  ||b - z_{k+1} - A x_k|| <= tol ||b||, the extended residual that
+ *           also goes to zero for inconsistent (least-squares) systems.
+ * Every test returns x_k, the iterate it was evaluated on. */
+enum { RGDBEK_STOP_NONE = 0, RGDBEK_STOP_ERR_REF = 1, RGDBEK_STOP_RSE = 2,
+       RGDBEK_STOP_RES_EXT = 3 };
+/* Arithmetic of the solve (rgdbek_params.precision):
+ *  FP64       every step in FP64;
+ *  MIXED_F32  inner RGDBEK iterations with FP32 matrix values, vectors and
+ *             accumulation, inside an FP64 refinement loop whose residuals
+ *             b - z - A x and A^T z, norms and stopping test are FP64;
+ *  MIXED_BF16 as MIXED_F32 with the inner matrix values rounded to bfloat16
+ *             (accumulation stays FP32). */
+enum { RGDBEK_PREC_FP64 = 0, RGDBEK_PREC_MIXED_F32 = 1,
+       RGDBEK_PREC_MIXED_BF16 = 2 };
+
+/* The coefficient matrix A (m x n).  All pointers are device pointers owned
+ * by the caller and read only during rgdbek_create: the library copies and
+ * converts what it needs, so the caller may free them once create returns.
+ *  dense:  values = m*n entries, row-major (entry (i,j) at i*n + j); nnz is
+ *          ignored; row_ptr/col_idx must be NULL.
+ *  CSR:    row_ptr[m+1] (int64, row_ptr[0] = 0, non-decreasing,
+ *          row_ptr[m] = nnz), col_idx[nnz] in [0, n) and strictly increasing
+ *          within each row, values[nnz]. */
+typedef struct {
+  int64_t m, n, nnz;
+  int32_t layout;      /* RGDBEK_DENSE_ROW_MAJOR or RGDBEK_CSR   */
+  int32_t value_type;  /* RGDBEK_F64 or RGDBEK_F32               */
+  const void *values;
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+} rgdbek_matrix;
+
+typedef struct {
+  int64_t k_col, k_row;  /* block sizes; 0 = derive from eta: k = min(d,
+                            max(1, floor(eta*d + 0.5))) for d = n resp. m   */
+  double eta;            /* block fraction of Algorithm 1 (0.5 in Section 3,
+                            0.1 in Section 5)                              */
+  double tol;            /* tolerance of the stopping test                  */
+  int32_t stop;          /* RGDBEK_STOP_*                                   */
+  int32_t precision;     /* RGDBEK_PREC_*                                   */
+  int64_t max_iter;      /* the paper's T: cap on (inner) iterations        */
+  uint64_t seed;         /* Philox key word 0                               */
+  int32_t inner_max;     /* cap on inner solver steps per projection (0 = 64) */
+  int32_t graph_iters;   /* iterations per captured HIP graph (0 = 8)       */
+  double inner_tol;      /* relative tolerance of the block projections
+                            (0 = 1e-14 in FP64, 1e-7 in FP32)             */
+  int32_t solver;        /* RGDBEK_SOLVER_* for dense blocks (0 = auto)     */
+  int32_t flags;         /* RGDBEK_FLAG_*                                   */
+} rgdbek_params;
+
+/* Dense block solvers: AUTO picks Cholesky for blocks up to 256 and
+ * preconditioned conjugate gradients on the Gram matrix above that. */
+enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
+/* Flags: GRAPH captures the iteration loop into HIP graphs (default on via
+ * rgdbek_params_default); GRAM_AAT precomputes A A^T for dense row blocks. */
+enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2 };
+
+typedef struct {
+  int64_t iterations;        /* RGDBEK iterations run (inner, summed)       */
+  int64_t outer_iterations;  /* FP64 refinement passes (mixed precision)    */
+  double final_metric;       /* value of the stopping test's left side      */
+  int32_t converged;         /* 1 when the stopping test held (NONE: 1)     */
+  int32_t status;            /* the status the call returned                */
+  double seconds;            /* wall time of the solve (host clock)         */
+} rgdbek_info;
+
+/* Fill *p with the defaults: k from eta = 0.5, tol 1e-8, STOP_ERR_REF,
+ * FP64, max_iter 10000, seed 0, GRAPH flag on.  INVALID_ARG if p is NULL. */
+rgdbek_status rgdbek_params_default(rgdbek_params *p);
+
+/* Build a solver for A: copies A to library-owned device storage (row-major
+ * and column-major copies for dense A; CSR and CSC for sparse A), computes
+ * the row and column squared norms (the denominators of the residual weights
+ * of Section 2) and allocates all work space.  `stream` is a hipStream_t
+ * (NULL = default stream).  On success *out receives the handle.
+ * Errors: INVALID_ARG (sizes, NULL pointers, k > dimension, CSR structure),
+ * NUMERIC (NaN/Inf in A), OUT_OF_MEMORY, DEVICE. */
+rgdbek_status rgdbek_create(const rgdbek_matrix *A, const rgdbek_params *p,
+                            void *stream, rgdbek_handle *out);
+
+/* Solve A x = b (Algorithm 1 with the handle's parameters).
+ *  b      device, m entries, FP64;
+ *  x      device, n entries, FP64, output only (x_0 = 0);
+ *  x_ref  device, n entries, FP64, required for STOP_ERR_REF, else NULL;
+ *  info   host, may be NULL.
+ * Returns OK when the stopping test held (or STOP_NONE ran max_iter),
+ * NOT_CONVERGED when max_iter ran out first (x still holds the last iterate),
+ * NUMERIC on NaN/Inf in b or a NaN weight during the solve. */
+rgdbek_status rgdbek_solve(rgdbek_handle h, const void *b, void *x,
+                           const void *x_ref, rgdbek_info *info);
+
+/* As rgdbek_solve but resuming from a saved state: x (n) and z (m) are read
+ * as x_{it0}, z_{it0} and overwritten with the final iterates, and the
+ * generator counter starts at it0.  Running K iterations, then resuming for
+ * K more, reproduces 2K uninterrupted iterations bit for bit. */
+rgdbek_status rgdbek_solve_resume(rgdbek_handle h, const void *b, void *x,
+                                  void *z, int64_t it0, const void *x_ref,
+                                  rgdbek_info *info);
+
+/* Copy the auxiliary vector z (m entries, FP64, device) of the last solve. */
+rgdbek_status rgdbek_get_z(rgdbek_handle h, void *z);
+
+/* Solve the adjoint system A^T w = g (n equations, m unknowns) with the same
+ * kernels and storage: the roles of rows and columns swap, and the generator
+ * uses key word 1 = 1.  g: device, n FP64; w: device, m FP64 (output).
+ * Stop test: RES_EXT/RSE/NONE as set in the handle (ERR_REF is treated as
+ * RES_EXT with the same tol). */
+rgdbek_status rgdbek_solve_adjoint(rgdbek_handle h, const void *g, void *w,
+                                   rgdbek_info *info);
+
+/* Gradient of a loss through x = A^+ b restricted to A's sparsity pattern:
+ * dA_values[e] = r_i lam_j - w_i x_j for each stored entry e = (i, j) of A
+ * (for dense A every entry, row-major).  r, w: device, m FP64; lam, x:
+ * device, n FP64; lam may be NULL (consistent systems, r = 0 term dropped);
+ * dA_values: device, nnz (dense: m*n) FP64, output. */
+rgdbek_status rgdbek_grad_pattern(rgdbek_handle h, const void *r,
+                                  const void *lam, const void *w,
+                                  const void *x, void *dA_values);
+
+/* One block draw on given weights, exactly as the solver does it (for
+ * parity tests): the k indices (ascending) drawn without replacement with
+ * probability proportional to eps, through keys E_j / eps_j with
+ * E_j = -ln(u_j), u_j from Philox4x64-10 counter (j>>2, it, phase, sys) and
+ * key (seed, key1), word j&3.  Indices with eps_j = 0 are never drawn; when at
+ * most k weights are positive all of them are returned.
+ *  eps: device, d FP64;  out_idx: device, room for min(k, d) int32;
+ *  out_count: host, receives the number of indices written.
+ * NUMERIC if a weight is NaN, negative or infinite. */
+rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
+                            uint64_t seed, uint64_t key1, uint64_t it,
+                            uint32_t phase, uint32_t sys, int32_t *out_idx,
+                            int64_t *out_count, void *stream);
+
+/* Release everything the handle owns.  NULL is a no-op. */
+rgdbek_status rgdbek_destroy(rgdbek_handle h);
+
+/* Static description of a status code. */
+const char *rgdbek_status_string(rgdbek_status s);
+
+/* Message of the last error on h (empty string if none; h may be NULL for
+ * errors raised before a handle existed). */
+const char *rgdbek_last_error(rgdbek_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RGDBEK_H */

@@ -1,0 +1,75 @@
+"""Closed-form references -- oracle side.
+
+Theorem 2.3 (Section 2) names the limits RGDBEK converges to: the
+minimum-norm solution x* = A^+ b and the optimal residual r = (I - A A^+) b,
+which the auxiliary vector z tracks.  These are computed here directly from
+the SVD pseudoinverse (``numpy.linalg.pinv``) for small systems.
+
+Differentiation (not part of the paper): for A of full column rank the map
+(A, b) -> x = A^+ b has the implicit gradient, for a loss L with
+gx = dL/dx,
+    w = (A^T)^+ gx = A (A^T A)^{-1} gx          (= dL/db)
+    lam = A^+ w = (A^T A)^{-1} gx
+    dL/dA = r lam^T - w x^T,    r = b - A x,
+obtained by differentiating x = (A^T A)^{-1} A^T b.  For a consistent system
+r = 0 and the first term drops.  ``grad_via_solves`` computes the same
+quantities with two runs of the oracle solver (the adjoint system A^T w = gx,
+then A lam = w) so that a GPU gradient can be compared with either.
+
+Test infrastructure only (see the package docstring).
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .rgdbek import rgdbek
+
+
+def pinv_solution(a):
+    """(x*, r) as functions of b for a small dense matrix: returns a
+    callable b -> (A^+ b, (I - A A^+) b)."""
+    a = np.asarray(a, dtype=np.float64)
+    p = np.linalg.pinv(a)
+
+    def apply(b):
+        x = p @ b
+        return x, b - a @ x
+    return apply
+
+
+def grad_reference(a, b, gx):
+    """Dense pinv reference of (dL/dA, dL/db) for L with dL/dx = gx."""
+    a = np.asarray(a, dtype=np.float64)
+    p = np.linalg.pinv(a)
+    x = p @ b
+    r = b - a @ x
+    w = p.T @ gx
+    lam = p @ w
+    return np.outer(r, lam) - np.outer(w, x), w
+
+
+def grad_via_solves(a, b, gx, x, *, k_col, k_row, max_iter, seed=0, tol=1e-13,
+                    least_squares=True):
+    """(dA restricted to A's pattern, w, lam) from two oracle RGDBEK solves.
+
+    The adjoint solve runs Algorithm 1 on A^T (n x m) with right-hand side
+    gx and key word 1 = 1; the second solve runs on A with right-hand side w.
+    Returns dA as a dense array for dense A and as the values of A's stored
+    entries (CSR order) for sparse A."""
+    at = a.T.tocsr() if sp.issparse(a) else np.ascontiguousarray(a.T)
+    w, _, _ = rgdbek(at, gx, k_col=k_row, k_row=k_col, max_iter=max_iter,
+                     seed=seed, key1=1, stop="res_ext", tol=tol)
+    r = b - a @ x
+    if least_squares:
+        lam, _, _ = rgdbek(a, w, k_col=k_col, k_row=k_row, max_iter=max_iter,
+                           seed=seed, key1=1, stop="res_ext", tol=tol)
+    else:
+        lam = np.zeros_like(x)
+    if sp.issparse(a):
+        c = sp.csr_matrix(a)
+        c.sort_indices()
+        rows = np.repeat(np.arange(c.shape[0]), np.diff(c.indptr))
+        cols = c.indices
+        da = r[rows] * lam[cols] - w[rows] * x[cols]
+    else:
+        da = np.outer(r, lam) - np.outer(w, x)
+    return da, w, lam
