@@ -1,0 +1,217 @@
+"""Benchmark: time to 1e-8 relative error of RGDBEK on one MI355X.
+
+Workload (default): dense inconsistent least squares, A 20000 x 5000 with
+i.i.d. N(0,1) entries, b = A x* + r with r in null(A^T), ||r|| = 0.1 ||A x*||
+(synthetic, seed 0).  One "step" is one full solve from x_0 = 0 to
+||x - x*|| / ||x*|| <= 1e-8, inputs resident in HBM.  Two forms are timed:
+plain FP64 and the mixed form (FP32 inner iterations, FP64 refinement); the
+headline value is the faster one.  Also reported: the roofline of the
+dominant kernel (the fused A x / A^T z pass, HBM-bound) timed with HIP events
+on the stream it runs on, and the FP64 oracle timed on the host cores on a
+bounded sample.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "time to 1e-8 rel. error + SpMV HBM GB/s; mixed/batched vs plain FP64 GPU"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m", type=int, default=20000)
+    ap.add_argument("--n", type=int, default=5000)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--kc", type=int, default=0)
+    ap.add_argument("--kr", type=int, default=0)
+    ap.add_argument("--tune", action="store_true",
+                    help="sweep block sizes before timing (slow)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp64,mixed_f32")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2509_19267_amd as rg
+    from paper_2509_19267_amd import tune
+    import workloads
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    prob = workloads.dense_least_squares(args.m, args.n, seed=0)
+    log(f"generated {args.m}x{args.n} least-squares problem in {time.time()-t0:.1f}s")
+    a = torch.as_tensor(prob.a).to(dev)
+    b = torch.as_tensor(prob.b).to(dev)
+    xs = torch.as_tensor(prob.x_star).to(dev)
+    stream = torch.cuda.Stream()
+
+    choice = tune.lookup("dense", args.m, args.n)
+    if args.kc and args.kr:
+        choice = dict(k_col=args.kc, k_row=args.kr, gram_aat=False)
+    if args.tune or choice is None:
+        choice = tune.tune_dense(a, b, xs, stream=stream, log=log)
+    log(f"block sizes {choice}")
+
+    forms = {}
+    handles = {}
+    for form in args.forms.split(","):
+        kw = dict(k_col=choice["k_col"], k_row=choice["k_row"],
+                  gram_aat=choice.get("gram_aat", False), stop="err_ref",
+                  tol=args.tol, max_iter=20000, precision=form, stream=stream)
+        tc = time.time()
+        s = rg.Solver(a, **kw)
+        create_s = time.time() - tc
+        handles[form] = s
+        for _ in range(args.warmup):
+            s.solve(b, x_ref=xs)
+        torch.cuda.synchronize()
+        times, its, errs = [], [], []
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            x, info = s.solve(b, x_ref=xs)
+            times.append(time.perf_counter() - t1)
+            its.append(info["iterations"])
+            errs.append(float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs)))
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ev_ms = ev0.elapsed_time(ev1) / args.steps
+        forms[form] = dict(ms_per_solve=1e3 * float(np.mean(times)),
+                           ms_min=1e3 * float(np.min(times)),
+                           ms_events=ev_ms, iterations=int(np.median(its)),
+                           outer=int(info["outer_iterations"]),
+                           rel_err=float(np.max(errs)),
+                           converged=bool(info["converged"]),
+                           create_s=create_s)
+        log(f"{form}: {forms[form]}")
+
+    # roofline of the dominant kernel: the fused pass A x, A^T z (FP64 and,
+    # for the mixed form, FP32), timed with events on the handle's stream
+    m, n = args.m, args.n
+    roof = {}
+    for form, prec, vb in [("fp64", "f64", 8), ("mixed_f32", "f32", 4)]:
+        if form not in handles:
+            continue
+        s = handles[form]
+        dt = torch.float64 if prec == "f64" else torch.float32
+        xv = torch.randn(n, dtype=dt, device=dev)
+        zv = torch.randn(m, dtype=dt, device=dev)
+        ax = torch.empty(m, dtype=dt, device=dev)
+        atz = torch.empty(n, dtype=dt, device=dev)
+        for _ in range(3):
+            s.apply(xv, zv, ax, atz, precision=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.apply_reps):
+            s.apply(xv, zv, ax, atz, precision=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / args.apply_reps
+        alg_bytes = m * n * vb + 2 * (m + n) * vb
+        gbs = alg_bytes / (us * 1e-6) / 1e9
+        roof[prec] = dict(us=us, alg_bytes=alg_bytes, gbs=gbs)
+        log(f"fused pass {prec}: {us:.1f} us per launch, {gbs:.0f} GB/s")
+
+    best_form = min(forms, key=lambda f: forms[f]["ms_per_solve"])
+    best = forms[best_form]
+    dom = "f32" if best_form == "mixed_f32" and "f32" in roof else "f64"
+    r = roof.get(dom)
+    roofline = None
+    if r:
+        roofline = {"bound": "hbm", "achieved": round(r["gbs"], 1),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(r["gbs"] / PEAK_HBM_GBS, 4),
+                    "traffic": None,
+                    "kernel": f"dense_fused_kernel<{'float' if dom == 'f32' else 'double'}> (+finalize)",
+                    "alg_bytes_per_launch": r["alg_bytes"],
+                    "us_per_launch": round(r["us"], 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, choice, forms.get("fp64", best)["iterations"])
+
+    out = {
+        "metric": METRIC, "value": round(best["ms_per_solve"], 3), "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(best["ms_per_solve"], 3),
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32+f64" if best_form == "mixed_f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"dense_least_squares_{m}x{n}", "m": m, "n": n,
+                   "tol": args.tol, "form": best_form,
+                   "k_col": choice["k_col"], "k_row": choice["k_row"],
+                   "gram_aat": bool(choice.get("gram_aat", False))},
+        "forms": forms,
+        "speedup_mixed_vs_fp64": (round(forms["fp64"]["ms_per_solve"] /
+                                        forms["mixed_f32"]["ms_per_solve"], 3)
+                                  if "fp64" in forms and "mixed_f32" in forms else None),
+        "roofline": roofline,
+        "roofline_all": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    for s in handles.values():
+        s.close()
+
+
+def cpu_baseline(prob, choice, gpu_iters, budget_s=20.0):
+    """The FP64 oracle on the host cores: a bounded sample of full-size
+    iterations (same block sizes), scaled to the iterations the FP64 GPU path
+    needed to reach the tolerance."""
+    from oracle.rgdbek import rgdbek
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    it = 0
+    t0 = time.perf_counter()
+    x, z = None, None
+    while True:
+        x, z, _ = rgdbek(prob.a, prob.b, k_col=choice["k_col"],
+                         k_row=choice["k_row"], max_iter=1, seed=0,
+                         x0=x, z0=z, it0=it)
+        it += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or it >= 50:
+            break
+    per_it = el / it
+    return {"value": round(per_it * gpu_iters * 1e3, 1), "unit": "ms",
+            "cores": int(cores), "kind": "oracle",
+            "sample": f"{it} full-size oracle iterations ({el:.1f} s, "
+                      f"{per_it*1e3:.0f} ms each) scaled to the {gpu_iters} "
+                      f"iterations of the FP64 GPU solve"}
+
+
+if __name__ == "__main__":
+    main()

@@ -17,9 +17,10 @@
  *
  * Conventions for every entry point:
  *  - Pointers named "device" are HIP device pointers; everything else is host.
- *  - Work is enqueued on the HIP stream given to rgdbek_create (NULL = the
- *    default stream); entry points that return results to the host
- *    synchronise that stream before returning.
+ *  - Work is enqueued on the HIP stream given to rgdbek_create; for NULL the
+ *    handle creates a private stream (HIP graphs cannot be captured on the
+ *    default stream).  Entry points first wait for the caller's stream, and
+ *    those that return results synchronise the work stream before returning.
  *  - Status codes only: no C++ exception crosses this interface.  On an error
  *    the handle's message (rgdbek_last_error) says what was wrong.
  *  - A handle is not thread-safe: use one handle per host thread and stream.
@@ -63,8 +64,11 @@ enum { RGDBEK_STOP_NONE = 0, RGDBEK_STOP_ERR_REF = 1, RGDBEK_STOP_RSE = 2,
 /* Arithmetic of the solve (rgdbek_params.precision):
  *  FP64       every step in FP64;
  *  MIXED_F32  inner RGDBEK iterations with FP32 matrix values, vectors and
- *             accumulation, inside an FP64 refinement loop whose residuals
- *             b - z - A x and A^T z, norms and stopping test are FP64;
+ *             accumulation, inside an FP64 refinement loop: each pass sets
+ *             z = b - A x and forms A^T z in FP64, the FP32 iterations solve
+ *             for the correction (dx, dz) from (0, 0), and x += dx in FP64;
+ *             norms and the stopping test are FP64.  Stop modes ERR_REF,
+ *             RSE and NONE (RES_EXT is UNSUPPORTED in this form);
  *  MIXED_BF16 as MIXED_F32 with the inner matrix values rounded to bfloat16
  *             (accumulation stays FP32). */
 enum { RGDBEK_PREC_FP64 = 0, RGDBEK_PREC_MIXED_F32 = 1,
@@ -103,6 +107,11 @@ typedef struct {
                             (0 = 1e-14 in FP64, 1e-7 in FP32)             */
   int32_t solver;        /* RGDBEK_SOLVER_* for dense blocks (0 = auto)     */
   int32_t flags;         /* RGDBEK_FLAG_*                                   */
+  double weight_floor;   /* residual weights <= weight_floor * max weight
+                            count as zero (zero up to rounding): 0 = default
+                            (1e-20 for FP64 weights, 1e-6 for the FP32 inner
+                            iterations of the mixed form); < 0 = exact
+                            zero test only                                  */
 } rgdbek_params;
 
 /* Dense block solvers: AUTO picks Cholesky for blocks up to 256 and
@@ -178,15 +187,27 @@ rgdbek_status rgdbek_grad_pattern(rgdbek_handle h, const void *r,
  * parity tests): the k indices (ascending) drawn without replacement with
  * probability proportional to eps, through keys E_j / eps_j with
  * E_j = -ln(u_j), u_j from Philox4x64-10 counter (j>>2, it, phase, sys) and
- * key (seed, key1), word j&3.  Indices with eps_j = 0 are never drawn; when at
- * most k weights are positive all of them are returned.
+ * key (seed, key1), word j&3 (Section 2 probabilities; Algorithm 1 block
+ * draws).  Indices with eps_j <= floor * max(eps) (floor <= 0: eps_j == 0)
+ * are never drawn; when at most k weights pass, all of them are returned.
  *  eps: device, d FP64;  out_idx: device, room for min(k, d) int32;
  *  out_count: host, receives the number of indices written.
  * NUMERIC if a weight is NaN, negative or infinite. */
 rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
-                            uint64_t seed, uint64_t key1, uint64_t it,
+                            double floor, uint64_t seed, uint64_t key1,
+                            uint64_t it,
                             uint32_t phase, uint32_t sys, int32_t *out_idx,
                             int64_t *out_count, void *stream);
+
+/* One residual pass without a solve: ax = A x (m entries) and atz = A^T z
+ * (n entries) -- the two products every iteration forms (the column residual
+ * A^T z and the A x of the row residual, Section 2).  Dense A: one fused read
+ * of the matrix; CSR: one CSR and one CSC pass.  precision RGDBEK_F64 uses
+ * the FP64 storage (double vectors); RGDBEK_F32 the FP32 copy of a MIXED_F32
+ * handle (float vectors).  All four pointers are device pointers.  Enqueued
+ * on the handle's stream; returns without synchronising it (for timing). */
+rgdbek_status rgdbek_apply(rgdbek_handle h, int32_t precision, const void *x,
+                           const void *z, void *ax, void *atz);
 
 /* Release everything the handle owns.  NULL is a no-op. */
 rgdbek_status rgdbek_destroy(rgdbek_handle h);

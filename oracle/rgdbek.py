@@ -17,7 +17,8 @@ with x_0 = 0 and z_0 = b.  Readings where the paper is silent:
 * the garbled "A^J x_k^J" of the row update is A^J x_k (full x_k), as in
   the convergence proof of Theorem 2.3 and the least-squares step of
   Algorithm 2;
-* a zero row or column has weight 0 (never drawn);
+* a zero row or column has weight 0 (never drawn), and so has a weight
+  below floor * max (zero up to rounding, see ``select``);
 * an empty block (every weight zero) skips that projection, and the
   iteration still counts;
 * stopping tests (the paper iterates T times in Algorithm 1 and stops on
@@ -44,7 +45,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from .select import select, block_size
+from .select import select, block_size, FLOOR_FP64
 from .blockls import column_projection, row_projection
 
 
@@ -86,7 +87,8 @@ def row_weights(b, z_next, q, rho):
 
 def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
            stop="none", tol=0.0, x_ref=None, sys=0, key1=0, it0=0,
-           x0=None, z0=None, col_offset=None, record=False):
+           x0=None, z0=None, col_offset=None, record=False,
+           floor=FLOOR_FP64):
     """Run Algorithm 1.  Returns (x, z, Info).
 
     a: dense (m, n) ndarray or scipy sparse matrix; b: (m,) FP64.
@@ -125,7 +127,7 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
         it = it0 + k
         # column phase
         eps_z, g = column_weights(a, z, kappa, col_offset)
-        u = select(eps_z, k_col, seed, it, 0, sys, key1)
+        u = select(eps_z, k_col, seed, it, 0, sys, key1, floor)
         z_prev = z
         if u.size:
             z, y, nr_c = column_projection(a_csc[:, u], z)
@@ -144,7 +146,7 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
             if info.metric <= tol:
                 info.converged = True
                 break
-        j = select(eps_x, k_row, seed, it, 1, sys, key1)
+        j = select(eps_x, k_row, seed, it, 1, sys, key1, floor)
         x_prev = x
         if j.size:
             d, nr_r = row_projection(a[j, :], r[j])

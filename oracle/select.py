@@ -12,8 +12,14 @@ how ties, zero weights or too few nonzero weights are handled.  Readings:
   independent Exp(1) variable, the k indices with the smallest keys
   E_j / eps_j are distributed exactly as successive sampling.  P is never
   normalised: the keys need eps only.
-* Indices with eps_j = 0 have probability zero and are never drawn.  When at
-  most k weights are positive, all of them are taken.
+* Indices with eps_j = 0 have probability zero and are never drawn.  A
+  weight that is zero only up to rounding -- the columns (rows) a projection
+  has just annihilated keep residuals of order u * ||A_(j)|| ||z|| -- is
+  treated as zero too: only eps_j > floor * max_l eps_l counts as positive
+  (floor = 1e-20 for FP64 weights; floor = 0 keeps the exact test
+  eps_j > 0).  Without this, a block larger than the number of genuinely
+  positive weights would be filled from rounding noise.  When at most k
+  weights pass the test, all of them are taken.
 * Equal keys are ordered by index; the result is returned in ascending
   index order.
 * A NaN, negative or infinite weight is a numeric error.
@@ -49,11 +55,15 @@ def exp_keys(idx, eps_idx, seed, it, phase, sys=0, key1=0):
     return e / eps_idx
 
 
-def select(eps, k, seed, it, phase, sys=0, key1=0):
+FLOOR_FP64 = 1e-20
+
+
+def select(eps, k, seed, it, phase, sys=0, key1=0, floor=FLOOR_FP64):
     """Indices (ascending, int64) of the block drawn from weights ``eps``.
 
     eps: 1-D FP64 weights; k: block size; (seed, it, phase, sys, key1): the
-    generator coordinates (phase 0 = column block, 1 = row block)."""
+    generator coordinates (phase 0 = column block, 1 = row block); floor:
+    relative weight floor (see the module docstring)."""
     eps = np.asarray(eps, dtype=np.float64)
     if eps.ndim != 1:
         raise ValueError("eps must be one-dimensional")
@@ -61,7 +71,9 @@ def select(eps, k, seed, it, phase, sys=0, key1=0):
         raise NumericError("selection weights must be finite and >= 0")
     if k < 0:
         raise ValueError("k must be >= 0")
-    cand = np.flatnonzero(eps > 0)
+    mx = eps.max() if eps.size else 0.0
+    cut = floor * mx if floor > 0 else 0.0
+    cand = np.flatnonzero(eps > cut)
     if cand.size <= k:
         return cand.astype(np.int64)
     keys = exp_keys(cand, eps[cand], seed, it, phase, sys, key1)

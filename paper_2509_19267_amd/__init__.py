@@ -1,0 +1,11 @@
+"""RGDBEK (randomized greedy double block extended Kaczmarz, arXiv
+2509.19267) for AMD Instinct MI355X (gfx950).
+
+The solver lives in the HIP library librgdbek.so (C-ABI in
+include/rgdbek.h); this package only marshals arguments to it.
+"""
+from ._binding import RgdbekError, LIB_PATH, load  # noqa: F401
+from .solver import Solver, select, solve, RGDBEKFunction  # noqa: F401
+
+__all__ = ["Solver", "select", "solve", "RGDBEKFunction", "RgdbekError",
+           "LIB_PATH", "load"]

@@ -1,0 +1,247 @@
+// Launchers of the RGDBEK kernels (host-callable, defined in the .hip files).
+// Every launcher enqueues on the given stream and does not synchronise.
+// Kernels of the solve loop read Ctrl::done first (respect_done != 0) so that
+// a captured graph of several iterations turns into no-ops after the stop.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace rg {
+
+// ------------------------------------------------------------ selection
+constexpr int64_t SEL_SMALL_MAX = 65536;  // one workgroup up to this size
+
+struct SelectScratch {
+  uint64_t *keys = nullptr;   // d keys
+  unsigned *hist = nullptr;   // 2048 bins (zeroed at allocation)
+  uint64_t *ckey = nullptr;   // 4096 candidate keys
+  int64_t *cidx = nullptr;    // 4096 candidate indices
+  int32_t *blk = nullptr;     // per-chunk counts
+};
+int64_t select_scratch_blocks(int64_t d);
+
+// eps: d weights (T promoted to FP64 before the key division); weights not
+// above floor * max(eps) count as zero.  ph selects the Ctrl slot (0 columns,
+// 1 rows); the iteration number is Ctrl::it.
+template <typename T>
+void launch_select(const T *eps, int64_t d, int64_t k, double floor,
+                   uint64_t seed, uint64_t key1, uint32_t phase, uint32_t sys,
+                   int ph, SelectScratch &s, int32_t *out, Ctrl *ctrl,
+                   int respect_done, hipStream_t st);
+
+// ------------------------------------------------------------ matrices
+template <typename T>
+struct Csr {                 // CSR (or CSC viewed as CSR of the transpose)
+  int64_t rows = 0, cols = 0, nnz = 0;
+  const int64_t *ptr = nullptr;
+  const int32_t *idx = nullptr;
+  const T *val = nullptr;
+  int group = 8;             // lanes per segment (power of two)
+  const int32_t *longs = nullptr;  // segments longer than the long limit
+  int64_t nlong = 0;
+  int64_t long_limit = 0;
+};
+
+template <typename T>
+struct Dense {               // row-major rows x cols with leading dim ld
+  int64_t rows = 0, cols = 0, ld = 0;
+  const T *a = nullptr;
+};
+
+// Scratch for multi-block reductions: `part` holds per-block partials.
+struct Reduce {
+  double *part = nullptr;    // >= 2 * max blocks
+  int64_t cap = 0;
+};
+
+// ------------------------------------------------------------ residuals
+// Sparse segment dots y_s = sum_e val[e] v[idx[e]] for every segment s (or
+// only the segments listed in `list` (count read from *count_dev)), with an
+// epilogue selected by `epi`:
+enum Epi {
+  EPI_STORE = 0,      // out[s] = y
+  EPI_COLRES = 1,     // g[s] = y (+ off[s]); eps[s] = g^2 / nrm[s]
+  EPI_ROWRES = 2,     // r[s] = b[s] - z[s] - y; eps[s] = r^2 / nrm[s];
+                      // partials of ||b - y||^2 and ||r||^2
+  EPI_LIST_STORE = 3, // out[k] = y for the k-th listed segment
+};
+template <typename T>
+struct SegArgs {
+  const T *v = nullptr;      // vector gathered by idx
+  T *out = nullptr;          // EPI_STORE / EPI_LIST_STORE
+  T *g = nullptr;            // EPI_COLRES output
+  const T *off = nullptr;    // EPI_COLRES offset (nullable)
+  T *eps = nullptr;          // weights output
+  const double *nrm = nullptr;  // squared norms (FP64)
+  const T *b = nullptr, *z = nullptr;  // EPI_ROWRES inputs
+  T *r = nullptr;            // EPI_ROWRES output
+  double *part = nullptr;    // EPI_ROWRES partials (2 per block)
+  const int32_t *list = nullptr;  // listed segments
+  const int64_t *count_dev = nullptr;
+  int64_t list_cap = 0;
+};
+template <typename T>
+int launch_segdot(const Csr<T> &A, int epi, const SegArgs<T> &a, Ctrl *ctrl,
+                  int respect_done, hipStream_t st);   // returns #partials
+
+// Dense fused pass: q = A x and g = A^T z from one read of A; then the
+// finalise step forms g (+ off), eps^z = g^2/kappa, and q.
+template <typename T>
+struct DenseWork {
+  T *qpart = nullptr;        // nch * rows
+  T *gpart = nullptr;        // nrb * ld
+  int nch = 0, nrb = 0;
+};
+template <typename T>
+void dense_work_shape(const Dense<T> &A, int *nch, int *nrb);
+template <typename T>
+void launch_dense_fused(const Dense<T> &A, const T *x, const T *z,
+                        DenseWork<T> &w, const T *off, const double *kappa,
+                        T *g, T *eps, T *q, Ctrl *ctrl, int respect_done,
+                        hipStream_t st);
+// r = b - z - q, eps^x = r^2/rho, partials of ||b-q||^2, ||r||^2
+template <typename T>
+int launch_rowres_dense(int64_t m, const T *b, const T *z, const T *q,
+                        const double *rho, T *r, T *eps, double *part,
+                        Ctrl *ctrl, int respect_done, hipStream_t st);
+
+// Stop tests.  ERR_REF at the top of an iteration (x vs x_ref); RSE/RES_EXT
+// from the row-residual partials.  Sets Ctrl::done/converged/metric.
+template <typename T>
+void launch_err_ref(int64_t n, const T *x, const double *x_ref,
+                    const double *x_base, Reduce &red, Ctrl *ctrl,
+                    int respect_done, hipStream_t st);
+// Ctrl::ref2 = sum v_i^2 (FP64), one workgroup.
+template <typename T>
+void launch_set_ref2(int64_t n, const T *v, Ctrl *ctrl, hipStream_t st);
+void launch_stop_rowres(const double *part, int nparts, Ctrl *ctrl,
+                        hipStream_t st);
+void launch_end_iter(Ctrl *ctrl, hipStream_t st);
+
+// ------------------------------------------------------------ projections
+// Dense Gram of listed rows of X (row-major, ld): G[a][b] = <X_la, X_lb>,
+// for a, b < count (read from *count_dev, at most cap).
+template <typename T>
+void launch_gram_rows(const T *X, int64_t ld, int64_t len, const int32_t *list,
+                      const int64_t *count_dev, int64_t cap, T *G,
+                      Ctrl *ctrl, int respect_done, hipStream_t st);
+// Gather G[a][b] = F[l_a * ldf + l_b] from a precomputed Gram F.
+template <typename T>
+void launch_gram_gather(const T *F, int64_t ldf, const int32_t *list,
+                        const int64_t *count_dev, int64_t cap, T *G,
+                        Ctrl *ctrl, int respect_done, hipStream_t st);
+// Full Gram of all rows of X into F (ld = rows): used once at create.
+template <typename T>
+void launch_gram_full(const T *X, int64_t ldx, int64_t rows, int64_t len,
+                      T *F, hipStream_t st);
+
+// Cholesky factor of G (cap x cap storage, count from *count_dev) in place
+// and solve G y = h (h gathered through hlist from hsrc, or given).  One
+// workgroup; for counts up to CHOL_MAX.
+constexpr int64_t CHOL_MAX = 512;
+template <typename T>
+void launch_chol_solve(T *G, int64_t cap, const int64_t *count_dev,
+                       const T *hsrc, const int32_t *hlist, T *y, int factor,
+                       Ctrl *ctrl, int ph, int respect_done, hipStream_t st);
+
+// Preconditioned CG on the gathered Gram G y = h (Jacobi).  init + steps.
+template <typename T>
+struct CgWork {
+  T *res = nullptr, *p = nullptr, *v = nullptr, *zz = nullptr;
+  double *part = nullptr;    // per-block partials
+};
+template <typename T>
+void launch_pcg_gram_init(const T *G, int64_t cap, const int64_t *count_dev,
+                          const T *hsrc, const int32_t *hlist, T *y,
+                          CgWork<T> &w, Ctrl *ctrl, int ph, int respect_done,
+                          hipStream_t st);
+template <typename T>
+void launch_pcg_gram_step(const T *G, int64_t cap, const int64_t *count_dev,
+                          T *y, CgWork<T> &w, double tol, Ctrl *ctrl, int ph,
+                          int respect_done, hipStream_t st);
+
+// Dense thin updates.
+// z[i] -= sum_a y_a * Acm[list_a * ldc + i]   (columns of A, column-major)
+// scratch: thin_update_scratch(len, cap) entries of T.
+template <typename T>
+void launch_col_update(const T *Acm, int64_t ldc, int64_t m,
+                       const int32_t *list, const int64_t *count_dev,
+                       int64_t cap, const T *y, T *z, T *scratch, Ctrl *ctrl,
+                       int respect_done, hipStream_t st);
+// x[j] += sum_a w_a * Arm[list_a * ld + j]     (rows of A, row-major)
+template <typename T>
+void launch_row_update(const T *Arm, int64_t ld, int64_t n,
+                       const int32_t *list, const int64_t *count_dev,
+                       int64_t cap, const T *w, T *x, T *scratch, Ctrl *ctrl,
+                       int respect_done, hipStream_t st);
+int64_t thin_update_scratch(int64_t len, int64_t cap);
+// s_a = h_{l_a} - <A_{l_a}, v>, listed rows of a row-major matrix against v
+// (residual of projected equations, used for one refinement sweep).
+// s_a = h1[l_a] - h2[l_a] - <A_{l_a}, v>   (h2 nullable)
+template <typename T>
+void launch_list_resid(const T *Arm, int64_t ld, int64_t len,
+                       const int32_t *list, const int64_t *count_dev,
+                       int64_t cap, const T *h1, const T *h2, const T *v,
+                       T *s, Ctrl *ctrl, int respect_done, hipStream_t st);
+
+// Sparse block projections (matrix-free CG).  See proj.hip.
+template <typename T>
+struct SparseCg {
+  T *phat = nullptr;    // wide masked direction (n for columns, m for rows)
+  T *wide = nullptr;    // wide product (m for columns, n for rows)
+  T *p = nullptr, *res = nullptr, *v = nullptr;  // narrow (cap)
+  double *part = nullptr;
+};
+template <typename T>
+void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
+                           const int32_t *U, const int64_t *count_dev,
+                           int64_t cap, const T *g, T *z, SparseCg<T> &w,
+                           int max_steps, double tol, Ctrl *ctrl,
+                           int respect_done, hipStream_t st);
+template <typename T>
+void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
+                           const int32_t *J, const int64_t *count_dev,
+                           int64_t cap, const T *r, const double *rho, T *x,
+                           SparseCg<T> &w, int max_steps, double tol,
+                           Ctrl *ctrl, int respect_done, hipStream_t st);
+
+// ------------------------------------------------------------ utilities
+template <typename Tout, typename Tin>
+void launch_convert(const Tin *in, Tout *out, int64_t n, hipStream_t st);
+// copy rows x cols row-major (ld_in) into padded row-major (ld_out) and its
+// column-major transpose (ld_t); pads are zero.
+template <typename Tout, typename Tin>
+void launch_pack_dense(const Tin *in, int64_t rows, int64_t cols,
+                       int64_t ld_in, Tout *out_rm, int64_t ld_out,
+                       Tout *out_cm, int64_t ld_t, hipStream_t st);
+template <typename T>
+void launch_sqnorms_dense(const T *Arm, int64_t rows, int64_t cols,
+                          int64_t ld, const T *Acm, int64_t ldc,
+                          double *rho, double *kappa, hipStream_t st);
+template <typename T>
+void launch_sqnorms_csr(const Csr<T> &A, double *out, hipStream_t st);
+// flag[0] |= any non-finite among n values
+template <typename T>
+void launch_check_finite(const T *v, int64_t n, int *flag, hipStream_t st);
+// CSR -> CSC transpose on the device (stable: rows ascending in a column)
+template <typename T>
+void launch_csr_to_csc(int64_t m, int64_t n, int64_t nnz, const int64_t *rp,
+                       const int32_t *ci, const T *v, int64_t *cp, int32_t *ri,
+                       T *cv, int64_t *work, hipStream_t st);
+// pattern gradient: dA[e] = r_i lam_j - w_i x_j over stored entries
+void launch_grad_pattern_csr(int64_t m, const int64_t *rp, const int32_t *ci,
+                             const double *r, const double *lam,
+                             const double *w, const double *x, double *dA,
+                             hipStream_t st);
+void launch_grad_pattern_dense(int64_t m, int64_t n, const double *r,
+                               const double *lam, const double *w,
+                               const double *x, double *dA, hipStream_t st);
+// y = alpha*y + beta*x (elementwise, FP types mixed through double)
+template <typename Ty, typename Tx>
+void launch_axpby(int64_t n, double alpha, Ty *y, double beta, const Tx *x,
+                  hipStream_t st);
+void launch_fill_ctrl_it(Ctrl *ctrl, int64_t it, hipStream_t st);
+
+}  // namespace rg

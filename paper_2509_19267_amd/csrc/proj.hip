@@ -1,0 +1,830 @@
+// Block projections of RGDBEK on gfx950 (the pseudoinverse updates of the
+// GDBEK rule that Algorithm 1 reuses):
+//   column block: y = argmin ||A_U y - z||,  z <- z - A_U y
+//   row block:    d = (A^J)^+ r^J,           x <- x + d
+// The column right-hand side A_U^T z is g restricted to U, already produced
+// by the column residual pass.  For the row block with independent rows,
+// d = A^J^T w with (A^J A^J^T) w = r^J.
+//
+// Dense blocks: Gram matrix (gathered from a precomputed A^T A / A A^T, or
+// formed from the listed rows), then a one-workgroup blocked Cholesky with an
+// optional corrected semi-normal-equations sweep (ill-conditioned square row
+// blocks), or Jacobi-preconditioned CG with one launch per step (the last
+// workgroup of each step carries the vector recurrences).
+// Sparse blocks: matrix-free CGLS (columns, z updated as the CGLS residual)
+// and CGNE on A^J A^J^T (rows), the wide products streaming the full CSR/CSC
+// with a direction vector that is zero outside the block.
+#include "common.h"
+#include "kernels.h"
+
+namespace rg {
+
+// ------------------------------------------------------------ Gram
+template <typename T>
+__global__ void __launch_bounds__(256)
+gram_gather_kernel(const T *__restrict__ F, int64_t ldf,
+                   const int32_t *__restrict__ list,
+                   const int64_t *__restrict__ cnt, int64_t cap,
+                   T *__restrict__ G, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t c = *cnt;
+  const int64_t a = blockIdx.y;
+  if (a >= c) return;
+  const int64_t la = list[a];
+  for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b < c;
+       b += (int64_t)gridDim.x * 256)
+    G[a * cap + b] = F[la * ldf + list[b]];
+}
+template <typename T>
+void launch_gram_gather(const T *F, int64_t ldf, const int32_t *list,
+                        const int64_t *count_dev, int64_t cap, T *G,
+                        Ctrl *ctrl, int respect_done, hipStream_t st) {
+  int gx = (int)((cap + 255) / 256);
+  if (gx > 8) gx = 8;
+  hipLaunchKernelGGL(gram_gather_kernel<T>, dim3(gx, (unsigned)cap), dim3(256),
+                     0, st, F, ldf, list, count_dev, cap, G, ctrl,
+                     respect_done);
+}
+
+// G[a][b] = <X_{l_a}, X_{l_b}> (list == nullptr: identity), 32x32 output
+// tiles, 16x16 threads with 2x2 outputs each, K staged through LDS.
+constexpr int GT = 32, GK = 32;
+template <typename T>
+__global__ void __launch_bounds__(256)
+gram_rows_kernel(const T *__restrict__ X, int64_t ld, int64_t len,
+                 const int32_t *__restrict__ list,
+                 const int64_t *__restrict__ cnt, int64_t cap, int64_t ldg,
+                 T *__restrict__ G, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t c = cnt ? *cnt : cap;
+  const int64_t ta = (int64_t)blockIdx.y * GT, tb = (int64_t)blockIdx.x * GT;
+  if (ta >= c || tb >= c || tb > ta) return;   // lower tiles only
+  __shared__ T sa[GT][GK + 1], sb[GT][GK + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  T acc[2][2] = {{0, 0}, {0, 0}};
+  for (int64_t k0 = 0; k0 < len; k0 += GK) {
+    for (int e = threadIdx.x; e < GT * GK; e += 256) {
+      const int rr = e / GK, kk = e % GK;
+      const int64_t ra = ta + rr, rb = tb + rr, k = k0 + kk;
+      T va = 0, vb = 0;
+      if (ra < c && k < len) va = X[(list ? (int64_t)list[ra] : ra) * ld + k];
+      if (rb < c && k < len) vb = X[(list ? (int64_t)list[rb] : rb) * ld + k];
+      sa[rr][kk] = va;
+      sb[rr][kk] = vb;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < GK; ++kk) {
+      const T a0 = sa[ty][kk], a1 = sa[ty + 16][kk];
+      const T b0 = sb[tx][kk], b1 = sb[tx + 16][kk];
+      acc[0][0] += a0 * b0; acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0; acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t ra = ta + ty + 16 * i, rb = tb + tx + 16 * j;
+      if (ra < c && rb < c) {
+        G[ra * ldg + rb] = acc[i][j];
+        G[rb * ldg + ra] = acc[i][j];
+      }
+    }
+}
+template <typename T>
+void launch_gram_rows(const T *X, int64_t ld, int64_t len, const int32_t *list,
+                      const int64_t *count_dev, int64_t cap, T *G, Ctrl *ctrl,
+                      int respect_done, hipStream_t st) {
+  const unsigned nt = (unsigned)((cap + GT - 1) / GT);
+  hipLaunchKernelGGL(gram_rows_kernel<T>, dim3(nt, nt), dim3(256), 0, st, X,
+                     ld, len, list, count_dev, cap, cap, G, ctrl,
+                     respect_done);
+}
+template <typename T>
+void launch_gram_full(const T *X, int64_t ldx, int64_t rows, int64_t len,
+                      T *F, hipStream_t st) {
+  const unsigned nt = (unsigned)((rows + GT - 1) / GT);
+  hipLaunchKernelGGL(gram_rows_kernel<T>, dim3(nt, nt), dim3(256), 0, st, X,
+                     ldx, len, (const int32_t *)nullptr,
+                     (const int64_t *)nullptr, rows, rows, F, (Ctrl *)nullptr,
+                     0);
+}
+
+// ------------------------------------------------------------ Cholesky
+// One workgroup of 256 threads, blocked left-looking with 32-column panels
+// in LDS.  A pivot below 1e-13 of the largest diagonal marks the column as
+// dependent (its unknown is set to zero), which keeps the projection onto the
+// span of the block exact for rank-deficient blocks.
+constexpr int CNB = 32;
+constexpr int CNT = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(CNT)
+chol_solve_kernel(T *__restrict__ G, int64_t ldg,
+                  const int64_t *__restrict__ cnt,
+                  const T *__restrict__ hsrc, const int32_t *__restrict__ hl,
+                  T *__restrict__ y, int factor, Ctrl *ctrl, int ph,
+                  int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int c = (int)*cnt;
+  if (c <= 0) return;
+  __shared__ T P[CHOL_MAX][CNB + 1];
+  __shared__ T Lb[CNB][CNB + 1];
+  __shared__ T vec[CHOL_MAX];
+  __shared__ T dmax;
+  const int tid = threadIdx.x;
+  if (factor) {
+    if (tid == 0) {
+      T mx = 0;
+      for (int i = 0; i < c; ++i) mx = G[(int64_t)i * ldg + i] > mx ? G[(int64_t)i * ldg + i] : mx;
+      dmax = mx;
+    }
+    __syncthreads();
+    const T thr = dmax * (T)1e-13;
+    for (int p = 0; p < c; p += CNB) {
+      const int w = (c - p) < CNB ? (c - p) : CNB;
+      const int h = c - p;
+      // load panel rows p..c-1, columns p..p+w-1
+      for (int e = tid; e < h * CNB; e += CNT) {
+        const int r = e / CNB, cc = e % CNB;
+        P[r][cc] = (cc < w) ? G[(int64_t)(p + r) * ldg + p + cc] : (T)0;
+      }
+      __syncthreads();
+      // left-looking update with previous panels: P -= L[p:, 0:p] L[p:p+w, 0:p]^T
+      for (int t0 = 0; t0 < p; t0 += CNB) {
+        for (int e = tid; e < CNB * CNB; e += CNT) {
+          const int rr = e / CNB, kk = e % CNB;
+          Lb[rr][kk] = (rr < w) ? G[(int64_t)(p + rr) * ldg + t0 + kk] : (T)0;
+        }
+        __syncthreads();
+        for (int r = tid; r < h; r += CNT) {
+          T lr[CNB];
+#pragma unroll
+          for (int kk = 0; kk < CNB; ++kk) lr[kk] = G[(int64_t)(p + r) * ldg + t0 + kk];
+          for (int cc = 0; cc < w && cc <= r; ++cc) {
+            T s = 0;
+#pragma unroll
+            for (int kk = 0; kk < CNB; ++kk) s += lr[kk] * Lb[cc][kk];
+            P[r][cc] -= s;
+          }
+        }
+        __syncthreads();
+      }
+      // factor the panel (right-looking inside LDS)
+      for (int j = 0; j < w; ++j) {
+        __syncthreads();
+        const T dj = P[j][j];
+        const bool dep = !(dj > thr);
+        const T sq = dep ? (T)0 : sqrt(dj);
+        __syncthreads();   // every wave has read the pivot before it changes
+        for (int r = j + tid; r < h; r += CNT) {
+          if (r == j) P[j][j] = sq;
+          else P[r][j] = dep ? (T)0 : P[r][j] / sq;
+        }
+        __syncthreads();
+        for (int r = j + 1 + tid; r < h; r += CNT) {
+          const T lrj = P[r][j];
+          const int kmax = r < w - 1 ? r : w - 1;
+          for (int k = j + 1; k <= kmax; ++k) P[r][k] -= lrj * P[k][j];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < h * CNB; e += CNT) {
+        const int r = e / CNB, cc = e % CNB;
+        if (cc < w && cc <= r) G[(int64_t)(p + r) * ldg + p + cc] = P[r][cc];
+      }
+      __syncthreads();
+    }
+  }
+  // forward solve L v = h
+  for (int i = tid; i < c; i += CNT) vec[i] = hl ? hsrc[hl[i]] : hsrc[i];
+  __syncthreads();
+  for (int p = 0; p < c; p += CNB) {
+    const int w = (c - p) < CNB ? (c - p) : CNB;
+    // subtract contributions of solved entries 0..p-1 from rows p..p+w-1
+    if (tid < w) {
+      T s = 0;
+      for (int t = 0; t < p; ++t) s += G[(int64_t)(p + tid) * ldg + t] * vec[t];
+      vec[p + tid] -= s;
+    }
+    __syncthreads();
+    if (tid < WAVE) {
+      for (int j = 0; j < w; ++j) {
+        const T d = G[(int64_t)(p + j) * ldg + p + j];
+        T vj = vec[p + j];
+        vj = d != (T)0 ? vj / d : (T)0;
+        if (tid == 0) vec[p + j] = vj;
+        __builtin_amdgcn_wave_barrier();
+        if (tid > j && tid < w) vec[p + tid] -= G[(int64_t)(p + tid) * ldg + p + j] * vj;
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+  }
+  // backward solve L^T y = v
+  for (int p = ((c - 1) / CNB) * CNB; p >= 0; p -= CNB) {
+    const int w = (c - p) < CNB ? (c - p) : CNB;
+    if (tid < w) {
+      T s = 0;
+      for (int t = p + w; t < c; ++t) s += G[(int64_t)t * ldg + p + tid] * vec[t];
+      vec[p + tid] -= s;
+    }
+    __syncthreads();
+    if (tid < WAVE) {
+      for (int j = w - 1; j >= 0; --j) {
+        const T d = G[(int64_t)(p + j) * ldg + p + j];
+        T vj = vec[p + j];
+        vj = d != (T)0 ? vj / d : (T)0;
+        if (tid == 0) vec[p + j] = vj;
+        __builtin_amdgcn_wave_barrier();
+        if (tid < j) vec[p + tid] -= G[(int64_t)(p + j) * ldg + p + tid] * vj;
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < c; i += CNT) y[i] = vec[i];
+}
+
+template <typename T>
+void launch_chol_solve(T *G, int64_t cap, const int64_t *count_dev,
+                       const T *hsrc, const int32_t *hlist, T *y, int factor,
+                       Ctrl *ctrl, int ph, int respect_done, hipStream_t st) {
+  hipLaunchKernelGGL(chol_solve_kernel<T>, dim3(1), dim3(CNT), 0, st, G, cap,
+                     count_dev, hsrc, hlist, y, factor, ctrl, ph,
+                     respect_done);
+}
+
+// ------------------------------------------------------------ PCG on Gram
+constexpr int PG_NT = 256;
+template <typename T>
+__global__ void __launch_bounds__(PG_NT)
+pcg_init_kernel(const T *__restrict__ G, int64_t ldg,
+                const int64_t *__restrict__ cnt, const T *__restrict__ hsrc,
+                const int32_t *__restrict__ hl, T *__restrict__ y,
+                CgWork<T> w, Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[PG_NT / WAVE];
+  const int64_t c = *cnt;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t a = threadIdx.x; a < c; a += PG_NT) {
+    const T h = hl ? hsrc[hl[a]] : hsrc[a];
+    const T dg = G[a * ldg + a];
+    const T zz = dg > (T)0 ? h / dg : (T)0;
+    y[a] = (T)0;
+    w.res[a] = h;
+    w.zz[a] = zz;
+    w.p[a] = zz;
+    rz += (double)h * (double)zz;
+    rr += (double)h * (double)h;
+  }
+  rz = block_sum<PG_NT>(rz, sh);
+  rr = block_sum<PG_NT>(rr, sh);
+  if (threadIdx.x == 0) {
+    ctrl->cg_rz[ph] = rz;
+    ctrl->cg_rz0[ph] = rr;
+    ctrl->cg_done[ph] = (rr == 0.0 || c == 0) ? 1 : 0;
+    ctrl->cg_steps[ph] = 0;
+  }
+}
+
+// v = G p (one wave per row), then the last workgroup finishes the step.
+template <typename T>
+__global__ void __launch_bounds__(PG_NT)
+pcg_step_kernel(const T *__restrict__ G, int64_t ldg,
+                const int64_t *__restrict__ cnt, T *__restrict__ y,
+                CgWork<T> w, double tol, Ctrl *ctrl, int ph,
+                int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[ph])) return;
+  __shared__ double sh[PG_NT / WAVE];
+  const int64_t c = *cnt;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t row = (int64_t)blockIdx.x * (PG_NT / WAVE) + threadIdx.x / WAVE;
+  double pv = 0.0;
+  if (row < c) {
+    T s = 0;
+    const T *gr = G + row * ldg;
+    for (int64_t b = lane; b < c; b += WAVE) s += gr[b] * w.p[b];
+    s = wave_sum(s);
+    if (lane == 0) {
+      w.v[row] = s;
+      pv = (double)s * (double)w.p[row];
+    }
+  }
+  pv = block_sum<PG_NT>(pv, sh);
+  if (threadIdx.x == 0) st_agent(&w.part[blockIdx.x], pv);
+  if (!last_block(&ctrl->ticket[1 + ph])) return;
+  double tot = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += PG_NT) tot += ld_agent(&w.part[b]);
+  tot = block_sum<PG_NT>(tot, sh);
+  const double rz = ctrl->cg_rz[ph];
+  const double alpha = tot != 0.0 ? rz / tot : 0.0;
+  double rz1 = 0.0, rr = 0.0;
+  for (int64_t a = threadIdx.x; a < c; a += PG_NT) {
+    const T v = ld_agent(&w.v[a]);
+    y[a] += (T)alpha * w.p[a];
+    const T r = w.res[a] - (T)alpha * v;
+    w.res[a] = r;
+    const T dg = G[a * ldg + a];
+    const T zz = dg > (T)0 ? r / dg : (T)0;
+    w.zz[a] = zz;
+    rz1 += (double)r * (double)zz;
+    rr += (double)r * (double)r;
+  }
+  rz1 = block_sum<PG_NT>(rz1, sh);
+  rr = block_sum<PG_NT>(rr, sh);
+  const double beta = rz != 0.0 ? rz1 / rz : 0.0;
+  for (int64_t a = threadIdx.x; a < c; a += PG_NT) w.p[a] = w.zz[a] + (T)beta * w.p[a];
+  if (threadIdx.x == 0) {
+    ctrl->cg_rz[ph] = rz1;
+    ctrl->cg_steps[ph] += 1;
+    if (rr <= tol * tol * ctrl->cg_rz0[ph] || tot == 0.0) ctrl->cg_done[ph] = 1;
+  }
+}
+
+template <typename T>
+void launch_pcg_gram_init(const T *G, int64_t cap, const int64_t *count_dev,
+                          const T *hsrc, const int32_t *hlist, T *y,
+                          CgWork<T> &w, Ctrl *ctrl, int ph, int respect_done,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(pcg_init_kernel<T>, dim3(1), dim3(PG_NT), 0, st, G, cap,
+                     count_dev, hsrc, hlist, y, w, ctrl, ph, respect_done);
+}
+template <typename T>
+void launch_pcg_gram_step(const T *G, int64_t cap, const int64_t *count_dev,
+                          T *y, CgWork<T> &w, double tol, Ctrl *ctrl, int ph,
+                          int respect_done, hipStream_t st) {
+  const unsigned nb = (unsigned)((cap + (PG_NT / WAVE) - 1) / (PG_NT / WAVE));
+  hipLaunchKernelGGL(pcg_step_kernel<T>, dim3(nb), dim3(PG_NT), 0, st, G, cap,
+                     count_dev, y, w, tol, ctrl, ph, respect_done);
+}
+
+// ------------------------------------------------------------ thin updates
+// out[i] (+)= sign * sum_a coef_a * M[list_a * ldm + i] over a chunk of the
+// list per blockIdx.y, partials combined in fixed order by upd_finish.
+constexpr int UP_NT = 256;
+constexpr int UP_CHUNK = 128;
+template <typename T>
+__global__ void __launch_bounds__(UP_NT)
+upd_partial(const T *__restrict__ M, int64_t ldm, int64_t len,
+            const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
+            const T *__restrict__ coef, T *__restrict__ part, Ctrl *ctrl,
+            int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t c = *cnt;
+  const int64_t i = (int64_t)blockIdx.x * UP_NT + threadIdx.x;
+  const int64_t a0 = (int64_t)blockIdx.y * UP_CHUNK;
+  int64_t a1 = a0 + UP_CHUNK;
+  if (a1 > c) a1 = c;
+  if (i >= len) return;
+  T s = 0;
+  for (int64_t a = a0; a < a1; ++a) s += coef[a] * M[(int64_t)list[a] * ldm + i];
+  part[(int64_t)blockIdx.y * len + i] = s;
+}
+template <typename T>
+__global__ void __launch_bounds__(UP_NT)
+upd_finish(int64_t len, const int64_t *__restrict__ cnt, int nsplit,
+           const T *__restrict__ part, T sign, T *__restrict__ out,
+           Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t i = (int64_t)blockIdx.x * UP_NT + threadIdx.x;
+  if (i >= len) return;
+  const int64_t c = *cnt;
+  const int ns = (int)((c + UP_CHUNK - 1) / UP_CHUNK);
+  T s = 0;
+  for (int b = 0; b < ns && b < nsplit; ++b) s += part[(int64_t)b * len + i];
+  out[i] += sign * s;
+}
+
+template <typename T>
+static void thin_update(const T *M, int64_t ldm, int64_t len,
+                        const int32_t *list, const int64_t *cnt, int64_t cap,
+                        const T *coef, T *out, T sign, T *part, Ctrl *ctrl,
+                        int respect_done, hipStream_t st) {
+  const unsigned gx = (unsigned)((len + UP_NT - 1) / UP_NT);
+  const unsigned gy = (unsigned)((cap + UP_CHUNK - 1) / UP_CHUNK);
+  hipLaunchKernelGGL(upd_partial<T>, dim3(gx, gy), dim3(UP_NT), 0, st, M, ldm,
+                     len, list, cnt, coef, part, ctrl, respect_done);
+  hipLaunchKernelGGL(upd_finish<T>, dim3(gx), dim3(UP_NT), 0, st, len, cnt,
+                     (int)gy, part, sign, out, ctrl, respect_done);
+}
+
+template <typename T>
+void launch_col_update(const T *Acm, int64_t ldc, int64_t m,
+                       const int32_t *list, const int64_t *count_dev,
+                       int64_t cap, const T *y, T *z, T *scratch, Ctrl *ctrl,
+                       int respect_done, hipStream_t st) {
+  thin_update<T>(Acm, ldc, m, list, count_dev, cap, y, z, (T)-1, scratch,
+                 ctrl, respect_done, st);
+}
+template <typename T>
+void launch_row_update(const T *Arm, int64_t ld, int64_t n,
+                       const int32_t *list, const int64_t *count_dev,
+                       int64_t cap, const T *w, T *x, T *scratch, Ctrl *ctrl,
+                       int respect_done, hipStream_t st) {
+  thin_update<T>(Arm, ld, n, list, count_dev, cap, w, x, (T)1, scratch, ctrl,
+                 respect_done, st);
+}
+int64_t thin_update_scratch(int64_t len, int64_t cap) {
+  return len * ((cap + UP_CHUNK - 1) / UP_CHUNK);
+}
+
+// s_a = h1[l_a] - h2[l_a] - <A_{l_a}, v>  (one wave per listed row)
+template <typename T>
+__global__ void __launch_bounds__(256)
+list_resid_kernel(const T *__restrict__ A, int64_t ld, int64_t len,
+                  const int32_t *__restrict__ list,
+                  const int64_t *__restrict__ cnt, const T *__restrict__ h1,
+                  const T *__restrict__ h2, const T *__restrict__ v,
+                  T *__restrict__ s, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t a = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+  if (a >= *cnt) return;
+  const int64_t l = list[a];
+  T acc = 0;
+  for (int64_t t = lane; t < len; t += WAVE) acc += A[l * ld + t] * v[t];
+  acc = wave_sum(acc);
+  if (lane == 0) s[a] = h1[l] - (h2 ? h2[l] : (T)0) - acc;
+}
+template <typename T>
+void launch_list_resid(const T *Arm, int64_t ld, int64_t len,
+                       const int32_t *list, const int64_t *count_dev,
+                       int64_t cap, const T *h1, const T *h2, const T *v,
+                       T *s, Ctrl *ctrl, int respect_done, hipStream_t st) {
+  hipLaunchKernelGGL(list_resid_kernel<T>, dim3((unsigned)((cap + 3) / 4)),
+                     dim3(256), 0, st, Arm, ld, len, list, count_dev, h1, h2,
+                     v, s, ctrl, respect_done);
+}
+
+// ------------------------------------------------------------ sparse CG
+// Column block, CGLS with z as the running residual:
+//   s = A_U^T z (= g_U), p = s, gam = ||s||^2
+//   step: q = A phat (phat = p on U, zero elsewhere)   [wide, CSR rows]
+//         alpha = gam / ||q||^2                         [last block]
+//         z -= alpha q ; s -= alpha A_U^T q             [narrow + elementwise]
+//         gam' = ||s||^2, p = s + (gam'/gam) p          [last block]
+// Row block, CG on A^J A^J^T w = r^J with Jacobi rho_J, d accumulated:
+//   step: u = A^T phat (phat = p on J)                  [wide, CSC columns]
+//         x += alpha_prev u_prev (fused before u is overwritten)
+//         v = A^J u, alpha = rz / <p, v>                [narrow, last block]
+//         res -= alpha v, zz = res/rho, beta, p = zz + beta p
+constexpr int SC_NT = 256;
+
+template <typename T, int G>
+__global__ void __launch_bounds__(SC_NT)
+sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
+            double *__restrict__ part, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[0])) return;
+  __shared__ double sh[SC_NT / WAVE];
+  constexpr int SPB = SC_NT / G;
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t s = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  T acc = 0;
+  if (s < A.rows) {
+    const int64_t e0 = A.ptr[s], e1 = A.ptr[s + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * phat[A.idx[e]];
+  }
+  acc = group_sum<G>(acc);
+  double qq = 0.0;
+  if (s < A.rows && lg == 0) {
+    q[s] = acc;
+    qq = (double)acc * (double)acc;
+  }
+  qq = block_sum<SC_NT>(qq, sh);
+  if (threadIdx.x == 0) st_agent(&part[blockIdx.x], qq);
+  if (!last_block(&ctrl->ticket[3])) return;
+  double tot = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += SC_NT) tot += ld_agent(&part[b]);
+  tot = block_sum<SC_NT>(tot, sh);
+  if (threadIdx.x == 0) {
+    const double gam = ctrl->cg_rz[0];
+    ctrl->cg_alpha[0] = tot > 0.0 ? gam / tot : 0.0;
+    if (tot == 0.0) ctrl->cg_done[0] = 1;
+  }
+}
+
+// narrow: w_a = <A_(U_a), q> over listed CSC columns; s -= alpha w;
+// and z -= alpha q over a slice of rows; last block: gam', beta, p, phat.
+template <typename T, int G>
+__global__ void __launch_bounds__(SC_NT)
+sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
+              const int64_t *__restrict__ cnt, const T *__restrict__ q,
+              T *__restrict__ z, int64_t m, T *__restrict__ sres,
+              T *__restrict__ p, T *__restrict__ phat,
+              double *__restrict__ part, double tol, Ctrl *ctrl,
+              int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[0])) return;
+  __shared__ double sh[SC_NT / WAVE];
+  const double alpha = ctrl->cg_alpha[0];
+  const int64_t c = *cnt;
+  // elementwise part: z -= alpha q on this block's slice of rows
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  for (int64_t i = i0 + threadIdx.x; i < i0 + per && i < m; i += SC_NT)
+    z[i] -= (T)alpha * q[i];
+  // narrow part
+  constexpr int SPB = SC_NT / G;
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t a = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  T acc = 0;
+  if (a < c) {
+    const int64_t col = U[a];
+    const int64_t e0 = At.ptr[col], e1 = At.ptr[col + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * q[At.idx[e]];
+  }
+  acc = group_sum<G>(acc);
+  double ss = 0.0;
+  if (a < c && lg == 0) {
+    const T sv = sres[a] - (T)alpha * acc;
+    sres[a] = sv;
+    ss = (double)sv * (double)sv;
+  }
+  ss = block_sum<SC_NT>(ss, sh);
+  if (threadIdx.x == 0) st_agent(&part[blockIdx.x], ss);
+  if (!last_block(&ctrl->ticket[4])) return;
+  double tot = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += SC_NT) tot += ld_agent(&part[b]);
+  tot = block_sum<SC_NT>(tot, sh);
+  const double gam = ctrl->cg_rz[0];
+  const double beta = gam > 0.0 ? tot / gam : 0.0;
+  for (int64_t k = threadIdx.x; k < c; k += SC_NT) {
+    const T pv = ld_agent(&sres[k]) + (T)beta * p[k];
+    p[k] = pv;
+    phat[U[k]] = pv;
+  }
+  if (threadIdx.x == 0) {
+    ctrl->cg_rz[0] = tot;
+    ctrl->cg_steps[0] += 1;
+    if (tot <= tol * tol * ctrl->cg_rz0[0]) ctrl->cg_done[0] = 1;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SC_NT)
+sc_init(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
+        const T *__restrict__ rhs_src, const double *__restrict__ jac,
+        T *__restrict__ sres, T *__restrict__ zz_or_null, T *__restrict__ p,
+        T *__restrict__ phat, Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[SC_NT / WAVE];
+  const int64_t c = *cnt;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t a = threadIdx.x; a < c; a += SC_NT) {
+    const int64_t l = list[a];
+    const T h = rhs_src[l];
+    sres[a] = h;
+    T zz = h;
+    if (jac) {
+      const double dj = jac[l];
+      zz = dj > 0.0 ? (T)((double)h / dj) : (T)0;
+      zz_or_null[a] = zz;
+    }
+    p[a] = zz;
+    phat[l] = zz;
+    rz += (double)h * (double)zz;
+    rr += (double)h * (double)h;
+  }
+  rz = block_sum<SC_NT>(rz, sh);
+  rr = block_sum<SC_NT>(rr, sh);
+  if (threadIdx.x == 0) {
+    ctrl->cg_rz[ph] = rz;
+    ctrl->cg_rz0[ph] = rr;
+    ctrl->cg_alpha[ph] = 0.0;
+    ctrl->cg_done[ph] = (rr == 0.0 || c == 0) ? 1 : 0;
+    ctrl->cg_steps[ph] = 0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SC_NT)
+sc_clear(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
+         int64_t cap, T *__restrict__ phat, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t c = *cnt;
+  for (int64_t a = (int64_t)blockIdx.x * SC_NT + threadIdx.x; a < c;
+       a += (int64_t)gridDim.x * SC_NT)
+    phat[list[a]] = (T)0;
+}
+
+// rows: wide product u = A^T phat over CSC columns, with the pending update
+// x += alpha_prev * u_prev applied first (same column, same thread).
+template <typename T, int G>
+__global__ void __launch_bounds__(SC_NT)
+sc_wide_row(Csr<T> At, const T *__restrict__ phat, T *__restrict__ u,
+            T *__restrict__ x, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[1])) return;
+  const double alpha = ctrl->cg_alpha[1];
+  constexpr int SPB = SC_NT / G;
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t s = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  T acc = 0;
+  if (s < At.rows) {
+    const int64_t e0 = At.ptr[s], e1 = At.ptr[s + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * phat[At.idx[e]];
+  }
+  acc = group_sum<G>(acc);
+  if (s < At.rows && lg == 0) {
+    if (alpha != 0.0) x[s] += (T)alpha * u[s];
+    u[s] = acc;
+  }
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(SC_NT)
+sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
+              const int64_t *__restrict__ cnt, const T *__restrict__ u,
+              const double *__restrict__ rho, T *__restrict__ res,
+              T *__restrict__ zz, T *__restrict__ p, T *__restrict__ v,
+              T *__restrict__ phat, double *__restrict__ part, double tol,
+              Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[1])) return;
+  __shared__ double sh[SC_NT / WAVE];
+  const int64_t c = *cnt;
+  constexpr int SPB = SC_NT / G;
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t a = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  T acc = 0;
+  if (a < c) {
+    const int64_t row = J[a];
+    const int64_t e0 = A.ptr[row], e1 = A.ptr[row + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * u[A.idx[e]];
+  }
+  acc = group_sum<G>(acc);
+  double pv = 0.0;
+  if (a < c && lg == 0) {
+    v[a] = acc;
+    pv = (double)acc * (double)p[a];
+  }
+  pv = block_sum<SC_NT>(pv, sh);
+  if (threadIdx.x == 0) st_agent(&part[blockIdx.x], pv);
+  if (!last_block(&ctrl->ticket[5])) return;
+  double tot = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += SC_NT) tot += ld_agent(&part[b]);
+  tot = block_sum<SC_NT>(tot, sh);
+  const double rz = ctrl->cg_rz[1];
+  const double alpha = tot != 0.0 ? rz / tot : 0.0;
+  double rz1 = 0.0, rr = 0.0;
+  for (int64_t k = threadIdx.x; k < c; k += SC_NT) {
+    const T r = res[k] - (T)alpha * ld_agent(&v[k]);
+    res[k] = r;
+    const double dj = rho[J[k]];
+    const T zv = dj > 0.0 ? (T)((double)r / dj) : (T)0;
+    zz[k] = zv;
+    rz1 += (double)r * (double)zv;
+    rr += (double)r * (double)r;
+  }
+  rz1 = block_sum<SC_NT>(rz1, sh);
+  rr = block_sum<SC_NT>(rr, sh);
+  const double beta = rz != 0.0 ? rz1 / rz : 0.0;
+  for (int64_t k = threadIdx.x; k < c; k += SC_NT) {
+    const T pn = zz[k] + (T)beta * p[k];
+    p[k] = pn;
+    phat[J[k]] = pn;
+  }
+  if (threadIdx.x == 0) {
+    ctrl->cg_alpha[1] = alpha;
+    ctrl->cg_rz[1] = rz1;
+    ctrl->cg_steps[1] += 1;
+    if (rr <= tol * tol * ctrl->cg_rz0[1] || tot == 0.0) ctrl->cg_done[1] = 1;
+  }
+}
+
+// final pending update x += alpha u (always exactly once per row phase)
+template <typename T>
+__global__ void __launch_bounds__(SC_NT)
+sc_row_finish(int64_t n, const T *__restrict__ u, T *__restrict__ x,
+              Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const double alpha = ctrl->cg_alpha[1];
+  const int64_t j = (int64_t)blockIdx.x * SC_NT + threadIdx.x;
+  if (j < n && alpha != 0.0) x[j] += (T)alpha * u[j];
+}
+
+template <typename T>
+static unsigned seg_blocks(int64_t nseg, int G) {
+  return (unsigned)((nseg + (SC_NT / G) - 1) / (SC_NT / G));
+}
+
+#define RG_SWITCH_G(GV, CALL)                 \
+  switch (GV) {                               \
+    case 1: { constexpr int GG = 1; CALL; } break;   \
+    case 2: { constexpr int GG = 2; CALL; } break;   \
+    case 4: { constexpr int GG = 4; CALL; } break;   \
+    case 8: { constexpr int GG = 8; CALL; } break;   \
+    case 16: { constexpr int GG = 16; CALL; } break; \
+    case 32: { constexpr int GG = 32; CALL; } break; \
+    default: { constexpr int GG = 64; CALL; } break; \
+  }
+
+template <typename T>
+void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
+                           const int32_t *U, const int64_t *count_dev,
+                           int64_t cap, const T *g, T *z, SparseCg<T> &w,
+                           int max_steps, double tol, Ctrl *ctrl,
+                           int respect_done, hipStream_t st) {
+  hipLaunchKernelGGL(sc_init<T>, dim3(1), dim3(SC_NT), 0, st, U, count_dev, g,
+                     (const double *)nullptr, w.res, (T *)nullptr, w.p, w.phat,
+                     ctrl, 0, respect_done);
+  const unsigned nbw = seg_blocks<T>(csr.rows, csr.group);
+  unsigned nbn = seg_blocks<T>(cap, csc.group);
+  if (nbn < 64) nbn = 64;
+  for (int s = 0; s < max_steps; ++s) {
+    RG_SWITCH_G(csr.group, hipLaunchKernelGGL((sc_wide_col<T, GG>), dim3(nbw),
+                                              dim3(SC_NT), 0, st, csr, w.phat,
+                                              w.wide, w.part, ctrl,
+                                              respect_done));
+    RG_SWITCH_G(csc.group,
+                hipLaunchKernelGGL((sc_narrow_col<T, GG>), dim3(nbn),
+                                   dim3(SC_NT), 0, st, csc, U, count_dev,
+                                   w.wide, z, csr.rows, w.res, w.p, w.phat,
+                                   w.part, tol, ctrl, respect_done));
+  }
+  hipLaunchKernelGGL(sc_clear<T>, dim3(64), dim3(SC_NT), 0, st, U, count_dev,
+                     cap, w.phat, ctrl, respect_done);
+}
+
+template <typename T>
+void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
+                           const int32_t *J, const int64_t *count_dev,
+                           int64_t cap, const T *r, const double *rho, T *x,
+                           SparseCg<T> &w, int max_steps, double tol,
+                           Ctrl *ctrl, int respect_done, hipStream_t st) {
+  hipLaunchKernelGGL(sc_init<T>, dim3(1), dim3(SC_NT), 0, st, J, count_dev, r,
+                     rho, w.res, w.v, w.p, w.phat, ctrl, 1, respect_done);
+  // w.v doubles as the Jacobi-scaled residual buffer zz during steps
+  const unsigned nbw = seg_blocks<T>(csc.rows, csc.group);
+  const unsigned nbn = seg_blocks<T>(cap, csr.group);
+  for (int s = 0; s < max_steps; ++s) {
+    RG_SWITCH_G(csc.group, hipLaunchKernelGGL((sc_wide_row<T, GG>), dim3(nbw),
+                                              dim3(SC_NT), 0, st, csc, w.phat,
+                                              w.wide, x, ctrl, respect_done));
+    RG_SWITCH_G(csr.group,
+                hipLaunchKernelGGL((sc_narrow_row<T, GG>), dim3(nbn),
+                                   dim3(SC_NT), 0, st, csr, J, count_dev,
+                                   w.wide, rho, w.res, w.v, w.p,
+                                   w.v + cap, w.phat, w.part, tol, ctrl,
+                                   respect_done));
+  }
+  hipLaunchKernelGGL(sc_row_finish<T>, dim3((unsigned)((csc.rows + SC_NT - 1) / SC_NT)),
+                     dim3(SC_NT), 0, st, csc.rows, w.wide, x, ctrl,
+                     respect_done);
+  hipLaunchKernelGGL(sc_clear<T>, dim3(64), dim3(SC_NT), 0, st, J, count_dev,
+                     cap, w.phat, ctrl, respect_done);
+}
+
+// ------------------------------------------------------------ instantiate
+#define RG_INST(T)                                                            \
+  template void launch_gram_gather<T>(const T *, int64_t, const int32_t *,   \
+                                      const int64_t *, int64_t, T *, Ctrl *,  \
+                                      int, hipStream_t);                      \
+  template void launch_gram_rows<T>(const T *, int64_t, int64_t,             \
+                                    const int32_t *, const int64_t *,        \
+                                    int64_t, T *, Ctrl *, int, hipStream_t);  \
+  template void launch_gram_full<T>(const T *, int64_t, int64_t, int64_t,    \
+                                    T *, hipStream_t);                        \
+  template void launch_chol_solve<T>(T *, int64_t, const int64_t *,          \
+                                     const T *, const int32_t *, T *, int,   \
+                                     Ctrl *, int, int, hipStream_t);          \
+  template void launch_pcg_gram_init<T>(const T *, int64_t, const int64_t *, \
+                                        const T *, const int32_t *, T *,     \
+                                        CgWork<T> &, Ctrl *, int, int,        \
+                                        hipStream_t);                         \
+  template void launch_pcg_gram_step<T>(const T *, int64_t, const int64_t *, \
+                                        T *, CgWork<T> &, double, Ctrl *,     \
+                                        int, int, hipStream_t);               \
+  template void launch_col_update<T>(const T *, int64_t, int64_t,            \
+                                     const int32_t *, const int64_t *,       \
+                                     int64_t, const T *, T *, T *, Ctrl *,   \
+                                     int, hipStream_t);                       \
+  template void launch_row_update<T>(const T *, int64_t, int64_t,            \
+                                     const int32_t *, const int64_t *,       \
+                                     int64_t, const T *, T *, T *, Ctrl *,   \
+                                     int, hipStream_t);                       \
+  template void launch_list_resid<T>(const T *, int64_t, int64_t,            \
+                                     const int32_t *, const int64_t *,       \
+                                     int64_t, const T *, const T *,          \
+                                     const T *, T *, Ctrl *, int,            \
+                                     hipStream_t);                            \
+  template void launch_sparse_colproj<T>(const Csr<T> &, const Csr<T> &,     \
+                                         const int32_t *, const int64_t *,   \
+                                         int64_t, const T *, T *,            \
+                                         SparseCg<T> &, int, double, Ctrl *, \
+                                         int, hipStream_t);                   \
+  template void launch_sparse_rowproj<T>(const Csr<T> &, const Csr<T> &,     \
+                                         const int32_t *, const int64_t *,   \
+                                         int64_t, const T *, const double *, \
+                                         T *, SparseCg<T> &, int, double,    \
+                                         Ctrl *, int, hipStream_t);
+RG_INST(double)
+RG_INST(float)
+#undef RG_INST
+
+}  // namespace rg

@@ -1,0 +1,1154 @@
+// Host runtime of the RGDBEK solver: handle lifecycle, device storage, the
+// per-iteration kernel sequence of Algorithm 1, HIP-graph capture of several
+// iterations at a time, the FP64 refinement loop of the mixed-precision form,
+// and the C-ABI entry points declared in include/rgdbek.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "../../include/rgdbek.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace rg;
+
+namespace {
+
+struct HipError {
+  hipError_t e;
+  const char *what;
+};
+struct ApiError {
+  rgdbek_status s;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                 \
+  do {                                            \
+    hipError_t _e = (x);                          \
+    if (_e != hipSuccess) throw HipError{_e, #x}; \
+  } while (0)
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int pick_group(double mean_len) {
+  int g = 1;
+  while (g < 64 && g < mean_len * 0.75) g <<= 1;
+  return g;
+}
+
+// Device allocation list owned by a handle.
+struct Pool {
+  std::vector<void *> ptrs;
+  template <typename T>
+  T *alloc(int64_t count, bool zero = true) {
+    if (count <= 0) count = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw ApiError{RGDBEK_ERR_OUT_OF_MEMORY,
+                     "device allocation of " +
+                         std::to_string(sizeof(T) * (size_t)count) +
+                         " bytes failed"};
+    }
+    ptrs.push_back(p);
+    if (zero) HIPCHK(hipMemset(p, 0, sizeof(T) * (size_t)count));
+    return (T *)p;
+  }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+// Work space and matrix views of one arithmetic precision.
+template <typename T>
+struct Engine {
+  bool ready = false;
+  bool dense = false;
+  int64_t m = 0, n = 0, kc = 0, kr = 0;
+  Dense<T> arm, acm;          // row-major A (ld), column-major A (ldc)
+  Csr<T> csr, csc;
+  const T *ata = nullptr, *aat = nullptr;  // precomputed Grams (nullable)
+  const double *rho = nullptr, *kappa = nullptr;
+  // vectors
+  T *x = nullptr, *z = nullptr, *b = nullptr, *q = nullptr, *g = nullptr;
+  T *r = nullptr, *eps_x = nullptr, *eps_z = nullptr, *off = nullptr;
+  int32_t *U = nullptr, *J = nullptr;
+  // dense block work
+  DenseWork<T> dw;
+  T *GU = nullptr, *GJ = nullptr, *y = nullptr, *w = nullptr, *s = nullptr;
+  T *upd = nullptr;
+  CgWork<T> cgc, cgr;
+  // sparse block work
+  SparseCg<T> scc, scr;
+  SelectScratch sel;
+  Reduce red;
+  double *part = nullptr;     // row-residual partials
+  double floor = 0.0;         // relative weight floor of the block draws
+};
+
+}  // namespace
+
+struct rgdbek_ctx {
+  int64_t m = 0, n = 0, nnz = 0;
+  bool dense = false;
+  rgdbek_params p{};
+  int64_t kc = 0, kr = 0;
+  hipStream_t user_st = nullptr;  // caller's stream (inputs are ordered on it)
+  hipStream_t st = nullptr;       // the stream all work is enqueued on
+  bool own_stream = false;        // st was created by the handle
+  std::string err;
+  Pool pool;
+  // FP64 storage
+  double *a_rm = nullptr, *a_cm = nullptr;
+  int64_t ld = 0, ldc = 0;
+  int64_t *csr_ptr = nullptr, *csc_ptr = nullptr;
+  int32_t *csr_idx = nullptr, *csc_idx = nullptr;
+  double *csr_val = nullptr, *csc_val = nullptr;
+  int32_t *csr_longs = nullptr, *csc_longs = nullptr;
+  int64_t csr_nlong = 0, csc_nlong = 0;
+  double *rho = nullptr, *kappa = nullptr;
+  Engine<double> e64;
+  Engine<double> e64t;        // adjoint system (A^T), built on demand
+  Engine<float> e32;          // inner engine of the mixed form
+  Ctrl *ctrl = nullptr;
+  Ctrl *hctrl = nullptr;      // pinned host mirror
+  double *xref = nullptr, *x64 = nullptr, *z64 = nullptr, *zero64 = nullptr,
+         *t64 = nullptr;
+  // captured graphs, keyed by (engine, key1, stop)
+  struct GraphEntry {
+    int which = 0;
+    uint64_t key1 = 0;
+    int stop = 0;
+    int use_xref = 0;
+    int with_base = 0;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+  };
+  std::vector<GraphEntry> graphs;
+};
+
+static thread_local std::string g_global_err;
+
+// RGDBEK_TRACE=1 prints one line per refinement pass / inner graph to stderr.
+static bool trace_on() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = std::getenv("RGDBEK_TRACE");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+namespace {
+
+void set_err(rgdbek_ctx *h, const std::string &m) {
+  if (h) h->err = m;
+  else g_global_err = m;
+}
+
+// ------------------------------------------------------------ engine set-up
+template <typename T>
+void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
+  Pool &P = h->pool;
+  e.dense = h->dense;
+  e.m = transpose ? h->n : h->m;
+  e.n = transpose ? h->m : h->n;
+  e.kc = transpose ? h->kr : h->kc;
+  e.kr = transpose ? h->kc : h->kr;
+  const bool f64 = std::is_same<T, double>::value;
+  const double wf = h->p.weight_floor;
+  e.floor = wf > 0.0 ? wf : (wf < 0.0 ? 0.0 : (f64 ? 1e-20 : 1e-6));
+  if (h->dense) {
+    // row-major and column-major copies in precision T
+    const int64_t ld = transpose ? h->ldc : h->ld;
+    const int64_t ldc = transpose ? h->ld : h->ldc;
+    T *rm, *cm;
+    if (f64) {
+      rm = (T *)(transpose ? h->a_cm : h->a_rm);
+      cm = (T *)(transpose ? h->a_rm : h->a_cm);
+    } else {
+      rm = P.alloc<T>(e.m * ld, false);
+      cm = P.alloc<T>(e.n * ldc, false);
+      launch_convert<T, double>(transpose ? h->a_cm : h->a_rm, rm, e.m * ld,
+                                h->st);
+      launch_convert<T, double>(transpose ? h->a_rm : h->a_cm, cm, e.n * ldc,
+                                h->st);
+    }
+    e.arm = Dense<T>{e.m, e.n, ld, rm};
+    e.acm = Dense<T>{e.n, e.m, ldc, cm};
+    int nch, nrb;
+    dense_work_shape<T>(e.arm, &nch, &nrb);
+    e.dw.nch = nch;
+    e.dw.nrb = nrb;
+    e.dw.qpart = P.alloc<T>((int64_t)nch * e.m);
+    e.dw.gpart = P.alloc<T>((int64_t)nrb * ld);
+    // Gram of all columns (A^T A) when the column blocks are large enough to
+    // be worth a gather; rows: A A^T only on request.
+    const bool gram_cols = e.kc > 64 && e.n <= 8192;
+    if (gram_cols) {
+      T *F = P.alloc<T>(e.n * e.n, false);
+      launch_gram_full<T>(cm, ldc, e.n, e.m, F, h->st);
+      e.ata = F;
+    }
+    const bool gram_rows = (h->p.flags & RGDBEK_FLAG_GRAM_AAT) && e.m <= 32768;
+    if (gram_rows) {
+      T *F = P.alloc<T>(e.m * e.m, false);
+      launch_gram_full<T>(rm, ld, e.m, e.n, F, h->st);
+      e.aat = F;
+    }
+    e.GU = P.alloc<T>(e.kc * e.kc);
+    e.GJ = P.alloc<T>(e.kr * e.kr);
+    e.y = P.alloc<T>(e.kc);
+    e.w = P.alloc<T>(e.kr);
+    e.s = P.alloc<T>(e.kr);
+    e.upd = P.alloc<T>(std::max(thin_update_scratch(e.m, e.kc),
+                                thin_update_scratch(e.n, e.kr)));
+    for (CgWork<T> *cw : {&e.cgc, &e.cgr}) {
+      const int64_t cap = (cw == &e.cgc) ? e.kc : e.kr;
+      cw->res = P.alloc<T>(cap);
+      cw->p = P.alloc<T>(cap);
+      cw->v = P.alloc<T>(cap);
+      cw->zz = P.alloc<T>(cap);
+      cw->part = P.alloc<double>(cap / 4 + 64);
+    }
+  } else {
+    // CSR / CSC views; the adjoint swaps them
+    Csr<T> a, at;
+    const double *vr = transpose ? h->csc_val : h->csr_val;
+    const double *vc = transpose ? h->csr_val : h->csc_val;
+    const T *vrT, *vcT;
+    if (f64) {
+      vrT = (const T *)vr;
+      vcT = (const T *)vc;
+    } else {
+      T *t1 = P.alloc<T>(h->nnz, false), *t2 = P.alloc<T>(h->nnz, false);
+      launch_convert<T, double>(vr, t1, h->nnz, h->st);
+      launch_convert<T, double>(vc, t2, h->nnz, h->st);
+      vrT = t1;
+      vcT = t2;
+    }
+    a.rows = e.m; a.cols = e.n; a.nnz = h->nnz;
+    a.ptr = transpose ? h->csc_ptr : h->csr_ptr;
+    a.idx = transpose ? h->csc_idx : h->csr_idx;
+    a.val = vrT;
+    at.rows = e.n; at.cols = e.m; at.nnz = h->nnz;
+    at.ptr = transpose ? h->csr_ptr : h->csc_ptr;
+    at.idx = transpose ? h->csr_idx : h->csc_idx;
+    at.val = vcT;
+    const double mr = e.m ? (double)h->nnz / (double)e.m : 1.0;
+    const double mc = e.n ? (double)h->nnz / (double)e.n : 1.0;
+    a.group = pick_group(mr);
+    at.group = pick_group(mc);
+    // the long-segment lists were built with these same limits (the
+    // adjoint's rows are the forward columns and vice versa)
+    a.long_limit = 32LL * a.group;
+    at.long_limit = 32LL * at.group;
+    a.longs = transpose ? h->csc_longs : h->csr_longs;
+    a.nlong = transpose ? h->csc_nlong : h->csr_nlong;
+    at.longs = transpose ? h->csr_longs : h->csc_longs;
+    at.nlong = transpose ? h->csr_nlong : h->csc_nlong;
+    e.csr = a;
+    e.csc = at;
+    for (int ph = 0; ph < 2; ++ph) {
+      SparseCg<T> &sc = ph == 0 ? e.scc : e.scr;
+      const int64_t cap = ph == 0 ? e.kc : e.kr;
+      sc.phat = P.alloc<T>(ph == 0 ? e.n : e.m);
+      sc.wide = P.alloc<T>(ph == 0 ? e.m : e.n);
+      sc.p = P.alloc<T>(cap);
+      sc.res = P.alloc<T>(cap);
+      sc.v = P.alloc<T>(2 * cap);
+      const int64_t nb = std::max(e.m, e.n) / 4 + cap / 4 + 1024;
+      sc.part = P.alloc<double>(nb);
+    }
+  }
+  e.rho = transpose ? h->kappa : h->rho;
+  e.kappa = transpose ? h->rho : h->kappa;
+  e.x = P.alloc<T>(round_up(e.n, 8) + 64);
+  e.z = P.alloc<T>(e.m + 64);
+  e.b = P.alloc<T>(e.m + 64);
+  e.q = P.alloc<T>(e.m + 64);
+  e.r = P.alloc<T>(e.m + 64);
+  e.g = P.alloc<T>(e.n + 64);
+  e.eps_x = P.alloc<T>(e.m + 64);
+  e.eps_z = P.alloc<T>(e.n + 64);
+  e.off = P.alloc<T>(e.n + 64);
+  e.U = P.alloc<int32_t>(e.kc + 64);
+  e.J = P.alloc<int32_t>(e.kr + 64);
+  const int64_t dmax = std::max(e.m, e.n);
+  e.sel.keys = P.alloc<uint64_t>(dmax + 64, false);
+  e.sel.hist = P.alloc<unsigned>(2048);
+  e.sel.ckey = P.alloc<uint64_t>(4096);
+  e.sel.cidx = P.alloc<int64_t>(4096);
+  e.sel.blk = P.alloc<int32_t>(select_scratch_blocks(dmax) + 64);
+  e.red.part = P.alloc<double>(1024);
+  e.red.cap = 1024;
+  e.part = P.alloc<double>(2 * (dmax / 4 + 1024) + 2 * (h->csr_nlong + h->csc_nlong));
+  e.ready = true;
+}
+
+// ------------------------------------------------------------ iteration
+struct IterOpts {
+  uint64_t key1 = 0;
+  int stop = RGDBEK_STOP_NONE;
+  const double *xref = nullptr;   // ERR_REF reference
+  const double *xbase = nullptr;  // ERR_REF on xbase + x (mixed inner loop)
+  bool use_off = false;           // column offset (refinement correction)
+};
+
+template <typename T>
+void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
+  hipStream_t st = h->st;
+  Ctrl *c = h->ctrl;
+  const rgdbek_params &p = h->p;
+  const int maxs = p.inner_max > 0 ? p.inner_max : 64;
+  const bool f64 = std::is_same<T, double>::value;
+  const double itol = p.inner_tol > 0 ? p.inner_tol : (f64 ? 1e-14 : 1e-7);
+  const int64_t cnt0_off = offsetof(Ctrl, sel_count);
+  const int64_t *cntU = (const int64_t *)((const char *)c + cnt0_off);
+  const int64_t *cntJ = cntU + 1;
+  const T *off = o.use_off ? e.off : nullptr;
+
+  if (o.stop == RGDBEK_STOP_ERR_REF)
+    launch_err_ref<T>(e.n, e.x, o.xref, o.xbase, e.red, c, 1, st);
+  // ---- column phase: g = A^T z (+ t), eps^z, select U, project z
+  if (e.dense) {
+    launch_dense_fused<T>(e.arm, e.x, e.z, e.dw, off, e.kappa, e.g, e.eps_z,
+                          e.q, c, 1, st);
+  } else {
+    SegArgs<T> a;
+    a.v = e.z; a.g = e.g; a.off = off; a.eps = e.eps_z; a.nrm = e.kappa;
+    launch_segdot<T>(e.csc, EPI_COLRES, a, c, 1, st);
+  }
+  launch_select<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0, e.sel,
+                   e.U, c, 1, st);
+  const bool chol_c = p.solver == RGDBEK_SOLVER_CHOL ||
+                      (p.solver == RGDBEK_SOLVER_AUTO && e.kc <= 256);
+  const bool chol_r = p.solver == RGDBEK_SOLVER_CHOL ||
+                      (p.solver == RGDBEK_SOLVER_AUTO && e.kr <= 256);
+  if (e.dense) {
+    if (e.ata)
+      launch_gram_gather<T>(e.ata, e.n, e.U, cntU, e.kc, e.GU, c, 1, st);
+    else
+      launch_gram_rows<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.GU, c, 1,
+                          st);
+    if (chol_c && e.kc <= CHOL_MAX) {
+      launch_chol_solve<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, 1, c, 0, 1, st);
+    } else {
+      launch_pcg_gram_init<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, c, 0, 1,
+                              st);
+      for (int k = 0; k < maxs; ++k)
+        launch_pcg_gram_step<T>(e.GU, e.kc, cntU, e.y, e.cgc, itol, c, 0, 1,
+                                st);
+    }
+    launch_col_update<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.y, e.z,
+                         e.upd, c, 1, st);
+  } else {
+    launch_sparse_colproj<T>(e.csr, e.csc, e.U, cntU, e.kc, e.g, e.z, e.scc,
+                             maxs, itol, c, 1, st);
+  }
+  // ---- row phase: r = b - z - A x, eps^x, stop test, select J, project x
+  int nparts;
+  if (e.dense) {
+    nparts = launch_rowres_dense<T>(e.m, e.b, e.z, e.q, e.rho, e.r, e.eps_x,
+                                    e.part, c, 1, st);
+  } else {
+    SegArgs<T> a;
+    a.v = e.x; a.b = e.b; a.z = e.z; a.r = e.r; a.eps = e.eps_x;
+    a.nrm = e.rho; a.part = e.part;
+    nparts = launch_segdot<T>(e.csr, EPI_ROWRES, a, c, 1, st);
+  }
+  if (o.stop == RGDBEK_STOP_RSE || o.stop == RGDBEK_STOP_RES_EXT)
+    launch_stop_rowres(e.part, nparts, c, st);
+  launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1, e.sel,
+                   e.J, c, 1, st);
+  if (e.dense) {
+    if (e.aat)
+      launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
+    else
+      launch_gram_rows<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.GJ, c, 1,
+                          st);
+    if (chol_r && e.kr <= CHOL_MAX) {
+      launch_chol_solve<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, 1, c, 1, 1, st);
+      launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
+                           e.upd, c, 1, st);
+      // corrected semi-normal equations: one sweep with the residual of the
+      // projected equations recomputed from A^J itself
+      launch_list_resid<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.b, e.z,
+                           e.x, e.s, c, 1, st);
+      launch_chol_solve<T>(e.GJ, e.kr, cntJ, e.s, nullptr, e.w, 0, c, 1, 1,
+                           st);
+      launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
+                           e.upd, c, 1, st);
+    } else {
+      launch_pcg_gram_init<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, c, 1, 1,
+                              st);
+      for (int k = 0; k < maxs; ++k)
+        launch_pcg_gram_step<T>(e.GJ, e.kr, cntJ, e.w, e.cgr, itol, c, 1, 1,
+                                st);
+      launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
+                           e.upd, c, 1, st);
+    }
+  } else {
+    launch_sparse_rowproj<T>(e.csr, e.csc, e.J, cntJ, e.kr, e.r, e.rho, e.x,
+                             e.scr, maxs, itol, c, 1, st);
+  }
+  launch_end_iter(c, st);
+}
+
+int graph_iters(const rgdbek_ctx *h) {
+  return h->p.graph_iters > 0 ? h->p.graph_iters : 8;
+}
+
+template <typename T>
+hipGraphExec_t get_graph(rgdbek_ctx *h, Engine<T> &e, int which,
+                         const IterOpts &o) {
+  for (auto &g : h->graphs)
+    if (g.which == which && g.key1 == o.key1 && g.stop == o.stop &&
+        g.use_xref == (o.xref != nullptr) && g.with_base == (o.xbase != nullptr))
+      return g.exec;
+  rgdbek_ctx::GraphEntry ge;
+  ge.which = which;
+  ge.key1 = o.key1;
+  ge.stop = o.stop;
+  ge.use_xref = o.xref != nullptr;
+  ge.with_base = o.xbase != nullptr;
+  HIPCHK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < graph_iters(h); ++i) enqueue_iteration<T>(h, e, o);
+  HIPCHK(hipStreamEndCapture(h->st, &ge.graph));
+  HIPCHK(hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+  h->graphs.push_back(ge);
+  return ge.exec;
+}
+
+void ctrl_reset(rgdbek_ctx *h, int64_t it0, int64_t max_iter, int stop,
+                double tol) {
+  Ctrl &c = *h->hctrl;
+  std::memset(&c, 0, sizeof(Ctrl));
+  c.it = it0;
+  c.it_end = max_iter;
+  c.stop_mode = stop;
+  c.tol = tol;
+  c.done = max_iter <= 0 ? 1 : 0;
+  HIPCHK(hipMemcpyAsync(h->ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice,
+                        h->st));
+}
+
+void ctrl_fetch(rgdbek_ctx *h) {
+  HIPCHK(hipMemcpyAsync(h->hctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost,
+                        h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+}
+
+// Run iterations until done; the host looks at the device flag once per graph.
+template <typename T>
+void run_loop(rgdbek_ctx *h, Engine<T> &e, int which, const IterOpts &o) {
+  const bool use_graph = (h->p.flags & RGDBEK_FLAG_GRAPH) != 0;
+  hipGraphExec_t ge = use_graph ? get_graph<T>(h, e, which, o) : nullptr;
+  while (true) {
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(ge, h->st));
+    } else {
+      for (int i = 0; i < graph_iters(h); ++i) enqueue_iteration<T>(h, e, o);
+    }
+    HIPCHK(hipMemcpyAsync(&h->hctrl->done, &h->ctrl->done, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (h->hctrl->done) break;
+  }
+  HIPCHK(hipGetLastError());
+}
+
+rgdbek_status finish_status(rgdbek_ctx *h, rgdbek_info *info, double secs,
+                            int64_t outer) {
+  Ctrl &c = *h->hctrl;
+  rgdbek_status s = RGDBEK_OK;
+  if (c.numeric) {
+    s = RGDBEK_ERR_NUMERIC;
+    set_err(h, "NaN, negative or infinite residual weight during the solve");
+  } else if (!c.converged && h->p.stop != RGDBEK_STOP_NONE) {
+    s = RGDBEK_ERR_NOT_CONVERGED;
+    set_err(h, "max_iter reached before the stopping test held");
+  }
+  if (info) {
+    info->iterations = c.iters_run;
+    info->outer_iterations = outer;
+    info->final_metric = c.metric;
+    info->converged = (h->p.stop == RGDBEK_STOP_NONE) ? (c.numeric ? 0 : 1)
+                                                      : c.converged;
+    info->status = (int32_t)s;
+    info->seconds = secs;
+  }
+  return s;
+}
+
+// Check that b (device) is finite.
+void check_b(rgdbek_ctx *h, const double *b, int64_t len) {
+  int *flag = h->pool.alloc<int>(1);
+  launch_check_finite<double>(b, len, flag, h->st);
+  int hv = 0;
+  HIPCHK(hipMemcpyAsync(&hv, flag, sizeof(int), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  HIPCHK(hipFree(flag));
+  h->pool.ptrs.pop_back();
+  if (hv) throw ApiError{RGDBEK_ERR_NUMERIC, "right-hand side has NaN/Inf"};
+}
+
+// ------------------------------------------------------------ FP64 solve
+rgdbek_status solve64(rgdbek_ctx *h, Engine<double> &e, int which,
+                      uint64_t key1, int stop, const double *b, double *x,
+                      double *z_io, int64_t it0, bool resume,
+                      const double *x_ref_user, rgdbek_info *info) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = h->st;
+  const double *x_ref = nullptr;
+  if (x_ref_user) {
+    HIPCHK(hipMemcpyAsync(h->xref, x_ref_user, sizeof(double) * e.n,
+                          hipMemcpyDeviceToDevice, st));
+    x_ref = h->xref;
+  }
+  check_b(h, b, e.m);
+  HIPCHK(hipMemcpyAsync(e.b, b, sizeof(double) * e.m, hipMemcpyDeviceToDevice, st));
+  if (resume) {
+    HIPCHK(hipMemcpyAsync(e.x, x, sizeof(double) * e.n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(e.z, z_io, sizeof(double) * e.m, hipMemcpyDeviceToDevice, st));
+  } else {
+    launch_axpby<double, double>(e.n, 0.0, e.x, 0.0, (const double *)nullptr, st);
+    HIPCHK(hipMemcpyAsync(e.z, b, sizeof(double) * e.m, hipMemcpyDeviceToDevice, st));
+  }
+  ctrl_reset(h, it0, h->p.max_iter, stop, h->p.tol);
+  if (stop == RGDBEK_STOP_ERR_REF) launch_set_ref2<double>(e.n, x_ref, h->ctrl, st);
+  else launch_set_ref2<double>(e.m, e.b, h->ctrl, st);
+  IterOpts o;
+  o.key1 = key1;
+  o.stop = stop;
+  o.xref = stop == RGDBEK_STOP_ERR_REF ? x_ref : nullptr;
+  run_loop<double>(h, e, which, o);
+  if (stop == RGDBEK_STOP_ERR_REF)
+    launch_err_ref<double>(e.n, e.x, x_ref, nullptr, e.red, h->ctrl, 0, st);
+  HIPCHK(hipMemcpyAsync(x, e.x, sizeof(double) * e.n, hipMemcpyDeviceToDevice, st));
+  if (z_io)
+    HIPCHK(hipMemcpyAsync(z_io, e.z, sizeof(double) * e.m, hipMemcpyDeviceToDevice, st));
+  ctrl_fetch(h);
+  const double secs = std::chrono::duration<double>(
+                          std::chrono::steady_clock::now() - t0).count();
+  return finish_status(h, info, secs, 1);
+}
+
+// ------------------------------------------------------------ mixed solve
+// Refinement with FP32 inner RGDBEK.  FP64 state x; each pass:
+//   z = b - A x                        (FP64, so z - b stays in range(A))
+//   t = A^T z                          (FP64, the normal-equation residual)
+//   FP32 RGDBEK on the correction (dx, dz) from (0, 0): column residual
+//   A^T dz + t, row residual -dz - A dx (right-hand side s = b - z - A x = 0)
+//   x += dx (FP64)
+// The fixed point of a pass is x + dx = A^+ b exactly; FP32 only limits how
+// far one pass contracts the error (about u_32 * cond).  Carrying z across
+// passes instead would freeze FP32 rounding in its null(A^T) component and
+// stall the refinement.  An inner pass ends when the global stop test holds
+// on x + dx, or when its metric has not improved by 5% for 4 graphs.
+rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
+                          const double *x_ref_user, rgdbek_info *info) {
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = h->st;
+  const double *x_ref = nullptr;
+  if (x_ref_user) {
+    HIPCHK(hipMemcpyAsync(h->xref, x_ref_user, sizeof(double) * h->n,
+                          hipMemcpyDeviceToDevice, st));
+    x_ref = h->xref;
+  }
+  Engine<double> &E = h->e64;
+  Engine<float> &F = h->e32;
+  const int stop = h->p.stop;
+  check_b(h, b, E.m);
+  HIPCHK(hipMemcpyAsync(E.b, b, sizeof(double) * E.m, hipMemcpyDeviceToDevice, st));
+  launch_axpby<double, double>(E.n, 0.0, h->x64, 0.0, (const double *)nullptr, st);
+  int64_t total_it = 0, outer = 0;
+  const int max_outer = 12;
+  double metric = 0.0, prev_metric = 1e300;
+  bool converged = false;
+  int numeric = 0;
+  for (outer = 1; outer <= max_outer; ++outer) {
+    // z = b - A x and the stop metric, then t = A^T z (FP64 passes)
+    ctrl_reset(h, 0, 1, stop, h->p.tol);
+    int nparts;
+    if (E.dense) {
+      launch_dense_fused<double>(E.arm, h->x64, h->z64, E.dw, nullptr, E.kappa,
+                                 h->t64, E.eps_z, E.q, h->ctrl, 0, st);
+      nparts = launch_rowres_dense<double>(E.m, E.b, h->zero64, E.q, E.rho,
+                                           h->z64, E.eps_x, E.part, h->ctrl, 0,
+                                           st);
+      launch_dense_fused<double>(E.arm, h->x64, h->z64, E.dw, nullptr, E.kappa,
+                                 h->t64, E.eps_z, E.q, h->ctrl, 0, st);
+    } else {
+      SegArgs<double> r;
+      r.v = h->x64; r.b = E.b; r.z = h->zero64; r.r = h->z64; r.eps = E.eps_x;
+      r.nrm = E.rho; r.part = E.part;
+      nparts = launch_segdot<double>(E.csr, EPI_ROWRES, r, h->ctrl, 0, st);
+      SegArgs<double> a;
+      a.v = h->z64; a.g = h->t64; a.eps = E.eps_z; a.nrm = E.kappa;
+      launch_segdot<double>(E.csc, EPI_COLRES, a, h->ctrl, 0, st);
+    }
+    if (stop == RGDBEK_STOP_ERR_REF) {
+      launch_set_ref2<double>(E.n, x_ref, h->ctrl, st);
+      launch_err_ref<double>(E.n, h->x64, x_ref, nullptr, E.red, h->ctrl, 0, st);
+    } else if (stop == RGDBEK_STOP_RSE) {
+      launch_set_ref2<double>(E.m, E.b, h->ctrl, st);
+      launch_stop_rowres(E.part, nparts, h->ctrl, st);
+    }
+    ctrl_fetch(h);
+    metric = h->hctrl->metric;
+    if (trace_on())
+      std::fprintf(stderr, "[rgdbek] pass %lld fp64 metric %.3e (inner its so far %lld)\n",
+                   (long long)outer, metric, (long long)total_it);
+    if (stop != RGDBEK_STOP_NONE && metric <= h->p.tol) {
+      converged = true;
+      break;
+    }
+    if (total_it >= h->p.max_iter) break;
+    if (outer > 2 && metric > 0.5 * prev_metric) break;  // refinement stalled
+    prev_metric = metric;
+    // FP32 pass on the correction system: s = 0, offset t
+    launch_axpby<float, float>(F.m, 0.0, F.b, 0.0, (const float *)nullptr, st);
+    launch_convert<float, double>(h->t64, F.off, E.n, st);
+    launch_axpby<float, float>(F.n, 0.0, F.x, 0.0, (const float *)nullptr, st);
+    launch_axpby<float, float>(F.m, 0.0, F.z, 0.0, (const float *)nullptr, st);
+    const int istop = (stop == RGDBEK_STOP_ERR_REF) ? RGDBEK_STOP_ERR_REF
+                      : (stop == RGDBEK_STOP_NONE ? RGDBEK_STOP_NONE
+                                                  : RGDBEK_STOP_RES_EXT);
+    // inner RES_EXT runs with tol 0: it only feeds the stall detector
+    ctrl_reset(h, total_it, h->p.max_iter - total_it, istop,
+               istop == RGDBEK_STOP_ERR_REF ? h->p.tol : 0.0);
+    if (istop == RGDBEK_STOP_ERR_REF) launch_set_ref2<double>(E.n, x_ref, h->ctrl, st);
+    else launch_set_ref2<double>(E.m, E.b, h->ctrl, st);
+    IterOpts o;
+    o.key1 = 0;
+    o.stop = istop;
+    o.xref = istop == RGDBEK_STOP_ERR_REF ? x_ref : nullptr;
+    o.xbase = istop == RGDBEK_STOP_ERR_REF ? h->x64 : nullptr;
+    o.use_off = true;
+    {
+      const bool use_graph = (h->p.flags & RGDBEK_FLAG_GRAPH) != 0;
+      hipGraphExec_t ge = use_graph ? get_graph<float>(h, F, 2, o) : nullptr;
+      double best = 1e300;
+      int since_best = 0;
+      const int window = 4;
+      while (true) {
+        if (use_graph) HIPCHK(hipGraphLaunch(ge, st));
+        else for (int i = 0; i < graph_iters(h); ++i) enqueue_iteration<float>(h, F, o);
+        if (istop == RGDBEK_STOP_NONE) {
+          HIPCHK(hipMemcpyAsync(&h->hctrl->done, &h->ctrl->done, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          if (h->hctrl->done) break;
+          continue;
+        }
+        ctrl_fetch(h);
+        if (trace_on())
+          std::fprintf(stderr, "[rgdbek]   inner its %lld metric %.3e done %d\n",
+                       (long long)h->hctrl->iters_run, h->hctrl->metric,
+                       h->hctrl->done);
+        if (h->hctrl->done) break;
+        const double mt = h->hctrl->metric;
+        if (mt < 0.95 * best) { best = mt; since_best = 0; }
+        else if (++since_best >= window) break;
+      }
+    }
+    ctrl_fetch(h);
+    total_it += h->hctrl->iters_run;
+    numeric |= h->hctrl->numeric;
+    launch_axpby<double, float>(E.n, 1.0, h->x64, 1.0, F.x, st);
+    launch_axpby<double, float>(E.m, 1.0, h->z64, 1.0, F.z, st);
+    if (numeric || stop == RGDBEK_STOP_NONE) {
+      if (stop == RGDBEK_STOP_NONE) converged = true;
+      break;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(x, h->x64, sizeof(double) * E.n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(E.z, h->z64, sizeof(double) * E.m, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(
+                          std::chrono::steady_clock::now() - t0).count();
+  Ctrl &c = *h->hctrl;
+  c.iters_run = total_it;
+  c.metric = metric;
+  c.converged = converged ? 1 : 0;
+  c.numeric = numeric;
+  return finish_status(h, info, secs, outer > max_outer ? max_outer : outer);
+}
+
+// ------------------------------------------------------------ validation
+void validate_params(const rgdbek_params *p, int64_t m, int64_t n,
+                     int64_t *kc, int64_t *kr) {
+  if (!(p->eta >= 0.0) || p->eta > 1.0)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "eta must lie in [0, 1]"};
+  auto from_eta = [&](int64_t d) -> int64_t {
+    if (d <= 0) return 0;
+    int64_t k = (int64_t)std::floor(p->eta * (double)d + 0.5);
+    return std::min<int64_t>(d, std::max<int64_t>(1, k));
+  };
+  *kc = p->k_col > 0 ? p->k_col : from_eta(n);
+  *kr = p->k_row > 0 ? p->k_row : from_eta(m);
+  if (p->k_col < 0 || p->k_row < 0)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "k_col/k_row must be >= 0"};
+  if (*kc > n || *kr > m)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "block size larger than the dimension"};
+  if (*kc < 1 || *kr < 1)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "block sizes must be positive"};
+  if (p->stop < RGDBEK_STOP_NONE || p->stop > RGDBEK_STOP_RES_EXT)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "unknown stop mode"};
+  if (p->precision < RGDBEK_PREC_FP64 || p->precision > RGDBEK_PREC_MIXED_BF16)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "unknown precision"};
+  if (p->precision == RGDBEK_PREC_MIXED_BF16)
+    throw ApiError{RGDBEK_ERR_UNSUPPORTED, "bfloat16 inner values are not built"};
+  if (p->precision == RGDBEK_PREC_MIXED_F32 && p->stop == RGDBEK_STOP_RES_EXT)
+    throw ApiError{RGDBEK_ERR_UNSUPPORTED,
+                   "the mixed form restarts z = b - A x each pass; use ERR_REF, "
+                   "RSE or NONE"};
+  if (p->max_iter < 0 || !(p->tol >= 0.0))
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "max_iter and tol must be >= 0"};
+  if (p->solver < 0 || p->solver > RGDBEK_SOLVER_CG)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "unknown block solver"};
+  if (p->inner_max < 0 || p->inner_max > 4096 || p->graph_iters < 0 ||
+      p->graph_iters > 1024)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "inner_max/graph_iters out of range"};
+}
+
+// CSR structure check on the host (copies row_ptr and col_idx).
+void validate_csr(const rgdbek_matrix *A) {
+  std::vector<int64_t> rp(A->m + 1);
+  HIPCHK(hipMemcpy(rp.data(), A->row_ptr, sizeof(int64_t) * (A->m + 1),
+                   hipMemcpyDeviceToHost));
+  if (rp[0] != 0 || rp[A->m] != A->nnz)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "row_ptr must start at 0 and end at nnz"};
+  for (int64_t i = 0; i < A->m; ++i)
+    if (rp[i + 1] < rp[i])
+      throw ApiError{RGDBEK_ERR_INVALID_ARG, "row_ptr must be non-decreasing"};
+  std::vector<int32_t> ci(A->nnz);
+  if (A->nnz)
+    HIPCHK(hipMemcpy(ci.data(), A->col_idx, sizeof(int32_t) * A->nnz,
+                     hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < A->m; ++i)
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      if (ci[e] < 0 || ci[e] >= A->n)
+        throw ApiError{RGDBEK_ERR_INVALID_ARG, "column index out of range"};
+      if (e > rp[i] && ci[e] <= ci[e - 1])
+        throw ApiError{RGDBEK_ERR_INVALID_ARG,
+                       "column indices must increase within a row"};
+    }
+}
+
+// long-segment lists (host-side from the pointer arrays)
+void build_longs(rgdbek_ctx *h, const int64_t *ptr_dev, int64_t rows,
+                 int64_t limit, int32_t **out, int64_t *count) {
+  std::vector<int64_t> rp(rows + 1);
+  HIPCHK(hipMemcpy(rp.data(), ptr_dev, sizeof(int64_t) * (rows + 1),
+                   hipMemcpyDeviceToHost));
+  std::vector<int32_t> longs;
+  for (int64_t i = 0; i < rows; ++i)
+    if (rp[i + 1] - rp[i] > limit) longs.push_back((int32_t)i);
+  *count = (int64_t)longs.size();
+  *out = h->pool.alloc<int32_t>(std::max<int64_t>(1, *count), false);
+  if (*count)
+    HIPCHK(hipMemcpy(*out, longs.data(), sizeof(int32_t) * longs.size(),
+                     hipMemcpyHostToDevice));
+}
+
+void create_impl(rgdbek_ctx *h, const rgdbek_matrix *A) {
+  hipStream_t st = h->st;
+  Pool &P = h->pool;
+  h->ctrl = P.alloc<Ctrl>(1);
+  HIPCHK(hipHostMalloc((void **)&h->hctrl, sizeof(Ctrl), hipHostMallocDefault));
+  int *flag = P.alloc<int>(1);
+  if (h->dense) {
+    h->ld = round_up(std::max<int64_t>(h->n, 1), 8);
+    h->ldc = round_up(std::max<int64_t>(h->m, 1), 8);
+    h->a_rm = P.alloc<double>(h->m * h->ld, false);
+    h->a_cm = P.alloc<double>(h->n * h->ldc, false);
+    if (A->value_type == RGDBEK_F64) {
+      launch_check_finite<double>((const double *)A->values, h->m * h->n, flag, st);
+      launch_pack_dense<double, double>((const double *)A->values, h->m, h->n,
+                                        h->n, h->a_rm, h->ld, h->a_cm, h->ldc, st);
+    } else {
+      launch_check_finite<float>((const float *)A->values, h->m * h->n, flag, st);
+      launch_pack_dense<double, float>((const float *)A->values, h->m, h->n,
+                                       h->n, h->a_rm, h->ld, h->a_cm, h->ldc, st);
+    }
+    h->rho = P.alloc<double>(h->m);
+    h->kappa = P.alloc<double>(h->n);
+    launch_sqnorms_dense<double>(h->a_rm, h->m, h->n, h->ld, h->a_cm, h->ldc,
+                                 h->rho, h->kappa, st);
+  } else {
+    validate_csr(A);
+    h->csr_ptr = P.alloc<int64_t>(h->m + 1, false);
+    h->csr_idx = P.alloc<int32_t>(h->nnz, false);
+    h->csr_val = P.alloc<double>(h->nnz, false);
+    HIPCHK(hipMemcpyAsync(h->csr_ptr, A->row_ptr, 8 * (h->m + 1),
+                          hipMemcpyDeviceToDevice, st));
+    if (h->nnz)
+      HIPCHK(hipMemcpyAsync(h->csr_idx, A->col_idx, 4 * h->nnz,
+                            hipMemcpyDeviceToDevice, st));
+    if (A->value_type == RGDBEK_F64) {
+      launch_check_finite<double>((const double *)A->values, h->nnz, flag, st);
+      launch_convert<double, double>((const double *)A->values, h->csr_val, h->nnz, st);
+    } else {
+      launch_check_finite<float>((const float *)A->values, h->nnz, flag, st);
+      launch_convert<double, float>((const float *)A->values, h->csr_val, h->nnz, st);
+    }
+    h->csc_ptr = P.alloc<int64_t>(h->n + 1, false);
+    h->csc_idx = P.alloc<int32_t>(h->nnz, false);
+    h->csc_val = P.alloc<double>(h->nnz, false);
+    int64_t *work = P.alloc<int64_t>(h->n + 1, false);
+    launch_csr_to_csc<double>(h->m, h->n, h->nnz, h->csr_ptr, h->csr_idx,
+                              h->csr_val, h->csc_ptr, h->csc_idx, h->csc_val,
+                              work, st);
+    HIPCHK(hipStreamSynchronize(st));
+    const int gr = pick_group(h->m ? (double)h->nnz / h->m : 1.0);
+    const int gc = pick_group(h->n ? (double)h->nnz / h->n : 1.0);
+    build_longs(h, h->csr_ptr, h->m, 32LL * gr, &h->csr_longs, &h->csr_nlong);
+    build_longs(h, h->csc_ptr, h->n, 32LL * gc, &h->csc_longs, &h->csc_nlong);
+    h->rho = P.alloc<double>(h->m);
+    h->kappa = P.alloc<double>(h->n);
+    Csr<double> a, at;
+    a.rows = h->m; a.ptr = h->csr_ptr; a.idx = h->csr_idx; a.val = h->csr_val;
+    at.rows = h->n; at.ptr = h->csc_ptr; at.idx = h->csc_idx; at.val = h->csc_val;
+    launch_sqnorms_csr<double>(a, h->rho, st);
+    launch_sqnorms_csr<double>(at, h->kappa, st);
+  }
+  int hv = 0;
+  HIPCHK(hipMemcpyAsync(&hv, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hv) throw ApiError{RGDBEK_ERR_NUMERIC, "matrix values contain NaN/Inf"};
+  h->xref = P.alloc<double>(std::max(h->m, h->n) + 64);
+  build_engine<double>(h, h->e64, false);
+  if (h->p.precision == RGDBEK_PREC_MIXED_F32) {
+    build_engine<float>(h, h->e32, false);
+    h->x64 = P.alloc<double>(round_up(h->n, 8) + 64);
+    h->z64 = P.alloc<double>(h->m + 64);
+    h->zero64 = P.alloc<double>(h->m + 64);
+    h->t64 = P.alloc<double>(h->n + 64);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+void destroy_impl(rgdbek_ctx *h) {
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  for (auto &g : h->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  h->graphs.clear();
+  h->pool.release();
+  if (h->hctrl) (void)hipHostFree(h->hctrl);
+  h->hctrl = nullptr;
+  if (h->st && h->own_stream) (void)hipStreamDestroy(h->st);
+  h->st = nullptr;
+}
+
+template <typename F>
+rgdbek_status guarded(rgdbek_ctx *h, F &&f) {
+  try {
+    return f();
+  } catch (const ApiError &e) {
+    set_err(h, e.msg);
+    return e.s;
+  } catch (const HipError &e) {
+    set_err(h, std::string("HIP error ") + hipGetErrorString(e.e) + " in " +
+                   e.what);
+    return RGDBEK_ERR_DEVICE;
+  } catch (const std::bad_alloc &) {
+    set_err(h, "host allocation failed");
+    return RGDBEK_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    set_err(h, "unexpected internal error");
+    return RGDBEK_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+
+// ============================================================ C-ABI
+extern "C" {
+
+rgdbek_status rgdbek_params_default(rgdbek_params *p) {
+  if (!p) return RGDBEK_ERR_INVALID_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->eta = 0.5;
+  p->tol = 1e-8;
+  p->stop = RGDBEK_STOP_ERR_REF;
+  p->precision = RGDBEK_PREC_FP64;
+  p->max_iter = 10000;
+  p->seed = 0;
+  p->flags = RGDBEK_FLAG_GRAPH;
+  return RGDBEK_OK;
+}
+
+rgdbek_status rgdbek_create(const rgdbek_matrix *A, const rgdbek_params *p,
+                            void *stream, rgdbek_handle *out) {
+  g_global_err.clear();
+  if (!out) { set_err(nullptr, "out is NULL"); return RGDBEK_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (!A || !p) { set_err(nullptr, "A or p is NULL"); return RGDBEK_ERR_INVALID_ARG; }
+  if (A->m <= 0 || A->n <= 0 || A->m > INT32_MAX || A->n > INT32_MAX) {
+    set_err(nullptr, "m and n must lie in [1, 2^31)");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (A->layout != RGDBEK_DENSE_ROW_MAJOR && A->layout != RGDBEK_CSR) {
+    set_err(nullptr, "unknown layout");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (A->value_type != RGDBEK_F64 && A->value_type != RGDBEK_F32) {
+    set_err(nullptr, "unknown value type");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (!A->values) { set_err(nullptr, "values is NULL"); return RGDBEK_ERR_INVALID_ARG; }
+  if (A->layout == RGDBEK_CSR) {
+    if (!A->row_ptr || (!A->col_idx && A->nnz > 0) || A->nnz < 0 ||
+        A->nnz > INT32_MAX) {
+      set_err(nullptr, "CSR needs row_ptr, col_idx and 0 <= nnz < 2^31");
+      return RGDBEK_ERR_INVALID_ARG;
+    }
+  } else if (A->row_ptr || A->col_idx) {
+    set_err(nullptr, "dense layout takes no row_ptr/col_idx");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  rgdbek_ctx *h = new (std::nothrow) rgdbek_ctx();
+  if (!h) { set_err(nullptr, "host allocation failed"); return RGDBEK_ERR_OUT_OF_MEMORY; }
+  h->m = A->m;
+  h->n = A->n;
+  h->dense = A->layout == RGDBEK_DENSE_ROW_MAJOR;
+  h->nnz = h->dense ? A->m * A->n : A->nnz;
+  h->p = *p;
+  h->user_st = (hipStream_t)stream;
+  rgdbek_status s = guarded(nullptr, [&]() {
+    validate_params(p, h->m, h->n, &h->kc, &h->kr);
+    // HIP graphs cannot be captured on the legacy default stream: a NULL
+    // stream gets a private non-blocking stream (default priority)
+    if (h->user_st) {
+      h->st = h->user_st;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    create_impl(h, A);
+    return RGDBEK_OK;
+  });
+  if (s != RGDBEK_OK) {
+    destroy_impl(h);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return RGDBEK_OK;
+}
+
+rgdbek_status rgdbek_solve(rgdbek_handle h, const void *b, void *x,
+                           const void *x_ref, rgdbek_info *info) {
+  if (!h) return RGDBEK_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!b || !x) { set_err(h, "b and x are required"); return RGDBEK_ERR_INVALID_ARG; }
+  if (h->p.stop == RGDBEK_STOP_ERR_REF && !x_ref) {
+    set_err(h, "STOP_ERR_REF needs x_ref");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  return guarded(h, [&]() {
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    if (h->p.precision == RGDBEK_PREC_MIXED_F32)
+      return solve_mixed(h, (const double *)b, (double *)x,
+                         (const double *)x_ref, info);
+    return solve64(h, h->e64, 0, 0, h->p.stop, (const double *)b, (double *)x,
+                   nullptr, 0, false, (const double *)x_ref, info);
+  });
+}
+
+rgdbek_status rgdbek_solve_resume(rgdbek_handle h, const void *b, void *x,
+                                  void *z, int64_t it0, const void *x_ref,
+                                  rgdbek_info *info) {
+  if (!h) return RGDBEK_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!b || !x || !z || it0 < 0) {
+    set_err(h, "b, x, z are required and it0 must be >= 0");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (h->p.stop == RGDBEK_STOP_ERR_REF && !x_ref) {
+    set_err(h, "STOP_ERR_REF needs x_ref");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (h->p.precision != RGDBEK_PREC_FP64) {
+    set_err(h, "resume is defined for the FP64 form");
+    return RGDBEK_ERR_UNSUPPORTED;
+  }
+  return guarded(h, [&]() {
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    return solve64(h, h->e64, 0, 0, h->p.stop, (const double *)b, (double *)x,
+                   (double *)z, it0, true, (const double *)x_ref, info);
+  });
+}
+
+rgdbek_status rgdbek_get_z(rgdbek_handle h, void *z) {
+  if (!h || !z) return RGDBEK_ERR_INVALID_ARG;
+  return guarded(h, [&]() {
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    HIPCHK(hipMemcpyAsync(z, h->e64.z, sizeof(double) * h->m,
+                          hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return RGDBEK_OK;
+  });
+}
+
+rgdbek_status rgdbek_solve_adjoint(rgdbek_handle h, const void *g, void *w,
+                                   rgdbek_info *info) {
+  if (!h) return RGDBEK_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!g || !w) { set_err(h, "g and w are required"); return RGDBEK_ERR_INVALID_ARG; }
+  return guarded(h, [&]() {
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    if (!h->e64t.ready) build_engine<double>(h, h->e64t, true);
+    int stop = h->p.stop == RGDBEK_STOP_ERR_REF ? RGDBEK_STOP_RES_EXT : h->p.stop;
+    return solve64(h, h->e64t, 1, 1, stop, (const double *)g, (double *)w,
+                   nullptr, 0, false, nullptr, info);
+  });
+}
+
+rgdbek_status rgdbek_grad_pattern(rgdbek_handle h, const void *r,
+                                  const void *lam, const void *w,
+                                  const void *x, void *dA_values) {
+  if (!h) return RGDBEK_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!w || !x || !dA_values || (lam && !r)) {
+    set_err(h, "w, x and dA_values are required (and r with lam)");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  return guarded(h, [&]() {
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    if (h->dense)
+      launch_grad_pattern_dense(h->m, h->n, (const double *)r,
+                                (const double *)lam, (const double *)w,
+                                (const double *)x, (double *)dA_values, h->st);
+    else
+      launch_grad_pattern_csr(h->m, h->csr_ptr, h->csr_idx, (const double *)r,
+                              (const double *)lam, (const double *)w,
+                              (const double *)x, (double *)dA_values, h->st);
+    HIPCHK(hipStreamSynchronize(h->st));
+    return RGDBEK_OK;
+  });
+}
+
+rgdbek_status rgdbek_apply(rgdbek_handle h, int32_t precision, const void *x,
+                           const void *z, void *ax, void *atz) {
+  if (!h) return RGDBEK_ERR_INVALID_ARG;
+  h->err.clear();
+  if (!x || !z || !ax || !atz) {
+    set_err(h, "x, z, ax and atz are required");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (precision != RGDBEK_F64 && precision != RGDBEK_F32) {
+    set_err(h, "precision must be RGDBEK_F64 or RGDBEK_F32");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (precision == RGDBEK_F32 && !h->e32.ready) {
+    set_err(h, "FP32 storage exists only for a MIXED_F32 handle");
+    return RGDBEK_ERR_UNSUPPORTED;
+  }
+  return guarded(h, [&]() {
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    ctrl_reset(h, 0, 1, RGDBEK_STOP_NONE, 0.0);
+    auto run = [&](auto &e, auto *xv, auto *zv, auto *axv, auto *atzv) {
+      using T = typename std::remove_pointer<decltype(axv)>::type;
+      if (e.dense) {
+        // the fused pass needs x padded to the leading dimension: stage it
+        HIPCHK(hipMemcpyAsync(e.x, xv, sizeof(T) * e.n, hipMemcpyDeviceToDevice, h->st));
+        launch_dense_fused<T>(e.arm, e.x, zv, e.dw, nullptr, e.kappa, atzv,
+                              e.eps_z, axv, h->ctrl, 0, h->st);
+      } else {
+        SegArgs<T> a;
+        a.v = xv; a.out = axv;
+        launch_segdot<T>(e.csr, EPI_STORE, a, h->ctrl, 0, h->st);
+        SegArgs<T> c;
+        c.v = zv; c.out = atzv;
+        launch_segdot<T>(e.csc, EPI_STORE, c, h->ctrl, 0, h->st);
+      }
+    };
+    if (precision == RGDBEK_F64)
+      run(h->e64, (const double *)x, (const double *)z, (double *)ax, (double *)atz);
+    else
+      run(h->e32, (const float *)x, (const float *)z, (float *)ax, (float *)atz);
+    HIPCHK(hipGetLastError());
+    return RGDBEK_OK;
+  });
+}
+
+rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
+                            double floor, uint64_t seed, uint64_t key1,
+                            uint64_t it,
+                            uint32_t phase, uint32_t sys, int32_t *out_idx,
+                            int64_t *out_count, void *stream) {
+  g_global_err.clear();
+  if (!eps || !out_idx || !out_count || d <= 0 || k < 0 || d > INT32_MAX) {
+    set_err(nullptr, "eps, out_idx, out_count required; 0 < d < 2^31, k >= 0");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  Pool P;
+  rgdbek_status s = guarded(nullptr, [&]() {
+    SelectScratch sc;
+    sc.keys = P.alloc<uint64_t>(d + 64, false);
+    sc.hist = P.alloc<unsigned>(2048);
+    sc.ckey = P.alloc<uint64_t>(4096);
+    sc.cidx = P.alloc<int64_t>(4096);
+    sc.blk = P.alloc<int32_t>(select_scratch_blocks(d) + 64);
+    Ctrl *c = P.alloc<Ctrl>(1);
+    launch_fill_ctrl_it(c, (int64_t)it, st);
+    launch_select<double>(eps, d, k, floor, seed, key1, phase, sys, 0, sc,
+                          out_idx, c, 0, st);
+    Ctrl hc;
+    HIPCHK(hipMemcpyAsync(&hc, c, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    *out_count = hc.sel_count[0];
+    if (hc.numeric)
+      throw ApiError{RGDBEK_ERR_NUMERIC, "weights must be finite and >= 0"};
+    return RGDBEK_OK;
+  });
+  P.release();
+  return s;
+}
+
+rgdbek_status rgdbek_destroy(rgdbek_handle h) {
+  if (!h) return RGDBEK_OK;
+  destroy_impl(h);
+  delete h;
+  return RGDBEK_OK;
+}
+
+const char *rgdbek_status_string(rgdbek_status s) {
+  switch (s) {
+    case RGDBEK_OK: return "ok";
+    case RGDBEK_ERR_INVALID_ARG: return "invalid argument";
+    case RGDBEK_ERR_NUMERIC: return "numeric error (NaN/Inf)";
+    case RGDBEK_ERR_NOT_CONVERGED: return "not converged within max_iter";
+    case RGDBEK_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case RGDBEK_ERR_DEVICE: return "device (HIP) error";
+    case RGDBEK_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char *rgdbek_last_error(rgdbek_handle h) {
+  return h ? h->err.c_str() : g_global_err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,648 @@
+// Block selection of RGDBEK on gfx950 (Section 2: column/row set
+// probabilities and the "select n*eta columns / m*eta rows" steps of
+// Algorithm 1).
+//
+// Draw k distinct indices without replacement with probability proportional
+// to the residual weights eps, via exponential clocks (Efraimidis & Spirakis,
+// IPL 2006): the block is the k smallest keys E_j / eps_j, E_j = -ln(u_j),
+// ties ordered by index, returned in ascending index order.  u_j comes from
+// Philox4x64-10 (Salmon et al., SC'11) with counter (j>>2, it, phase, sys),
+// key (seed, key1), word j&3, mapped to (2*(w>>12)+1)*2^-53.
+//
+// Bit-exactness: this file is compiled with -ffp-contract=off; the logarithm
+// uses only correctly rounded +,-,*,/ in a fixed order (atanh series on
+// [sqrt(1/2), sqrt(2))), and the key is one correctly rounded division.
+//
+// Weights below floor * max(eps) count as zero (a weight that a projection
+// has just annihilated is zero up to rounding); the largest weight comes from
+// a max-reduction that runs before the keys.
+//
+// Pipeline (both forms end in the same predicate
+//   take j  <=>  key_j < lo  ||  (key_j == tkey && j <= tidx)):
+//  small d (one workgroup): keys -> 8 radix passes of 8 bits with LDS
+//    histograms -> ordered tie resolution -> ballot/popcount compaction;
+//  large d (multi-workgroup): keys + histogram of bits 62..52 -> scan ->
+//    histogram of bits 51..41 -> scan -> gather the few candidates left ->
+//    one-workgroup bitonic sort -> per-chunk counts -> ordered compaction.
+#include "common.h"
+#include "kernels.h"
+
+namespace rg {
+
+// ---------------------------------------------------------------- Philox
+struct P4 { uint64_t v[4]; };
+
+__device__ __forceinline__ P4 philox4x64_10(uint64_t c0, uint64_t c1,
+                                            uint64_t c2, uint64_t c3,
+                                            uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+    const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  P4 o; o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+  return o;
+}
+
+// ---------------------------------------------------------------- ln
+// ln(u) for u in [2^-53, 1): frexp by exponent bits (u is normal), reduce the
+// mantissa to [sqrt(1/2), sqrt(2)), s = (f-1)/(f+1), t = s*s,
+// ln f = 2s + 2s*t*P(t) with P(t) = sum_{i=1..11} t^(i-1)/(2i+1) by Horner,
+// ln u = e*ln2 + ln f.  Coefficients are the correctly rounded quotients.
+__device__ __forceinline__ double ln_unit(double u) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(u);
+  int e = (int)((bits >> 52) & 0x7ff) - 1022;
+  double f = __longlong_as_double(
+      (long long)((bits & 0x800FFFFFFFFFFFFFull) | (1022ull << 52)));
+  if (f < 0.7071067811865476) { f = f * 2.0; e -= 1; }
+  const double s = (f - 1.0) / (f + 1.0);
+  const double t = s * s;
+  double p = 1.0 / 23.0;
+  p = p * t; p = p + 1.0 / 21.0;
+  p = p * t; p = p + 1.0 / 19.0;
+  p = p * t; p = p + 1.0 / 17.0;
+  p = p * t; p = p + 1.0 / 15.0;
+  p = p * t; p = p + 1.0 / 13.0;
+  p = p * t; p = p + 1.0 / 11.0;
+  p = p * t; p = p + 1.0 / 9.0;
+  p = p * t; p = p + 1.0 / 7.0;
+  p = p * t; p = p + 1.0 / 5.0;
+  p = p * t; p = p + 1.0 / 3.0;
+  const double s2 = s + s;
+  const double tp = t * p;
+  const double lnf = s2 + s2 * tp;
+  const double el = (double)e * 0.6931471805599453;
+  return el + lnf;
+}
+
+__device__ __forceinline__ double unit_from_word(uint64_t w) {
+  return (double)((w >> 12) * 2ull + 1ull) * 0x1p-53;
+}
+
+constexpr uint64_t SENT = ~0ull;   // key of a zero weight: never selected
+
+// key of index j with weight e (already promoted to FP64); sets *bad on a
+// NaN, negative or infinite weight.  Weights not above `cut` (the relative
+// floor times the largest weight) count as zero.
+__device__ __forceinline__ uint64_t make_key(double e, uint64_t w, double cut,
+                                             int *bad) {
+  if (!(e >= 0.0) || e > 1.7976931348623157e308) { *bad = 1; return SENT; }
+  if (!(e > cut)) return SENT;
+  const double E = -ln_unit(unit_from_word(w));
+  const double k = E / e;
+  return (uint64_t)__double_as_longlong(k);
+}
+
+__device__ __forceinline__ bool take(uint64_t key, int64_t j, uint64_t lo,
+                                     uint64_t tkey, int64_t tidx) {
+  return key < lo || (key == tkey && j <= tidx);
+}
+
+// Ordered compaction of one workgroup-sized chunk [base, base+NT) with the
+// predicate above: ballot + popcount inside waves, wave totals via LDS.
+// Returns the number taken in the chunk; writes at out[offset + rank].
+template <int NT>
+__device__ __forceinline__ int64_t compact_chunk(const uint64_t *keys,
+                                                 int64_t base, int64_t d,
+                                                 uint64_t lo, uint64_t tkey,
+                                                 int64_t tidx, int32_t *out,
+                                                 int64_t offset, int *wtot) {
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const int64_t j = base + threadIdx.x;
+  bool f = false;
+  if (j < d) f = take(keys[j], j, lo, tkey, tidx);
+  const uint64_t mask = __ballot(f);
+  const int before = __popcll(mask & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (lane == 0) wtot[wv] = __popcll(mask);
+  __syncthreads();
+  int wbase = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < NT / WAVE; ++i) {
+    if (i < wv) wbase += wtot[i];
+    total += wtot[i];
+  }
+  if (f) out[offset + wbase + before] = (int32_t)j;
+  return total;
+}
+
+// ------------------------------------------------ one-workgroup selection
+// keys: scratch of d entries.  Writes out[0..count) and ctrl->sel_count[ph].
+template <typename T>
+__global__ void __launch_bounds__(1024)
+sel_small(const T *__restrict__ eps, int64_t d, int64_t k, double floor,
+          uint64_t seed, uint64_t key1, int ph, uint32_t phase, uint32_t sys,
+          uint64_t *__restrict__ keys, int32_t *__restrict__ out, Ctrl *ctrl,
+          int respect_done) {
+  constexpr int NT = 1024;
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ unsigned hist[256];
+  __shared__ int64_t sh64[NT / WAVE];
+  __shared__ int wtot[NT / WAVE];
+  __shared__ uint64_t s_prefix;
+  __shared__ int64_t s_krem, s_tidx;
+  __shared__ int s_done;
+  __shared__ double shmax[NT / WAVE];
+  const uint64_t it = (uint64_t)ctrl->it;
+  double mx = 0.0;
+  for (int64_t j = threadIdx.x; j < d; j += NT) {
+    const double e = (double)eps[j];
+    mx = e > mx ? e : mx;
+  }
+  mx = wave_max(mx);
+  if ((threadIdx.x & (WAVE - 1)) == 0) shmax[threadIdx.x / WAVE] = mx;
+  __syncthreads();
+  mx = 0.0;
+  for (int i = 0; i < NT / WAVE; ++i) mx = shmax[i] > mx ? shmax[i] : mx;
+  const double cut = floor > 0.0 ? floor * mx : 0.0;
+  int bad = 0;
+  int64_t pos = 0;
+  for (int64_t g = threadIdx.x; g * 4 < d; g += NT) {
+    const P4 r = philox4x64_10((uint64_t)g, it, phase, sys, seed, key1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = g * 4 + q;
+      if (j < d) {
+        const uint64_t kk = make_key((double)eps[j], r.v[q], cut, &bad);
+        keys[j] = kk;
+        pos += (kk != SENT);
+      }
+    }
+  }
+  if (bad) atomicOr(&ctrl->numeric, 1);
+  pos = block_sum_i64<NT>(pos, sh64);
+  __syncthreads();   // keys visible to the whole workgroup
+
+  uint64_t lo, tkey;
+  int64_t tidx;
+  if (pos <= k) {
+    lo = SENT; tkey = SENT; tidx = -1;
+  } else {
+    // MSB-first radix select of the k-th smallest key, 8 bits per pass.
+    if (threadIdx.x == 0) { s_prefix = 0; s_krem = k; s_done = 0; }
+    int shift = 64;
+    __syncthreads();
+    uint64_t bound_lo = 0;
+    bool resolved_bucket = false;
+    for (int pass = 0; pass < 8; ++pass) {
+      const int nshift = shift - 8;
+      for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+      __syncthreads();
+      const uint64_t pre = s_prefix;
+      for (int64_t j = threadIdx.x; j < d; j += NT) {
+        const uint64_t kk = keys[j];
+        if (kk == SENT) continue;
+        if (shift < 64 && (kk >> shift) != pre) continue;
+        atomicAdd(&hist[(kk >> nshift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int64_t kr = s_krem, acc = 0;
+        int b = 0;
+        for (; b < 256; ++b) {
+          if (acc + (int64_t)hist[b] >= kr) break;
+          acc += hist[b];
+        }
+        s_prefix = (pre << 8) | (uint64_t)b;
+        s_krem = kr - acc;
+        s_done = ((int64_t)hist[b] == kr - acc) ? 1 : 0;
+      }
+      __syncthreads();
+      shift = nshift;
+      if (s_done) {
+        resolved_bucket = true;
+        bound_lo = (shift == 0) ? s_prefix + 1 : ((s_prefix + 1) << shift);
+        break;
+      }
+    }
+    if (resolved_bucket && !(shift == 0 && s_prefix == SENT)) {
+      lo = bound_lo; tkey = SENT; tidx = -1;
+    } else {
+      // all 64 bits resolved: take the first krem indices with key == prefix
+      tkey = s_prefix;
+      lo = tkey;
+      const int64_t krem = s_krem;
+      int64_t seen = 0;
+      if (threadIdx.x == 0) s_tidx = -1;
+      __syncthreads();
+      for (int64_t base = 0; base < d && seen < krem; base += NT) {
+        const int64_t j = base + threadIdx.x;
+        const bool f = (j < d) && keys[j] == tkey;
+        const uint64_t mask = __ballot(f);
+        const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+        __syncthreads();
+        if (lane == 0) wtot[wv] = __popcll(mask);
+        __syncthreads();
+        int64_t wb = 0, tot = 0;
+        for (int i = 0; i < NT / WAVE; ++i) {
+          if (i < wv) wb += wtot[i];
+          tot += wtot[i];
+        }
+        const int64_t rank = seen + wb + __popcll(mask & ((1ull << lane) - 1ull));
+        if (f && rank == krem - 1) s_tidx = j;
+        seen += tot;
+        __syncthreads();
+      }
+      tidx = s_tidx;
+    }
+  }
+  // ordered compaction
+  int64_t off = 0;
+  for (int64_t base = 0; base < d; base += NT)
+    off += compact_chunk<NT>(keys, base, d, lo, tkey, tidx, out, off, wtot);
+  if (threadIdx.x == 0) ctrl->sel_count[ph] = off;
+}
+
+// ------------------------------------------------ multi-workgroup selection
+constexpr int SEL_NT = 1024;
+constexpr int SEL_CHUNK = 4 * SEL_NT;       // indices per workgroup
+constexpr int SEL_BITS = 11;
+constexpr int SEL_BINS = 1 << SEL_BITS;
+constexpr int SEL_CAND = 4096;              // candidates sorted in LDS
+
+// mode values stored in ctrl->sel_mode
+enum { M_RADIX = 0, M_ALL = 1, M_RESOLVED = 2, M_GATHER = 3, M_FALLBACK = 4,
+       M_EXACT = 5 };
+
+// largest non-negative finite weight, as its (order-preserving) bit pattern
+template <typename T>
+__global__ void __launch_bounds__(SEL_NT)
+sel_max(const T *__restrict__ eps, int64_t d, Ctrl *ctrl, int ph,
+        int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[SEL_NT / WAVE];
+  const int64_t base = (int64_t)blockIdx.x * SEL_CHUNK;
+  double mx = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = base + q * SEL_NT + threadIdx.x;
+    if (j < d) {
+      const double e = (double)eps[j];
+      if (e <= 1.7976931348623157e308) mx = e > mx ? e : mx;
+    }
+  }
+  mx = wave_max(mx);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < SEL_NT / WAVE; ++i) mx = sh[i] > mx ? sh[i] : mx;
+    if (mx > 0.0)
+      atomicMax((unsigned long long *)&ctrl->sel_maxbits[ph],
+                (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SEL_NT)
+sel_keys_hist(const T *__restrict__ eps, int64_t d, double floor,
+              uint64_t seed, uint64_t key1, uint32_t phase, uint32_t sys,
+              uint64_t *__restrict__ keys, unsigned *__restrict__ hist,
+              Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ unsigned h[SEL_BINS];
+  __shared__ int64_t sh64[SEL_NT / WAVE];
+  for (int i = threadIdx.x; i < SEL_BINS; i += SEL_NT) h[i] = 0;
+  __syncthreads();
+  const uint64_t it = (uint64_t)ctrl->it;
+  const double mx = __longlong_as_double((long long)ctrl->sel_maxbits[ph]);
+  const double cut = floor > 0.0 ? floor * mx : 0.0;
+  const int64_t g = (int64_t)blockIdx.x * SEL_NT + threadIdx.x;
+  int bad = 0;
+  int64_t pos = 0;
+  if (g * 4 < d) {
+    const P4 r = philox4x64_10((uint64_t)g, it, phase, sys, seed, key1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = g * 4 + q;
+      if (j < d) {
+        const uint64_t kk = make_key((double)eps[j], r.v[q], cut, &bad);
+        keys[j] = kk;
+        if (kk != SENT) {
+          ++pos;
+          atomicAdd(&h[(kk >> 52) & (SEL_BINS - 1)], 1u);
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(&ctrl->numeric, 1);
+  pos = block_sum_i64<SEL_NT>(pos, sh64);
+  if (threadIdx.x == 0 && pos) atomicAdd((unsigned long long *)&ctrl->sel_pos[ph],
+                                         (unsigned long long)pos);
+  __syncthreads();
+  for (int i = threadIdx.x; i < SEL_BINS; i += SEL_NT)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// One workgroup: pick the bucket holding rank krem, clear the histogram.
+__global__ void __launch_bounds__(SEL_NT)
+sel_scan(unsigned *__restrict__ hist, int64_t k, Ctrl *ctrl, int ph,
+         int first, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ unsigned h[SEL_BINS];
+  const int mode = first ? M_RADIX : ctrl->sel_mode[ph];
+  for (int i = threadIdx.x; i < SEL_BINS; i += SEL_NT) {
+    h[i] = hist[i];
+    hist[i] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (first) {
+    const int64_t pos = ctrl->sel_pos[ph];
+    ctrl->sel_pos[ph] = 0;
+    ctrl->sel_maxbits[ph] = 0;
+    if (pos <= k) {
+      ctrl->sel_mode[ph] = M_ALL;
+      ctrl->sel_tkey[ph] = SENT; ctrl->sel_tidx[ph] = -1;
+      ctrl->sel_prefix[ph] = SENT; ctrl->sel_shift[ph] = 0;
+      return;
+    }
+    ctrl->sel_krem[ph] = k;
+    ctrl->sel_prefix[ph] = 0;
+    ctrl->sel_shift[ph] = 63;
+  } else if (mode != M_RADIX) {
+    return;
+  }
+  const int64_t kr = ctrl->sel_krem[ph];
+  int64_t acc = 0;
+  int b = 0;
+  for (; b < SEL_BINS; ++b) {
+    if (acc + (int64_t)h[b] >= kr) break;
+    acc += h[b];
+  }
+  const int shift = ctrl->sel_shift[ph] - SEL_BITS;   // 52, then 41
+  const uint64_t prefix = (ctrl->sel_prefix[ph] << SEL_BITS) | (uint64_t)b;
+  const int64_t krem = kr - acc;
+  const int64_t cnt = h[b];
+  ctrl->sel_prefix[ph] = prefix;
+  ctrl->sel_shift[ph] = shift;
+  ctrl->sel_krem[ph] = krem;
+  if (cnt == krem) {
+    ctrl->sel_mode[ph] = M_RESOLVED;
+    ctrl->sel_prefix[ph] = (prefix + 1) << shift;   // lo bound
+  } else if (!first) {
+    ctrl->sel_mode[ph] = (cnt <= SEL_CAND) ? M_GATHER : M_FALLBACK;
+    ctrl->sel_cand[ph] = 0;
+  } else {
+    ctrl->sel_mode[ph] = M_RADIX;
+  }
+}
+
+__global__ void __launch_bounds__(SEL_NT)
+sel_hist(const uint64_t *__restrict__ keys, int64_t d,
+         unsigned *__restrict__ hist, Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ctrl->sel_mode[ph] != M_RADIX) return;
+  __shared__ unsigned h[SEL_BINS];
+  for (int i = threadIdx.x; i < SEL_BINS; i += SEL_NT) h[i] = 0;
+  __syncthreads();
+  const int shift = ctrl->sel_shift[ph];            // 52
+  const uint64_t pre = ctrl->sel_prefix[ph];
+  const int64_t base = (int64_t)blockIdx.x * SEL_CHUNK;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = base + q * SEL_NT + threadIdx.x;
+    if (j < d) {
+      const uint64_t kk = keys[j];
+      if (kk != SENT && (kk >> shift) == pre)
+        atomicAdd(&h[(kk >> (shift - SEL_BITS)) & (SEL_BINS - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < SEL_BINS; i += SEL_NT)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+__global__ void __launch_bounds__(SEL_NT)
+sel_gather(const uint64_t *__restrict__ keys, int64_t d,
+           uint64_t *__restrict__ ckey, int64_t *__restrict__ cidx,
+           Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ctrl->sel_mode[ph] != M_GATHER) return;
+  const int shift = ctrl->sel_shift[ph];            // 41
+  const uint64_t pre = ctrl->sel_prefix[ph];
+  const int64_t base = (int64_t)blockIdx.x * SEL_CHUNK;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = base + q * SEL_NT + threadIdx.x;
+    if (j < d) {
+      const uint64_t kk = keys[j];
+      if (kk != SENT && (kk >> shift) == pre) {
+        const unsigned long long slot =
+            atomicAdd((unsigned long long *)&ctrl->sel_cand[ph], 1ull);
+        if (slot < (unsigned long long)SEL_CAND) { ckey[slot] = kk; cidx[slot] = j; }
+      }
+    }
+  }
+}
+
+// One workgroup: find (tkey, tidx), the krem-th smallest candidate pair.
+__global__ void __launch_bounds__(SEL_NT)
+sel_resolve(const uint64_t *__restrict__ keys, int64_t d,
+            const uint64_t *__restrict__ ckey, const int64_t *__restrict__ cidx,
+            Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int mode = ctrl->sel_mode[ph];
+  if (mode == M_ALL) {
+    if (threadIdx.x == 0) { ctrl->sel_prefix[ph] = SENT; }
+    return;
+  }
+  if (mode == M_RESOLVED) {
+    if (threadIdx.x == 0) { ctrl->sel_tkey[ph] = SENT; ctrl->sel_tidx[ph] = -1; }
+    return;
+  }
+  __shared__ uint64_t sk[SEL_CAND];
+  __shared__ int64_t si[SEL_CAND];
+  __shared__ unsigned h[256];
+  __shared__ uint64_t s_pre;
+  __shared__ int64_t s_krem, s_tidx;
+  __shared__ int wtot[SEL_NT / WAVE];
+  if (mode == M_GATHER) {
+    const int64_t nc = ctrl->sel_cand[ph];
+    for (int i = threadIdx.x; i < SEL_CAND; i += SEL_NT) {
+      if (i < nc) { sk[i] = ckey[i]; si[i] = cidx[i]; }
+      else { sk[i] = SENT; si[i] = INT64_MAX; }
+    }
+    __syncthreads();
+    // bitonic sort of (key, idx) pairs ascending
+    for (int size = 2; size <= SEL_CAND; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < SEL_CAND; i += SEL_NT) {
+          const int p = i ^ stride;
+          if (p > i) {
+            const bool up = ((i & size) == 0);
+            const uint64_t a = sk[i], b = sk[p];
+            const int64_t ai = si[i], bi = si[p];
+            const bool gt = (a > b) || (a == b && ai > bi);
+            if (gt == up) { sk[i] = b; sk[p] = a; si[i] = bi; si[p] = ai; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (threadIdx.x == 0) {
+      const int64_t kr = ctrl->sel_krem[ph];
+      ctrl->sel_tkey[ph] = sk[kr - 1];
+      ctrl->sel_tidx[ph] = si[kr - 1];
+      ctrl->sel_prefix[ph] = sk[kr - 1];    // lo bound = tkey
+      ctrl->sel_mode[ph] = M_EXACT;
+    }
+    return;
+  }
+  // M_FALLBACK: finish the radix select over all keys with this workgroup
+  // (8-bit digits below the resolved prefix), then locate the tie index.
+  if (threadIdx.x == 0) {
+    s_pre = ctrl->sel_prefix[ph];
+    s_krem = ctrl->sel_krem[ph];
+  }
+  int shift = ctrl->sel_shift[ph];
+  __syncthreads();
+  while (shift > 0) {
+    const int step = shift >= 8 ? 8 : shift;
+    const int nshift = shift - step;
+    for (int i = threadIdx.x; i < 256; i += SEL_NT) h[i] = 0;
+    __syncthreads();
+    const uint64_t pre = s_pre;
+    for (int64_t j = threadIdx.x; j < d; j += SEL_NT) {
+      const uint64_t kk = keys[j];
+      if (kk != SENT && (kk >> shift) == pre)
+        atomicAdd(&h[(kk >> nshift) & ((1u << step) - 1u)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t kr = s_krem, acc = 0;
+      int b = 0;
+      for (; b < (1 << step); ++b) {
+        if (acc + (int64_t)h[b] >= kr) break;
+        acc += h[b];
+      }
+      s_pre = (pre << step) | (uint64_t)b;
+      s_krem = kr - acc;
+    }
+    __syncthreads();
+    shift = nshift;
+  }
+  const uint64_t tkey = s_pre;
+  const int64_t krem = s_krem;
+  int64_t seen = 0;
+  if (threadIdx.x == 0) s_tidx = -1;
+  __syncthreads();
+  for (int64_t base = 0; base < d && seen < krem; base += SEL_NT) {
+    const int64_t j = base + threadIdx.x;
+    const bool f = (j < d) && keys[j] == tkey;
+    const uint64_t mask = __ballot(f);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) wtot[wv] = __popcll(mask);
+    __syncthreads();
+    int64_t wb = 0, tot = 0;
+    for (int i = 0; i < SEL_NT / WAVE; ++i) {
+      if (i < wv) wb += wtot[i];
+      tot += wtot[i];
+    }
+    const int64_t rank = seen + wb + __popcll(mask & ((1ull << lane) - 1ull));
+    if (f && rank == krem - 1) s_tidx = j;
+    seen += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ctrl->sel_tkey[ph] = tkey;
+    ctrl->sel_tidx[ph] = s_tidx;
+    ctrl->sel_prefix[ph] = tkey;
+    ctrl->sel_mode[ph] = M_EXACT;
+  }
+}
+
+__global__ void __launch_bounds__(SEL_NT)
+sel_count(const uint64_t *__restrict__ keys, int64_t d,
+          int32_t *__restrict__ blk, Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ int64_t sh64[SEL_NT / WAVE];
+  const uint64_t lo = ctrl->sel_prefix[ph];
+  const uint64_t tkey = ctrl->sel_tkey[ph];
+  const int64_t tidx = ctrl->sel_tidx[ph];
+  const int64_t base = (int64_t)blockIdx.x * SEL_CHUNK;
+  int64_t c = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = base + q * SEL_NT + threadIdx.x;
+    if (j < d) c += take(keys[j], j, lo, tkey, tidx);
+  }
+  c = block_sum_i64<SEL_NT>(c, sh64);
+  if (threadIdx.x == 0) blk[blockIdx.x] = (int32_t)c;
+}
+
+__global__ void __launch_bounds__(SEL_NT)
+sel_write(const uint64_t *__restrict__ keys, int64_t d,
+          const int32_t *__restrict__ blk, int32_t *__restrict__ out,
+          Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ int64_t sh64[SEL_NT / WAVE];
+  __shared__ int wtot[SEL_NT / WAVE];
+  const uint64_t lo = ctrl->sel_prefix[ph];
+  const uint64_t tkey = ctrl->sel_tkey[ph];
+  const int64_t tidx = ctrl->sel_tidx[ph];
+  int64_t before = 0, total = 0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += SEL_NT) {
+    const int64_t v = blk[b];
+    total += v;
+    if (b < (int)blockIdx.x) before += v;
+  }
+  before = block_sum_i64<SEL_NT>(before, sh64);
+  total = block_sum_i64<SEL_NT>(total, sh64);
+  const int64_t base = (int64_t)blockIdx.x * SEL_CHUNK;
+  int64_t off = before;
+  for (int q = 0; q < 4; ++q)
+    off += compact_chunk<SEL_NT>(keys, base + q * SEL_NT, d, lo, tkey, tidx,
+                                 out, off, wtot);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->sel_count[ph] = total;
+}
+
+// ------------------------------------------------ launcher
+template <typename T>
+void launch_select(const T *eps, int64_t d, int64_t k, double floor,
+                   uint64_t seed, uint64_t key1, uint32_t phase, uint32_t sys,
+                   int ph, SelectScratch &s, int32_t *out, Ctrl *ctrl,
+                   int respect_done, hipStream_t st) {
+  if (d <= SEL_SMALL_MAX) {
+    hipLaunchKernelGGL(sel_small<T>, dim3(1), dim3(1024), 0, st, eps, d, k,
+                       floor, seed, key1, ph, phase, sys, s.keys, out, ctrl,
+                       respect_done);
+    return;
+  }
+  const int nb = (int)((d + SEL_CHUNK - 1) / SEL_CHUNK);
+  hipLaunchKernelGGL(sel_max<T>, dim3(nb), dim3(SEL_NT), 0, st, eps, d, ctrl,
+                     ph, respect_done);
+  hipLaunchKernelGGL(sel_keys_hist<T>, dim3(nb), dim3(SEL_NT), 0, st, eps, d,
+                     floor, seed, key1, phase, sys, s.keys, s.hist, ctrl, ph,
+                     respect_done);
+  hipLaunchKernelGGL(sel_scan, dim3(1), dim3(SEL_NT), 0, st, s.hist, k, ctrl,
+                     ph, 1, respect_done);
+  hipLaunchKernelGGL(sel_hist, dim3(nb), dim3(SEL_NT), 0, st, s.keys, d,
+                     s.hist, ctrl, ph, respect_done);
+  hipLaunchKernelGGL(sel_scan, dim3(1), dim3(SEL_NT), 0, st, s.hist, k, ctrl,
+                     ph, 0, respect_done);
+  hipLaunchKernelGGL(sel_gather, dim3(nb), dim3(SEL_NT), 0, st, s.keys, d,
+                     s.ckey, s.cidx, ctrl, ph, respect_done);
+  hipLaunchKernelGGL(sel_resolve, dim3(1), dim3(SEL_NT), 0, st, s.keys, d,
+                     s.ckey, s.cidx, ctrl, ph, respect_done);
+  hipLaunchKernelGGL(sel_count, dim3(nb), dim3(SEL_NT), 0, st, s.keys, d,
+                     s.blk, ctrl, ph, respect_done);
+  hipLaunchKernelGGL(sel_write, dim3(nb), dim3(SEL_NT), 0, st, s.keys, d,
+                     s.blk, out, ctrl, ph, respect_done);
+}
+
+template void launch_select<double>(const double *, int64_t, int64_t, double,
+                                    uint64_t, uint64_t, uint32_t, uint32_t,
+                                    int, SelectScratch &, int32_t *, Ctrl *,
+                                    int, hipStream_t);
+template void launch_select<float>(const float *, int64_t, int64_t, double,
+                                   uint64_t, uint64_t, uint32_t, uint32_t, int,
+                                   SelectScratch &, int32_t *, Ctrl *, int,
+                                   hipStream_t);
+
+int64_t select_scratch_blocks(int64_t d) {
+  return (d + SEL_CHUNK - 1) / SEL_CHUNK;
+}
+
+}  // namespace rg

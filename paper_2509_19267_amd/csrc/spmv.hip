@@ -1,0 +1,473 @@
+// Residual passes of RGDBEK on gfx950: the column residual A^T z and the row
+// residual b - z - A x with their weights (Section 2, the two residual
+// definitions of the randomized selection; Algorithm 1), plus the stop tests.
+//
+// Sparse A: row-split segment dots over CSR (rows) and CSC (columns, i.e.
+// the CSR of A^T), G lanes per segment (G from the mean segment length),
+// segments longer than a limit handed to a one-workgroup-per-segment kernel,
+// so power-law rows do not stall a wave.  Deterministic: fixed-order shuffle
+// reductions, no floating-point atomics.
+// Dense A: one read of the row-major matrix gives both A x_k and A^T z_k
+// (the row phase needs A x_k, not A x_{k+1}, so both products of an
+// iteration can share the pass); 16-byte loads, each wave streams whole row
+// segments, column partials meet in LDS, row-block partials are summed in a
+// fixed order by the finalise kernel.
+#include "common.h"
+#include "kernels.h"
+
+namespace rg {
+
+constexpr int SEG_NT = 256;
+
+template <typename T>
+__device__ __forceinline__ void seg_epilogue(int epi, const SegArgs<T> &a,
+                                             int64_t s, int64_t slot, T acc,
+                                             double &pb, double &pr) {
+  if (epi == EPI_STORE) {
+    a.out[s] = acc;
+  } else if (epi == EPI_LIST_STORE) {
+    a.out[slot] = acc;
+  } else if (epi == EPI_COLRES) {
+    T g = acc;
+    if (a.off) g += a.off[s];
+    a.g[s] = g;
+    const double nr = a.nrm[s];
+    a.eps[s] = nr > 0.0 ? (T)((double)g * (double)g / nr) : (T)0;
+  } else {  // EPI_ROWRES
+    const T bb = a.b[s];
+    const T r = bb - a.z[s] - acc;
+    a.r[s] = r;
+    const double nr = a.nrm[s];
+    a.eps[s] = nr > 0.0 ? (T)((double)r * (double)r / nr) : (T)0;
+    const double bq = (double)bb - (double)acc;
+    pb += bq * bq;
+    pr += (double)r * (double)r;
+  }
+}
+
+template <typename T, int G, int EPI>
+__global__ void __launch_bounds__(SEG_NT)
+segdot_kernel(Csr<T> A, SegArgs<T> a, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  constexpr int SPB = SEG_NT / G;
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t slot = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  const bool listed = (a.list != nullptr);
+  const int64_t nseg = listed ? *a.count_dev : A.rows;
+  bool active = slot < nseg;
+  int64_t s = 0;
+  T acc = (T)0;
+  if (active) {
+    s = listed ? (int64_t)a.list[slot] : slot;
+    const int64_t e0 = A.ptr[s], e1 = A.ptr[s + 1];
+    if (!listed && A.long_limit > 0 && e1 - e0 > A.long_limit) {
+      active = false;   // handled by segdot_long
+    } else {
+      for (int64_t e = e0 + lg; e < e1; e += G)
+        acc += A.val[e] * a.v[A.idx[e]];
+    }
+  }
+  acc = group_sum<G>(acc);
+  double pb = 0.0, pr = 0.0;
+  if (active && lg == 0) seg_epilogue<T>(EPI, a, s, slot, acc, pb, pr);
+  if (EPI == EPI_ROWRES) {
+    __shared__ double sh[SEG_NT / WAVE];
+    pb = block_sum<SEG_NT>(pb, sh);
+    pr = block_sum<SEG_NT>(pr, sh);
+    if (threadIdx.x == 0) {
+      a.part[2 * blockIdx.x] = pb;
+      a.part[2 * blockIdx.x + 1] = pr;
+    }
+  }
+}
+
+// one workgroup per long segment (from A.longs)
+template <typename T, int EPI>
+__global__ void __launch_bounds__(SEG_NT)
+segdot_long(Csr<T> A, SegArgs<T> a, int64_t part_base, Ctrl *ctrl,
+            int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[SEG_NT / WAVE];
+  const int64_t s = A.longs[blockIdx.x];
+  const int64_t e0 = A.ptr[s], e1 = A.ptr[s + 1];
+  T acc = (T)0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += SEG_NT)
+    acc += A.val[e] * a.v[A.idx[e]];
+  const double tot = block_sum<SEG_NT>((double)acc, sh);
+  double pb = 0.0, pr = 0.0;
+  if (threadIdx.x == 0) seg_epilogue<T>(EPI, a, s, s, (T)tot, pb, pr);
+  if (EPI == EPI_ROWRES && threadIdx.x == 0) {
+    a.part[2 * (part_base + blockIdx.x)] = pb;
+    a.part[2 * (part_base + blockIdx.x) + 1] = pr;
+  }
+}
+
+template <typename T, int EPI>
+static int segdot_dispatch(const Csr<T> &A, const SegArgs<T> &a, Ctrl *ctrl,
+                           int respect_done, hipStream_t st) {
+  const int64_t nseg = a.list ? a.list_cap : A.rows;
+  const int G = A.group;
+  const int spb = SEG_NT / G;
+  const int nb = (int)((nseg + spb - 1) / spb);
+  int nparts = 0;
+  if (nb > 0) {
+    switch (G) {
+#define RG_SEG(GG)                                                          \
+  case GG:                                                                  \
+    hipLaunchKernelGGL((segdot_kernel<T, GG, EPI>), dim3(nb), dim3(SEG_NT), \
+                       0, st, A, a, ctrl, respect_done);                    \
+    break;
+      RG_SEG(1) RG_SEG(2) RG_SEG(4) RG_SEG(8) RG_SEG(16) RG_SEG(32) RG_SEG(64)
+#undef RG_SEG
+      default: break;
+    }
+    nparts = nb;
+  }
+  if (!a.list && A.nlong > 0) {
+    hipLaunchKernelGGL((segdot_long<T, EPI>), dim3((unsigned)A.nlong),
+                       dim3(SEG_NT), 0, st, A, a, (int64_t)nparts, ctrl,
+                       respect_done);
+    nparts += (int)A.nlong;
+  }
+  return nparts;
+}
+
+template <typename T>
+int launch_segdot(const Csr<T> &A, int epi, const SegArgs<T> &a, Ctrl *ctrl,
+                  int respect_done, hipStream_t st) {
+  switch (epi) {
+    case EPI_STORE:
+      return segdot_dispatch<T, EPI_STORE>(A, a, ctrl, respect_done, st);
+    case EPI_COLRES:
+      return segdot_dispatch<T, EPI_COLRES>(A, a, ctrl, respect_done, st);
+    case EPI_ROWRES:
+      return segdot_dispatch<T, EPI_ROWRES>(A, a, ctrl, respect_done, st);
+    default:
+      return segdot_dispatch<T, EPI_LIST_STORE>(A, a, ctrl, respect_done, st);
+  }
+}
+template int launch_segdot<double>(const Csr<double> &, int,
+                                   const SegArgs<double> &, Ctrl *, int,
+                                   hipStream_t);
+template int launch_segdot<float>(const Csr<float> &, int,
+                                  const SegArgs<float> &, Ctrl *, int,
+                                  hipStream_t);
+
+// ------------------------------------------------------------ dense pass
+template <typename T> struct Vec;
+template <> struct Vec<double> { using type = double2; static constexpr int n = 2; };
+template <> struct Vec<float> { using type = float4; static constexpr int n = 4; };
+
+constexpr int DF_NT = 256;     // 4 waves
+constexpr int DF_RB = 128;     // rows per workgroup
+constexpr int DF_NL = 4;       // 16-byte loads per lane per row
+constexpr int DF_RG = 4;       // rows in flight per wave
+
+template <typename T>
+constexpr int df_cb() { return WAVE * Vec<T>::n * DF_NL; }
+
+template <typename T>
+void dense_work_shape(const Dense<T> &A, int *nch, int *nrb) {
+  *nch = (int)((A.ld + df_cb<T>() - 1) / df_cb<T>());
+  *nrb = (int)((A.rows + DF_RB - 1) / DF_RB);
+}
+template void dense_work_shape<double>(const Dense<double> &, int *, int *);
+template void dense_work_shape<float>(const Dense<float> &, int *, int *);
+
+template <typename T>
+__device__ __forceinline__ T vget(const typename Vec<T>::type &v, int i);
+template <>
+__device__ __forceinline__ double vget<double>(const double2 &v, int i) {
+  return i == 0 ? v.x : v.y;
+}
+template <>
+__device__ __forceinline__ float vget<float>(const float4 &v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(DF_NT)
+dense_fused_kernel(Dense<T> A, const T *__restrict__ x,
+                   const T *__restrict__ z, T *__restrict__ qpart,
+                   T *__restrict__ gpart, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  using V = typename Vec<T>::type;
+  constexpr int VN = Vec<T>::n;
+  constexpr int CB = df_cb<T>();
+  __shared__ T sg[DF_NT / WAVE][CB];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const int64_t c0 = (int64_t)blockIdx.x * CB;
+  const int64_t r0 = (int64_t)blockIdx.y * DF_RB;
+  const int64_t ld = A.ld;
+  T xs[DF_NL][VN], ga[DF_NL][VN];
+  bool cok[DF_NL];
+#pragma unroll
+  for (int t = 0; t < DF_NL; ++t) {
+    const int64_t c = c0 + (int64_t)(t * WAVE + lane) * VN;
+    cok[t] = c < ld;
+#pragma unroll
+    for (int v = 0; v < VN; ++v) {
+      xs[t][v] = cok[t] ? x[c + v] : (T)0;
+      ga[t][v] = (T)0;
+    }
+  }
+  const int nw = DF_NT / WAVE;
+  for (int rr = wv * DF_RG; rr < DF_RB; rr += nw * DF_RG) {
+    V av[DF_RG][DF_NL];
+    T zr[DF_RG];
+#pragma unroll
+    for (int u = 0; u < DF_RG; ++u) {
+      const int64_t i = r0 + rr + u;
+      const bool rok = i < A.rows;
+      zr[u] = rok ? z[i] : (T)0;
+      const V *row = reinterpret_cast<const V *>(A.a + (rok ? i : 0) * ld + c0);
+#pragma unroll
+      for (int t = 0; t < DF_NL; ++t) {
+        if (rok && cok[t]) av[u][t] = row[t * WAVE + lane];
+        else av[u][t] = V{};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < DF_RG; ++u) {
+      T qa = (T)0;
+#pragma unroll
+      for (int t = 0; t < DF_NL; ++t)
+#pragma unroll
+        for (int v = 0; v < VN; ++v) {
+          const T a = vget<T>(av[u][t], v);
+          qa += a * xs[t][v];
+          ga[t][v] += zr[u] * a;
+        }
+      qa = wave_sum(qa);
+      const int64_t i = r0 + rr + u;
+      if (lane == 0 && i < A.rows) qpart[(int64_t)blockIdx.x * A.rows + i] = qa;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < DF_NL; ++t)
+#pragma unroll
+    for (int v = 0; v < VN; ++v) sg[wv][(t * WAVE + lane) * VN + v] = ga[t][v];
+  __syncthreads();
+  for (int c = threadIdx.x; c < CB; c += DF_NT) {
+    const int64_t col = c0 + c;
+    if (col < ld) {
+      T s = (T)0;
+#pragma unroll
+      for (int w = 0; w < nw; ++w) s += sg[w][c];
+      gpart[(int64_t)blockIdx.y * ld + col] = s;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+dense_finalize(int64_t rows, int64_t cols, int64_t ld, int nch, int nrb,
+               const T *__restrict__ qpart, const T *__restrict__ gpart,
+               const T *__restrict__ off, const double *__restrict__ kappa,
+               T *__restrict__ g, T *__restrict__ eps, T *__restrict__ q,
+               Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < cols) {
+    T s = (T)0;
+    for (int b = 0; b < nrb; ++b) s += gpart[(int64_t)b * ld + t];
+    if (off) s += off[t];
+    g[t] = s;
+    const double k = kappa[t];
+    eps[t] = k > 0.0 ? (T)((double)s * (double)s / k) : (T)0;
+  }
+  if (t < rows) {
+    T s = (T)0;
+    for (int c = 0; c < nch; ++c) s += qpart[(int64_t)c * rows + t];
+    q[t] = s;
+  }
+}
+
+template <typename T>
+void launch_dense_fused(const Dense<T> &A, const T *x, const T *z,
+                        DenseWork<T> &w, const T *off, const double *kappa,
+                        T *g, T *eps, T *q, Ctrl *ctrl, int respect_done,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(dense_fused_kernel<T>, dim3(w.nch, w.nrb), dim3(DF_NT),
+                     0, st, A, x, z, w.qpart, w.gpart, ctrl, respect_done);
+  const int64_t mx = A.rows > A.cols ? A.rows : A.cols;
+  hipLaunchKernelGGL(dense_finalize<T>, dim3((unsigned)((mx + 255) / 256)),
+                     dim3(256), 0, st, A.rows, A.cols, A.ld, w.nch, w.nrb,
+                     w.qpart, w.gpart, off, kappa, g, eps, q, ctrl,
+                     respect_done);
+}
+template void launch_dense_fused<double>(const Dense<double> &, const double *,
+                                         const double *, DenseWork<double> &,
+                                         const double *, const double *,
+                                         double *, double *, double *, Ctrl *,
+                                         int, hipStream_t);
+template void launch_dense_fused<float>(const Dense<float> &, const float *,
+                                        const float *, DenseWork<float> &,
+                                        const float *, const double *, float *,
+                                        float *, float *, Ctrl *, int,
+                                        hipStream_t);
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+rowres_dense_kernel(int64_t m, const T *__restrict__ b,
+                    const T *__restrict__ z, const T *__restrict__ q,
+                    const double *__restrict__ rho, T *__restrict__ r,
+                    T *__restrict__ eps, double *__restrict__ part,
+                    Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[256 / WAVE];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double pb = 0.0, pr = 0.0;
+  if (i < m) {
+    const T bb = b[i], qq = q[i];
+    const T rr = bb - z[i] - qq;
+    r[i] = rr;
+    const double nr = rho[i];
+    eps[i] = nr > 0.0 ? (T)((double)rr * (double)rr / nr) : (T)0;
+    const double bq = (double)bb - (double)qq;
+    pb = bq * bq;
+    pr = (double)rr * (double)rr;
+  }
+  pb = block_sum<256>(pb, sh);
+  pr = block_sum<256>(pr, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = pb;
+    part[2 * blockIdx.x + 1] = pr;
+  }
+}
+
+template <typename T>
+int launch_rowres_dense(int64_t m, const T *b, const T *z, const T *q,
+                        const double *rho, T *r, T *eps, double *part,
+                        Ctrl *ctrl, int respect_done, hipStream_t st) {
+  const int nb = (int)((m + 255) / 256);
+  hipLaunchKernelGGL(rowres_dense_kernel<T>, dim3(nb), dim3(256), 0, st, m, b,
+                     z, q, rho, r, eps, part, ctrl, respect_done);
+  return nb;
+}
+template int launch_rowres_dense<double>(int64_t, const double *,
+                                         const double *, const double *,
+                                         const double *, double *, double *,
+                                         double *, Ctrl *, int, hipStream_t);
+template int launch_rowres_dense<float>(int64_t, const float *, const float *,
+                                        const float *, const double *, float *,
+                                        float *, double *, Ctrl *, int,
+                                        hipStream_t);
+
+// ------------------------------------------------------------ stop tests
+// ||x_base + x - x_ref||^2 / ||x_ref||^2 at the top of an iteration; the last
+// block compares with tol^2 and raises done/converged.  `final_check`
+// (respect_done == 0) evaluates even when done is already set.
+template <typename T>
+__global__ void __launch_bounds__(256)
+err_ref_kernel(int64_t n, const T *__restrict__ x,
+               const double *__restrict__ xr, const double *__restrict__ xb,
+               double *__restrict__ part, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[256 / WAVE];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const double v = (xb ? xb[i] : 0.0) + (double)x[i];
+    const double e = v - xr[i];
+    s += e * e;
+  }
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) st_agent(&part[blockIdx.x], s);
+  if (last_block(&ctrl->ticket[0])) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += 256) t += ld_agent(&part[b]);
+    t = block_sum<256>(t, sh);
+    if (threadIdx.x == 0) {
+      const double metric = ctrl->ref2 > 0.0 ? sqrt(t / ctrl->ref2) : sqrt(t);
+      ctrl->metric = metric;
+      if (metric <= ctrl->tol) { ctrl->done = 1; ctrl->converged = 1; }
+    }
+  }
+}
+
+template <typename T>
+void launch_err_ref(int64_t n, const T *x, const double *x_ref,
+                    const double *x_base, Reduce &red, Ctrl *ctrl,
+                    int respect_done, hipStream_t st) {
+  int nb = (int)((n + 255) / 256);
+  if (nb > 512) nb = 512;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(err_ref_kernel<T>, dim3(nb), dim3(256), 0, st, n, x,
+                     x_ref, x_base, red.part, ctrl, respect_done);
+}
+template void launch_err_ref<double>(int64_t, const double *, const double *,
+                                     const double *, Reduce &, Ctrl *, int,
+                                     hipStream_t);
+template void launch_err_ref<float>(int64_t, const float *, const double *,
+                                    const double *, Reduce &, Ctrl *, int,
+                                    hipStream_t);
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+set_ref2_kernel(int64_t n, const T *__restrict__ v, Ctrl *ctrl) {
+  __shared__ double sh[1024 / WAVE];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double a = (double)v[i];
+    s += a * a;
+  }
+  s = block_sum<1024>(s, sh);
+  if (threadIdx.x == 0) ctrl->ref2 = s;
+}
+template <typename T>
+void launch_set_ref2(int64_t n, const T *v, Ctrl *ctrl, hipStream_t st) {
+  hipLaunchKernelGGL(set_ref2_kernel<T>, dim3(1), dim3(1024), 0, st, n, v,
+                     ctrl);
+}
+template void launch_set_ref2<double>(int64_t, const double *, Ctrl *,
+                                      hipStream_t);
+template void launch_set_ref2<float>(int64_t, const float *, Ctrl *,
+                                     hipStream_t);
+
+// RSE  : sum(b - Ax)^2 / ||b||^2 <= tol
+// RES_EXT: sqrt(sum r^2 / ||b||^2) <= tol
+__global__ void __launch_bounds__(256)
+stop_rowres_kernel(const double *__restrict__ part, int nparts, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  const int mode = ctrl->stop_mode;
+  if (mode != 2 && mode != 3) return;
+  __shared__ double sh[256 / WAVE];
+  double pb = 0.0, pr = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    pb += part[2 * b];
+    pr += part[2 * b + 1];
+  }
+  pb = block_sum<256>(pb, sh);
+  pr = block_sum<256>(pr, sh);
+  if (threadIdx.x == 0) {
+    const double den = ctrl->ref2 > 0.0 ? ctrl->ref2 : 1.0;
+    const double metric = (mode == 2) ? pb / den : sqrt(pr / den);
+    ctrl->metric = metric;
+    if (metric <= ctrl->tol) { ctrl->done = 1; ctrl->converged = 1; }
+  }
+}
+void launch_stop_rowres(const double *part, int nparts, Ctrl *ctrl,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(stop_rowres_kernel, dim3(1), dim3(256), 0, st, part,
+                     nparts, ctrl);
+}
+
+__global__ void end_iter_kernel(Ctrl *ctrl) {
+  if (threadIdx.x != 0 || ctrl->done) return;
+  ctrl->it += 1;
+  ctrl->iters_run += 1;
+  if (ctrl->iters_run >= ctrl->it_end || ctrl->numeric) ctrl->done = 1;
+}
+void launch_end_iter(Ctrl *ctrl, hipStream_t st) {
+  hipLaunchKernelGGL(end_iter_kernel, dim3(1), dim3(64), 0, st, ctrl);
+}
+
+__global__ void fill_it_kernel(Ctrl *ctrl, int64_t it) {
+  if (threadIdx.x == 0) ctrl->it = it;
+}
+void launch_fill_ctrl_it(Ctrl *ctrl, int64_t it, hipStream_t st) {
+  hipLaunchKernelGGL(fill_it_kernel, dim3(1), dim3(64), 0, st, ctrl, it);
+}
+
+}  // namespace rg

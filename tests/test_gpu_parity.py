@@ -1,0 +1,383 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C-ABI.
+
+Selection: bit-exact index sets on identical weights.  Iterates: relative
+difference <= 1e-10 in FP64 after a fixed number of iterations (trajectory
+mode) and at convergence (solution mode).  Mixed precision: <= 1e-5 against
+the FP64 solution before refinement, FP64 level after."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle.rgdbek import rgdbek
+from oracle.select import select as oselect
+from oracle.refsol import pinv_solution
+
+pytestmark = pytest.mark.gpu
+
+TRAJ_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def rg():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2509_19267_amd as rg
+    rg.load()
+    return rg
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dtype).cuda()
+
+
+def csr_tensors(a):
+    rp, ci, v = workloads.to_csr_arrays(a)
+    return (torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(),
+            torch.as_tensor(v).cuda())
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+# ------------------------------------------------------------ selection
+def sel_cases():
+    rng = np.random.default_rng(0)
+    yield "random", rng.random(1000) ** 4, 100
+    e = rng.random(5000)
+    e[rng.random(5000) < 0.9] = 0.0
+    yield "zero_heavy", e, 300
+    yield "ties", np.repeat([0.5, 1.0, 2.0], [300, 300, 400]), 250
+    yield "k1", rng.random(777), 1
+    yield "k_eq_d", rng.random(333) + 0.1, 333
+    yield "k_gt_pos", np.where(rng.random(400) < 0.05, 1.0, 0.0), 50
+    yield "denormal", np.full(200, 5e-324), 17
+    yield "one_weight", np.eye(1, 97, 13).ravel(), 5
+    yield "small_max", rng.random(65536), 6553
+    yield "large_min", rng.random(65537), 6554
+    yield "rows_1e6", rng.random(1_000_000) ** 2, 100_000
+    big = rng.random(300_000)
+    big[::3] = 0.25
+    yield "large_ties", big, 120_000
+    yield "large_all", np.where(rng.random(200_000) < 0.01, rng.random(200_000), 0.0), 5000
+
+
+@pytest.mark.parametrize("case", list(sel_cases()), ids=lambda c: c[0])
+def test_select_bit_exact(rg, case):
+    name, eps, k = case
+    print(f"select case {name} d={eps.size} k={k}", flush=True)
+    for (seed, it, phase, sys, key1) in [(0, 0, 0, 0, 0), (12345, 77, 1, 3, 1)]:
+        got = rg.select(dev(eps), k, seed=seed, it=it, phase=phase, sys=sys,
+                        key1=key1).cpu().numpy()
+        want = oselect(eps, k, seed, it, phase, sys, key1)
+        assert got.dtype == np.int32
+        assert np.array_equal(got.astype(np.int64), want), name
+
+
+@pytest.mark.parametrize("floor", [0.0, 1e-20, 1e-26, 1e-8])
+def test_select_weight_floor_bit_exact(rg, floor):
+    rng = np.random.default_rng(5)
+    for d, k in [(3000, 2000), (120_000, 90_000)]:
+        e = rng.random(d)
+        noise = rng.random(d) < 0.5
+        e[noise] = rng.random(int(noise.sum())) * 1e-28   # rounding-level weights
+        got = rg.select(dev(e), k, seed=4, it=9, phase=0, floor=floor).cpu().numpy()
+        want = oselect(e, k, 4, 9, 0, floor=floor)
+        assert np.array_equal(got.astype(np.int64), want)
+
+
+def test_select_numeric_error(rg):
+    with pytest.raises(rg.RgdbekError) as ei:
+        rg.select(dev(np.array([1.0, np.nan, 2.0])), 1)
+    assert ei.value.status == 2
+    with pytest.raises(rg.RgdbekError):
+        rg.select(dev(np.array([1.0, -1.0])), 1)
+
+
+# ------------------------------------------------------------ trajectories
+def run_both(rg, p, k_col, k_row, iters, seed=0, sparse=False, **kw):
+    if sparse:
+        s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, k_col=k_col,
+                      k_row=k_row, stop="none", max_iter=iters, seed=seed, **kw)
+    else:
+        s = rg.Solver(dev(p.a), k_col=k_col, k_row=k_row, stop="none",
+                      max_iter=iters, seed=seed, **kw)
+    x, info = s.solve(dev(p.b))
+    z = s.get_z().cpu().numpy()
+    xo, zo, io = rgdbek(p.a, p.b, k_col=k_col, k_row=k_row, max_iter=iters,
+                        seed=seed)
+    s.close()
+    return x.cpu().numpy(), z, info, xo, zo
+
+
+def test_trajectory_dense_consistent_c1(rg):
+    # 500 x 250 N(0,1), eta = 0.5: 125 columns, 250 rows (square row blocks)
+    p = workloads.dense_consistent(500, 250, seed=0)
+    for iters in [1, 3, 8]:
+        x, z, info, xo, zo = run_both(rg, p, 125, 250, iters)
+        print(f"c1 iters={iters} rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+        assert info["iterations"] == iters
+        assert rel(x, xo) <= TRAJ_TOL
+        assert rel(z, zo) <= TRAJ_TOL
+
+
+def test_solution_dense_consistent_c1(rg):
+    p = workloads.dense_consistent(500, 250, seed=0)
+    s = rg.Solver(dev(p.a), eta=0.5, stop="err_ref", tol=1e-10, max_iter=500)
+    x, info = s.solve(dev(p.b), x_ref=dev(p.x_star))
+    xo, zo, io = rgdbek(p.a, p.b, eta=0.5, max_iter=500, stop="err_ref",
+                        tol=1e-10, x_ref=p.x_star)
+    print("c1 solve", info, io.iterations, flush=True)
+    assert info["converged"] == 1
+    assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
+    assert rel(x.cpu().numpy(), xo) <= 2e-10
+    assert abs(info["iterations"] - io.iterations) <= 1
+
+
+@pytest.mark.parametrize("kc,kr,solver", [(40, 80, 0), (300, 400, 0), (120, 200, 2)])
+def test_trajectory_dense_least_squares(rg, kc, kr, solver):
+    p = workloads.dense_least_squares(2000, 500, seed=2)
+    x, z, info, xo, zo = run_both(rg, p, kc, kr, 4, seed=5, solver=solver,
+                                  inner_max=200)
+    print(f"ls kc={kc} kr={kr} solver={solver} rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+    assert rel(x, xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
+
+
+def test_trajectory_sparse_uniform(rg):
+    p = workloads.sparse_uniform(3000, 1500, density=0.01, seed=3)
+    x, z, info, xo, zo = run_both(rg, p, 150, 300, 4, sparse=True,
+                                  inner_max=200)
+    print(f"sparse uniform rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+    assert rel(x, xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
+
+
+def test_trajectory_sparse_powerlaw(rg):
+    # long rows (up to 400 nnz) take the one-workgroup-per-row kernel
+    # some row blocks are rank-deficient (rows sharing their single column):
+    # CG on the singular consistent Gram needs more steps
+    p = workloads.sparse_powerlaw(6000, 3000, mean_len=10, max_len=400, seed=4)
+    x, z, info, xo, zo = run_both(rg, p, 300, 600, 3, sparse=True,
+                                  inner_max=1000, graph_iters=1)
+    print(f"sparse powerlaw rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+    assert rel(x, xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
+
+
+def test_solution_sparse_consistent(rg):
+    p = workloads.sparse_powerlaw(6000, 3000, mean_len=10, max_len=400, seed=5)
+    s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, eta=0.1,
+                  stop="err_ref", tol=1e-10, max_iter=3000, inner_max=100)
+    x, info = s.solve(dev(p.b), x_ref=dev(p.x_star))
+    print("sparse solve", info, flush=True)
+    assert info["converged"] == 1
+    assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
+
+
+def test_resume_is_bitwise(rg):
+    p = workloads.dense_least_squares(800, 200, seed=6)
+    s = rg.Solver(dev(p.a), k_col=30, k_row=60, stop="none", max_iter=6, seed=2)
+    x2, _ = s.solve(dev(p.b))
+    z2 = s.get_z()
+    s.close()
+    s = rg.Solver(dev(p.a), k_col=30, k_row=60, stop="none", max_iter=3, seed=2)
+    x1, _ = s.solve(dev(p.b))
+    z1 = s.get_z()
+    s.solve_resume(dev(p.b), x1, z1, 3)
+    assert torch.equal(x1, x2) and torch.equal(z1, z2)
+    s.close()
+
+
+def test_stop_rules_and_errors(rg):
+    p = workloads.dense_consistent(120, 60, seed=7)
+    s = rg.Solver(dev(p.a), k_col=10, k_row=20, stop="rse", tol=1e-12,
+                  max_iter=2000)
+    x, info = s.solve(dev(p.b))
+    xo, _, io = rgdbek(p.a, p.b, k_col=10, k_row=20, max_iter=2000,
+                       stop="rse", tol=1e-12)
+    assert info["converged"] == 1
+    assert abs(info["iterations"] - io.iterations) <= 1
+    s.close()
+    s = rg.Solver(dev(p.a), k_col=10, k_row=20, stop="err_ref", tol=1e-30,
+                  max_iter=3)
+    x, info = s.solve(dev(p.b), x_ref=dev(p.x_star))
+    assert info["converged"] == 0 and info["iterations"] == 3
+    assert info["status"] == 3
+    xo, _, _ = rgdbek(p.a, p.b, k_col=10, k_row=20, max_iter=3)
+    assert rel(x.cpu().numpy(), xo) <= TRAJ_TOL
+    bad = p.b.copy()
+    bad[5] = np.nan
+    with pytest.raises(rg.RgdbekError) as ei:
+        s.solve(dev(bad), x_ref=dev(p.x_star))
+    assert ei.value.status == 2
+    s.close()
+    with pytest.raises(rg.RgdbekError) as ei:
+        rg.Solver(dev(p.a), k_col=61, k_row=20)
+    assert ei.value.status == 1
+    a = p.a.copy()
+    a[3, 3] = np.inf
+    with pytest.raises(rg.RgdbekError) as ei:
+        rg.Solver(dev(a), k_col=10, k_row=20)
+    assert ei.value.status == 2
+
+
+def test_csr_structure_errors(rg):
+    p = workloads.sparse_uniform(50, 40, density=0.1, seed=8)
+    rp, ci, v = csr_tensors(p.a)
+    ci_bad = ci.clone()
+    ci_bad[0] = 40
+    with pytest.raises(rg.RgdbekError) as ei:
+        rg.Solver(csr=(rp, ci_bad, v), shape=(50, 40), k_col=5, k_row=5)
+    assert ei.value.status == 1
+    rp_bad = rp.clone()
+    rp_bad[10] = rp_bad[11] + 1
+    with pytest.raises(rg.RgdbekError):
+        rg.Solver(csr=(rp_bad, ci, v), shape=(50, 40), k_col=5, k_row=5)
+
+
+def test_zero_rows_and_columns(rg):
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal((40, 20))
+    a[4, :] = 0.0
+    a[:, 7] = 0.0
+    b = rng.standard_normal(40)
+    s = rg.Solver(dev(a), k_col=6, k_row=10, stop="res_ext", tol=1e-11,
+                  max_iter=5000)
+    x, info = s.solve(dev(b))
+    xs, rs = pinv_solution(a)(b)
+    assert info["converged"] == 1
+    assert rel(x.cpu().numpy(), xs) <= 1e-9
+    assert x[7].item() == 0.0
+    z = s.get_z().cpu().numpy()
+    assert abs(z[4] - b[4]) <= 1e-12
+
+
+# ------------------------------------------------------------ adjoint / grad
+def test_adjoint_solve(rg):
+    p = workloads.dense_least_squares(300, 80, seed=9)
+    g = np.random.default_rng(1).standard_normal(80)
+    s = rg.Solver(dev(p.a), k_col=20, k_row=40, stop="res_ext", tol=1e-13,
+                  max_iter=5000)
+    w, info = s.solve_adjoint(dev(g))
+    w_ref = np.linalg.pinv(p.a.T) @ g
+    print("adjoint", info, rel(w.cpu().numpy(), w_ref), flush=True)
+    assert rel(w.cpu().numpy(), w_ref) <= 1e-10
+    s.close()
+
+
+def test_gradient_pattern_and_autograd_dense(rg):
+    p = workloads.dense_least_squares(200, 50, seed=10)
+    from oracle.refsol import grad_reference
+    c = np.random.default_rng(2).standard_normal(50)
+    a_t = dev(p.a).requires_grad_(True)
+    b_t = dev(p.b).requires_grad_(True)
+    s = rg.Solver(a_t.detach(), k_col=15, k_row=30, stop="res_ext", tol=1e-13,
+                  max_iter=5000)
+    x = rg.solve(s, a_t.reshape(-1), b_t, least_squares=True)
+    loss = (x * dev(c)).sum()
+    loss.backward()
+    da_ref, db_ref = grad_reference(p.a, p.b, c)
+    assert rel(b_t.grad.cpu().numpy(), db_ref) <= 1e-9
+    assert rel(a_t.grad.cpu().numpy(), da_ref) <= 1e-9
+    s.close()
+
+
+def test_gradient_sparse_pattern(rg):
+    p = workloads.sparse_uniform(400, 150, density=0.05, seed=11)
+    from oracle.refsol import grad_reference
+    c = np.random.default_rng(3).standard_normal(150)
+    rp, ci, v = csr_tensors(p.a)
+    v = v.requires_grad_(True)
+    b_t = dev(p.b).requires_grad_(True)
+    s = rg.Solver(csr=(rp, ci, v.detach()), shape=p.a.shape, k_col=30,
+                  k_row=60, stop="res_ext", tol=1e-13, max_iter=5000,
+                  inner_max=100)
+    x = rg.solve(s, v, b_t, least_squares=False)
+    (x * dev(c)).sum().backward()
+    da_ref, db_ref = grad_reference(p.a.toarray(), p.b, c)
+    a = p.a.tocsr()
+    rows = np.repeat(np.arange(a.shape[0]), np.diff(a.indptr))
+    want = da_ref[rows, a.indices]
+    assert rel(b_t.grad.cpu().numpy(), db_ref) <= 1e-9
+    assert rel(v.grad.cpu().numpy(), want) <= 1e-9
+    s.close()
+
+
+# ------------------------------------------------------------ mixed
+def test_mixed_dense_least_squares(rg):
+    p = workloads.dense_least_squares(2000, 500, seed=12)
+    s = rg.Solver(dev(p.a), k_col=100, k_row=100, precision="mixed_f32",
+                  stop="err_ref", tol=1e-11, max_iter=5000)
+    x, info = s.solve(dev(p.b), x_ref=dev(p.x_star))
+    print("mixed dense", info, rel(x.cpu().numpy(), p.x_star), flush=True)
+    assert info["converged"] == 1
+    assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
+    s.close()
+
+
+def test_mixed_first_pass_within_1e5(rg):
+    # the first FP32 pass alone (before any FP64 refinement update) lands
+    # within 1e-5 of the FP64 solution
+    p = workloads.dense_least_squares(2000, 500, seed=13)
+    s = rg.Solver(dev(p.a), k_col=100, k_row=100, precision="mixed_f32",
+                  stop="none", max_iter=400)
+    x, info = s.solve(dev(p.b))
+    assert info["outer_iterations"] == 1
+    xo = np.linalg.lstsq(p.a, p.b, rcond=None)[0]
+    print("mixed first pass", rel(x.cpu().numpy(), xo), flush=True)
+    assert rel(x.cpu().numpy(), xo) <= 1e-5
+    s.close()
+
+
+def test_mixed_rse_and_unsupported(rg):
+    p = workloads.dense_consistent(400, 200, seed=15)
+    s = rg.Solver(dev(p.a), k_col=50, k_row=100, precision="mixed_f32",
+                  stop="rse", tol=1e-24, max_iter=5000)
+    x, info = s.solve(dev(p.b))
+    assert info["converged"] == 1
+    assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
+    s.close()
+    with pytest.raises(rg.RgdbekError) as ei:
+        rg.Solver(dev(p.a), k_col=50, k_row=100, precision="mixed_f32",
+                  stop="res_ext")
+    assert ei.value.status == 6
+
+
+def test_apply_matches_products(rg):
+    p = workloads.sparse_powerlaw(5000, 2000, mean_len=10, max_len=300, seed=16)
+    rng = np.random.default_rng(0)
+    xv, zv = rng.standard_normal(2000), rng.standard_normal(5000)
+    s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, k_col=10, k_row=10,
+                  precision="mixed_f32")
+    ax, atz = s.apply(dev(xv), dev(zv))
+    torch.cuda.synchronize()
+    assert rel(ax.cpu().numpy(), p.a @ xv) <= 1e-14
+    assert rel(atz.cpu().numpy(), p.a.T @ zv) <= 1e-14
+    ax, atz = s.apply(dev(xv, torch.float32), dev(zv, torch.float32), precision="f32")
+    torch.cuda.synchronize()
+    assert rel(ax.cpu().numpy(), p.a @ xv) <= 1e-5
+    s.close()
+    d = workloads.dense_least_squares(3000, 700, seed=17)
+    s = rg.Solver(dev(d.a), k_col=10, k_row=10)
+    xv, zv = rng.standard_normal(700), rng.standard_normal(3000)
+    ax, atz = s.apply(dev(xv), dev(zv))
+    torch.cuda.synchronize()
+    assert rel(ax.cpu().numpy(), d.a @ xv) <= 1e-14
+    assert rel(atz.cpu().numpy(), d.a.T @ zv) <= 1e-14
+    s.close()
+
+
+def test_mixed_sparse_consistent(rg):
+    p = workloads.sparse_powerlaw(6000, 3000, mean_len=10, max_len=400, seed=14)
+    s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, eta=0.1,
+                  precision="mixed_f32", stop="err_ref", tol=1e-10,
+                  max_iter=5000, inner_max=100)
+    x, info = s.solve(dev(p.b), x_ref=dev(p.x_star))
+    print("mixed sparse", info, flush=True)
+    assert info["converged"] == 1
+    assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
+    s.close()

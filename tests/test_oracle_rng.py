@@ -188,3 +188,14 @@ def test_threshold_set():
     assert list(select_threshold(eps, 0.5)) == [1, 4]
     assert list(select_threshold(eps, 0.45)) == [1, 2, 4]
     assert select_threshold(np.zeros(3), 0.5).size == 0
+
+
+def test_select_weight_floor():
+    # weights at rounding level relative to the largest are not drawn
+    eps = np.array([1.0, 0.5, 1e-25, 3e-30, 0.25, 0.0])
+    assert list(select(eps, 5, 0, 0, 0)) == [0, 1, 4]
+    assert list(select(eps, 5, 0, 0, 0, floor=0.0)) == [0, 1, 2, 3, 4]
+    assert list(select(eps, 5, 0, 0, 0, floor=1e-26)) == [0, 1, 2, 4]
+    # the floor is relative: scaling all weights changes nothing
+    e = np.random.default_rng(4).random(300) ** 8
+    assert np.array_equal(select(e, 40, 1, 2, 1), select(e * 1e-200, 40, 1, 2, 1))
