@@ -41,12 +41,45 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--kc", type=int, default=0)
     ap.add_argument("--kr", type=int, default=0)
+    ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--inner-max", type=int, default=0)
     ap.add_argument("--tune", action="store_true",
                     help="sweep block sizes before timing (slow)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed_f32")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--probe", action="store_true",
+                    help="counter probe: a 1 GiB device copy (calibration) "
+                         "and fused-pass launches only, no solves")
     return ap.parse_args()
+
+
+def probe(args):
+    """Short program for hardware-counter runs: torch's device copy of a
+    known size (FETCH_SIZE/WRITE_SIZE calibration), then the fused residual
+    pass in FP64 and FP32 (rgdbek_apply) on the benchmark matrix."""
+    import torch
+    import paper_2509_19267_amd as rg
+    dev = torch.device("cuda", 0)
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy: 1 GiB read + 1 GiB write per launch")
+    rng = np.random.default_rng(0)
+    m, n = args.m, args.n
+    a = torch.as_tensor(rng.standard_normal((m, n))).to(dev)
+    s = rg.Solver(a, k_col=8, k_row=8, precision="mixed_f32")
+    for prec, dt in [("f64", torch.float64), ("f32", torch.float32)]:
+        xv = torch.randn(n, dtype=dt, device=dev)
+        zv = torch.randn(m, dtype=dt, device=dev)
+        for _ in range(3):
+            s.apply(xv, zv, precision=prec)
+        torch.cuda.synchronize()
+        log(f"fused pass {prec}: 3 launches")
+    s.close()
+    print(json.dumps({"probe": "done", "m": m, "n": n}))
 
 
 def main():
@@ -61,6 +94,9 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if args.probe:
+        probe(args)
+        return
     dev = torch.device("cuda", 0)
     t0 = time.time()
     prob = workloads.dense_least_squares(args.m, args.n, seed=0)
@@ -72,7 +108,8 @@ def main():
 
     choice = tune.lookup("dense", args.m, args.n)
     if args.kc and args.kr:
-        choice = dict(k_col=args.kc, k_row=args.kr, gram_aat=False)
+        choice = dict(k_col=args.kc, k_row=args.kr, gram_aat=args.kr > 256,
+                      inner_tol=args.inner_tol, inner_max=args.inner_max)
     if args.tune or choice is None:
         choice = tune.tune_dense(a, b, xs, stream=stream, log=log)
     log(f"block sizes {choice}")
@@ -82,7 +119,9 @@ def main():
     for form in args.forms.split(","):
         kw = dict(k_col=choice["k_col"], k_row=choice["k_row"],
                   gram_aat=choice.get("gram_aat", False), stop="err_ref",
-                  tol=args.tol, max_iter=20000, precision=form, stream=stream)
+                  tol=args.tol, max_iter=20000, precision=form, stream=stream,
+                  inner_tol=choice.get("inner_tol", 0.0),
+                  inner_max=choice.get("inner_max", 0))
         tc = time.time()
         s = rg.Solver(a, **kw)
         create_s = time.time() - tc
@@ -170,7 +209,9 @@ def main():
         "config": {"workload": f"dense_least_squares_{m}x{n}", "m": m, "n": n,
                    "tol": args.tol, "form": best_form,
                    "k_col": choice["k_col"], "k_row": choice["k_row"],
-                   "gram_aat": bool(choice.get("gram_aat", False))},
+                   "gram_aat": bool(choice.get("gram_aat", False)),
+                   "inner_tol": choice.get("inner_tol", 0.0),
+                   "inner_max": choice.get("inner_max", 0)},
         "forms": forms,
         "speedup_mixed_vs_fp64": (round(forms["fp64"]["ms_per_solve"] /
                                         forms["mixed_f32"]["ms_per_solve"], 3)

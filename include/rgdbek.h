@@ -144,6 +144,41 @@ rgdbek_status rgdbek_params_default(rgdbek_params *p);
 rgdbek_status rgdbek_create(const rgdbek_matrix *A, const rgdbek_params *p,
                             void *stream, rgdbek_handle *out);
 
+/* A batch of independent sparse systems solved together: A is their
+ * block-diagonal concatenation in CSR with global indices -- system s owns
+ * rows [row_off[s], row_off[s+1]) and columns [col_off[s], col_off[s+1]) and
+ * no entry may leave that block (INVALID_ARG otherwise).  row_off/col_off:
+ * host arrays of nsys+1.  Each system gets its own block sizes (from eta, or
+ * k_col/k_row capped by the system's dimensions), its own generator stream
+ * (system id in Philox counter word 3), iteration counter and stop test;
+ * every residual pass and block-projection launch covers all systems.
+ * rgdbek_solve then solves all systems (b, x, x_ref concatenated); it is
+ * converged when every system is; rgdbek_batch_info gives the per-system
+ * figures.  rgdbek_solve_adjoint solves every system's adjoint. */
+rgdbek_status rgdbek_create_batched(const rgdbek_matrix *A, int64_t nsys,
+                                    const int64_t *row_off,
+                                    const int64_t *col_off,
+                                    const rgdbek_params *p, void *stream,
+                                    rgdbek_handle *out);
+
+/* Many right-hand sides of one sparse matrix: solves A x_s = b_s for
+ * s < nrhs.  A is stored once; the batch behaves as the block-diagonal
+ * system I_nrhs (x) A with one system per right-hand side (own draws,
+ * generator stream, iteration counter and stop test, as for
+ * rgdbek_create_batched), and every pass over A serves all right-hand sides
+ * (consecutive reads of a stored row belong to different right-hand sides,
+ * so A is fetched from HBM about once per pass).  Vectors are right-hand-side
+ * major: b[s*m + i], x[s*n + j].  rgdbek_grad_pattern then sums the pattern
+ * gradient over the right-hand sides. */
+rgdbek_status rgdbek_create_multirhs(const rgdbek_matrix *A, int64_t nrhs,
+                                     const rgdbek_params *p, void *stream,
+                                     rgdbek_handle *out);
+
+/* Per-system results of the last solve of a batch (host arrays of nsys, any
+ * may be NULL): iterations run, last stop metric, converged flag. */
+rgdbek_status rgdbek_batch_info(rgdbek_handle h, int64_t *iterations,
+                                double *metric, int32_t *converged);
+
 /* Solve A x = b (Algorithm 1 with the handle's parameters).
  *  b      device, m entries, FP64;
  *  x      device, n entries, FP64, output only (x_0 = 0);

@@ -5,7 +5,8 @@ The solver lives in the HIP library librgdbek.so (C-ABI in
 include/rgdbek.h); this package only marshals arguments to it.
 """
 from ._binding import RgdbekError, LIB_PATH, load  # noqa: F401
-from .solver import Solver, select, solve, RGDBEKFunction  # noqa: F401
+from .solver import (Solver, BatchSolver, MultiRhsSolver,  # noqa: F401
+                     block_diagonal, select, solve, RGDBEKFunction)
 
-__all__ = ["Solver", "select", "solve", "RGDBEKFunction", "RgdbekError",
+__all__ = ["Solver", "BatchSolver", "MultiRhsSolver", "block_diagonal", "select", "solve", "RGDBEKFunction", "RgdbekError",
            "LIB_PATH", "load"]

@@ -69,11 +69,23 @@ SIGNATURES = {
     "rgdbek_grad_pattern": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "rgdbek_select": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.c_double, ctypes.c_uint64,
-                                     ctypes.c_uint64,
-                                     ctypes.c_uint32,
-                                     ctypes.c_uint32, _vp,
+                                     ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_uint32, _vp,
                                      ctypes.POINTER(ctypes.c_int64), _vp]),
     "rgdbek_apply": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]),
+    "rgdbek_create_batched": (ctypes.c_int, [ctypes.POINTER(Matrix),
+                                             ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(Params), _vp,
+                                             ctypes.POINTER(_vp)]),
+    "rgdbek_create_multirhs": (ctypes.c_int, [ctypes.POINTER(Matrix),
+                                              ctypes.c_int64,
+                                              ctypes.POINTER(Params), _vp,
+                                              ctypes.POINTER(_vp)]),
+    "rgdbek_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int32)]),
     "rgdbek_destroy": (ctypes.c_int, [_vp]),
     "rgdbek_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rgdbek_last_error": (ctypes.c_char_p, [_vp]),

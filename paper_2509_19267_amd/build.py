@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "_lib")
 LIBNAME = "librgdbek.so"
 ARCH = "gfx950"
 
-SOURCES = ["select.hip", "spmv.hip", "proj.hip", "utils.hip", "runtime.hip"]
+SOURCES = ["select.hip", "spmv.hip", "proj.hip", "utils.hip", "batch.hip",
+           "runtime.hip"]
 # Bit-exact selection needs unfused, correctly rounded FP64 operations.
 EXTRA = {"select.hip": ["-ffp-contract=off"]}
 

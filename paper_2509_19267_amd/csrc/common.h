@@ -38,6 +38,21 @@ struct Ctrl {
   unsigned ticket[8];     // last-block tickets (reset by the last block)
 };
 
+// Per-system state of a batch of independent systems stored block-diagonally
+// (system s owns rows [row_off, row_off + nrow) and columns [col_off,
+// col_off + ncol)).  Block sizes kc/kr; kc_off/kr_off: offsets of the
+// system's slots in the per-phase draw scratch.
+struct SegInfo {
+  int64_t row_off, nrow, col_off, ncol;
+  int64_t kc, kr, kc_off, kr_off;
+  int64_t it;          // generator iteration counter of this system
+  int64_t iters_run;   // iterations this system has run in the solve
+  int32_t done;        // 1: this system stopped (tested or capped)
+  int32_t converged;
+  double metric;
+  double ref2;
+};
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);

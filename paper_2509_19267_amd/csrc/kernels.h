@@ -31,6 +31,36 @@ void launch_select(const T *eps, int64_t d, int64_t k, double floor,
                    int ph, SelectScratch &s, int32_t *out, Ctrl *ctrl,
                    int respect_done, hipStream_t st);
 
+// Per-system draws for a block-diagonal batch (one workgroup per system);
+// the concatenated global index list goes to out, its length to
+// Ctrl::sel_count[ph].  tmp/cnt: scratch (sum of block sizes / nseg).
+template <typename T>
+void launch_select_seg(const T *eps, const SegInfo *seg, int nseg, int ph,
+                       double floor, uint64_t seed, uint64_t key1,
+                       uint32_t phase, uint64_t *keys, int32_t *tmp,
+                       int64_t *cnt, int32_t *out, Ctrl *ctrl,
+                       int respect_done, hipStream_t st);
+
+// Per-system control of a batch (batch.hip): reference norms, state reset,
+// ERR_REF / RSE / RES_EXT per system, and the fold into Ctrl.
+template <typename T>
+void launch_seg_ref2(const T *v, SegInfo *seg, int nseg, int cols,
+                     hipStream_t st);
+void launch_seg_reset(SegInfo *seg, int nseg, int64_t it0, int keep_it,
+                      const int32_t *fixed, hipStream_t st);
+template <typename T>
+void launch_seg_err_ref(const T *x, const double *xr, const double *xb,
+                        SegInfo *seg, int nseg, Ctrl *ctrl, int respect_done,
+                        hipStream_t st);
+template <typename T>
+void launch_seg_stop_rowres(const T *r, const T *z, SegInfo *seg, int nseg,
+                            int mode, Ctrl *ctrl, int respect_done,
+                            hipStream_t st);
+void launch_seg_fold(SegInfo *seg, int nseg, Ctrl *ctrl, int end_iter,
+                     int64_t cap, int force, hipStream_t st);
+void launch_seg_converged(const SegInfo *seg, int nseg, int32_t *flags,
+                          hipStream_t st);
+
 // ------------------------------------------------------------ matrices
 template <typename T>
 struct Csr {                 // CSR (or CSC viewed as CSR of the transpose)
@@ -39,10 +69,36 @@ struct Csr {                 // CSR (or CSC viewed as CSR of the transpose)
   const int32_t *idx = nullptr;
   const T *val = nullptr;
   int group = 8;             // lanes per segment (power of two)
-  const int32_t *longs = nullptr;  // segments longer than the long limit
+  const int32_t *longs = nullptr;  // base segments longer than the limit
   int64_t nlong = 0;
   int64_t long_limit = 0;
+  // Replicated operator I_rep (x) A for many right-hand sides: the stored
+  // matrix is the base (brows x bcols); rows = rep * brows virtual rows.
+  // Virtual segments are visited in RHS-minor order (slot = i * rep + s) so
+  // the rep reads of one stored row follow each other and hit in cache.
+  int64_t rep = 1, brows = 0, bcols = 0;
 };
+
+// slot of a full sweep -> global row, stored row, column offset
+template <typename T>
+__device__ __forceinline__ void vrow(const Csr<T> &A, int64_t slot,
+                                     int64_t &grow, int64_t &brow,
+                                     int64_t &coff) {
+  if (A.rep == 1) { grow = slot; brow = slot; coff = 0; return; }
+  brow = slot / A.rep;
+  const int64_t s = slot - brow * A.rep;
+  grow = s * A.brows + brow;
+  coff = s * A.bcols;
+}
+// global row (from an index list) -> stored row, column offset
+template <typename T>
+__device__ __forceinline__ void gsplit(const Csr<T> &A, int64_t g,
+                                       int64_t &brow, int64_t &coff) {
+  if (A.rep == 1) { brow = g; coff = 0; return; }
+  const int64_t s = g / A.brows;
+  brow = g - s * A.brows;
+  coff = s * A.bcols;
+}
 
 template <typename T>
 struct Dense {               // row-major rows x cols with leading dim ld
@@ -149,9 +205,16 @@ void launch_chol_solve(T *G, int64_t cap, const int64_t *count_dev,
 // Preconditioned CG on the gathered Gram G y = h (Jacobi).  init + steps.
 template <typename T>
 struct CgWork {
-  T *res = nullptr, *p = nullptr, *v = nullptr, *zz = nullptr;
-  double *part = nullptr;    // per-block partials
+  T *res = nullptr, *v = nullptr, *zz = nullptr;
+  T *p = nullptr;            // 2 * cap (direction, alternating by step)
+  int64_t cap = 0;
+  double *pv = nullptr;      // per-block <p, v> partials (cap/4 + 1)
+  double *part = nullptr;    // 2 parities x 2 x part_cap (<r,zz>, <r,r>)
+  int64_t part_cap = 0;      // cap/256 + 1
+  double *rzs = nullptr;     // rz by step parity (2)
 };
+// largest Gram dimension the PCG kernels accept (direction staged in LDS)
+int64_t pcg_cap_max();
 template <typename T>
 void launch_pcg_gram_init(const T *G, int64_t cap, const int64_t *count_dev,
                           const T *hsrc, const int32_t *hlist, T *y,
@@ -159,8 +222,9 @@ void launch_pcg_gram_init(const T *G, int64_t cap, const int64_t *count_dev,
                           hipStream_t st);
 template <typename T>
 void launch_pcg_gram_step(const T *G, int64_t cap, const int64_t *count_dev,
-                          T *y, CgWork<T> &w, double tol, Ctrl *ctrl, int ph,
-                          int respect_done, hipStream_t st);
+                          T *y, CgWork<T> &w, int step, double tol,
+                          Ctrl *ctrl, int ph, int respect_done,
+                          hipStream_t st);
 
 // Dense thin updates.
 // z[i] -= sum_a y_a * Acm[list_a * ldc + i]   (columns of A, column-major)
@@ -230,11 +294,16 @@ template <typename T>
 void launch_csr_to_csc(int64_t m, int64_t n, int64_t nnz, const int64_t *rp,
                        const int32_t *ci, const T *v, int64_t *cp, int32_t *ri,
                        T *cv, int64_t *work, hipStream_t st);
-// pattern gradient: dA[e] = r_i lam_j - w_i x_j over stored entries
-void launch_grad_pattern_csr(int64_t m, const int64_t *rp, const int32_t *ci,
+// pattern gradient: dA[e] = sum_s (r_i lam_j - w_i x_j) over stored entries
+// (s over the rep right-hand sides sharing A; vectors RHS-major)
+void launch_grad_pattern_csr(int64_t m, int64_t n, int64_t rep,
+                             const int64_t *rp, const int32_t *ci,
                              const double *r, const double *lam,
                              const double *w, const double *x, double *dA,
                              hipStream_t st);
+// out[s*len + i] = in[i] for s < rep (replicate a base vector)
+void launch_replicate(const double *in, int64_t len, int64_t rep,
+                      double *out, hipStream_t st);
 void launch_grad_pattern_dense(int64_t m, int64_t n, const double *r,
                                const double *lam, const double *w,
                                const double *x, double *dA, hipStream_t st);

@@ -258,7 +258,24 @@ void launch_chol_solve(T *G, int64_t cap, const int64_t *count_dev,
 }
 
 // ------------------------------------------------------------ PCG on Gram
+// Jacobi-preconditioned CG on G y = h with two fence-free launches per step.
+// Scalars are never broadcast through memory within a launch: every block
+// re-derives them from small arrays of per-block partials of the previous
+// launch, in a fixed order, so all blocks hold identical bits.
+//   step t, launch A (one wave per row of G, 4 rows per block):
+//     t > 0: rz_t = sum rz partials, rr = sum rr partials; stop when
+//            rr <= tol^2 rr_0 (every block reaches the same verdict);
+//            beta = rz_t / rz_{t-1};  p_t = zz + beta p_{t-1}  (whole vector,
+//            rebuilt in LDS by every block; block 0 stores it)
+//     v = G p_t on the block's rows; partial <p_t, v>
+//   step t, launch B (k/256 blocks):
+//     alpha = rz_t / sum <p,v> partials; y += alpha p_t; res -= alpha v;
+//     zz = res / diag(G); partials of <res, zz> and <res, res>
+// p alternates between two buffers by step parity.
 constexpr int PG_NT = 256;
+constexpr int PG_ROWS = PG_NT / WAVE;     // rows per block in launch A
+constexpr int64_t PG_LDS_MAX = 8192;      // p staged in LDS (FP64: 64 KB)
+
 template <typename T>
 __global__ void __launch_bounds__(PG_NT)
 pcg_init_kernel(const T *__restrict__ G, int64_t ldg,
@@ -276,72 +293,111 @@ pcg_init_kernel(const T *__restrict__ G, int64_t ldg,
     y[a] = (T)0;
     w.res[a] = h;
     w.zz[a] = zz;
-    w.p[a] = zz;
+    w.p[a] = zz;               // p_0 in buffer 0
     rz += (double)h * (double)zz;
     rr += (double)h * (double)h;
   }
   rz = block_sum<PG_NT>(rz, sh);
   rr = block_sum<PG_NT>(rr, sh);
   if (threadIdx.x == 0) {
-    ctrl->cg_rz[ph] = rz;
-    ctrl->cg_rz0[ph] = rr;
+    ctrl->cg_rz[ph] = rz;      // rz_0
+    ctrl->cg_rz0[ph] = rr;     // ||h||^2
     ctrl->cg_done[ph] = (rr == 0.0 || c == 0) ? 1 : 0;
     ctrl->cg_steps[ph] = 0;
   }
 }
 
-// v = G p (one wave per row), then the last workgroup finishes the step.
 template <typename T>
 __global__ void __launch_bounds__(PG_NT)
-pcg_step_kernel(const T *__restrict__ G, int64_t ldg,
-                const int64_t *__restrict__ cnt, T *__restrict__ y,
-                CgWork<T> w, double tol, Ctrl *ctrl, int ph,
-                int respect_done) {
+pcg_step_a(const T *__restrict__ G, int64_t ldg, const int64_t *__restrict__ cnt,
+           CgWork<T> w, int t, int nb_b, double tol, Ctrl *ctrl, int ph,
+           int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[ph])) return;
+  if (ctrl->cg_done[ph]) return;
+  __shared__ T ps[PG_LDS_MAX];
   __shared__ double sh[PG_NT / WAVE];
   const int64_t c = *cnt;
+  const T *pold = w.p + (int64_t)((t + 1) & 1) * w.cap;
+  T *pnew = w.p + (int64_t)(t & 1) * w.cap;
+  if (t > 0) {
+    const double *part = w.part + (int64_t)((t - 1) & 1) * 2 * w.part_cap;
+    double rz = 0.0, rr = 0.0;
+    for (int b = threadIdx.x; b < nb_b; b += PG_NT) {
+      rz += part[2 * b];
+      rr += part[2 * b + 1];
+    }
+    rz = block_sum<PG_NT>(rz, sh);
+    rr = block_sum<PG_NT>(rr, sh);
+    const double rz_prev = w.rzs[(t - 1) & 1];
+    if (rr <= tol * tol * ctrl->cg_rz0[ph] || rz_prev == 0.0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->cg_done[ph] = 1;
+        ctrl->cg_steps[ph] = t;
+      }
+      return;
+    }
+    const double beta = rz / rz_prev;
+    for (int64_t a = threadIdx.x; a < c; a += PG_NT) {
+      const T pv = w.zz[a] + (T)beta * pold[a];
+      ps[a] = pv;
+      if (blockIdx.x == 0) pnew[a] = pv;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.rzs[t & 1] = rz;
+  } else {
+    for (int64_t a = threadIdx.x; a < c; a += PG_NT) ps[a] = pnew[a];
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.rzs[0] = ctrl->cg_rz[ph];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t row = (int64_t)blockIdx.x * (PG_NT / WAVE) + threadIdx.x / WAVE;
+  const int64_t row = (int64_t)blockIdx.x * PG_ROWS + threadIdx.x / WAVE;
   double pv = 0.0;
   if (row < c) {
     T s = 0;
     const T *gr = G + row * ldg;
-    for (int64_t b = lane; b < c; b += WAVE) s += gr[b] * w.p[b];
+    for (int64_t b = lane; b < c; b += WAVE) s += gr[b] * ps[b];
     s = wave_sum(s);
     if (lane == 0) {
       w.v[row] = s;
-      pv = (double)s * (double)w.p[row];
+      pv = (double)s * (double)ps[row];
     }
   }
   pv = block_sum<PG_NT>(pv, sh);
-  if (threadIdx.x == 0) st_agent(&w.part[blockIdx.x], pv);
-  if (!last_block(&ctrl->ticket[1 + ph])) return;
-  double tot = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += PG_NT) tot += ld_agent(&w.part[b]);
-  tot = block_sum<PG_NT>(tot, sh);
-  const double rz = ctrl->cg_rz[ph];
-  const double alpha = tot != 0.0 ? rz / tot : 0.0;
-  double rz1 = 0.0, rr = 0.0;
-  for (int64_t a = threadIdx.x; a < c; a += PG_NT) {
-    const T v = ld_agent(&w.v[a]);
-    y[a] += (T)alpha * w.p[a];
-    const T r = w.res[a] - (T)alpha * v;
+  if (threadIdx.x == 0) w.pv[blockIdx.x] = pv;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(PG_NT)
+pcg_step_b(const T *__restrict__ G, int64_t ldg, const int64_t *__restrict__ cnt,
+           T *__restrict__ y, CgWork<T> w, int t, int nb_a, Ctrl *ctrl, int ph,
+           int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ctrl->cg_done[ph]) return;
+  __shared__ double sh[PG_NT / WAVE];
+  const int64_t c = *cnt;
+  const T *pt = w.p + (int64_t)(t & 1) * w.cap;
+  double pv = 0.0;
+  for (int b = threadIdx.x; b < nb_a; b += PG_NT) pv += w.pv[b];
+  pv = block_sum<PG_NT>(pv, sh);
+  const double rz = w.rzs[t & 1];
+  const double alpha = pv != 0.0 ? rz / pv : 0.0;
+  double rzn = 0.0, rr = 0.0;
+  const int64_t a = (int64_t)blockIdx.x * PG_NT + threadIdx.x;
+  if (a < c) {
+    y[a] += (T)alpha * pt[a];
+    const T r = w.res[a] - (T)alpha * w.v[a];
     w.res[a] = r;
     const T dg = G[a * ldg + a];
     const T zz = dg > (T)0 ? r / dg : (T)0;
     w.zz[a] = zz;
-    rz1 += (double)r * (double)zz;
-    rr += (double)r * (double)r;
+    rzn = (double)r * (double)zz;
+    rr = (double)r * (double)r;
   }
-  rz1 = block_sum<PG_NT>(rz1, sh);
+  rzn = block_sum<PG_NT>(rzn, sh);
   rr = block_sum<PG_NT>(rr, sh);
-  const double beta = rz != 0.0 ? rz1 / rz : 0.0;
-  for (int64_t a = threadIdx.x; a < c; a += PG_NT) w.p[a] = w.zz[a] + (T)beta * w.p[a];
   if (threadIdx.x == 0) {
-    ctrl->cg_rz[ph] = rz1;
-    ctrl->cg_steps[ph] += 1;
-    if (rr <= tol * tol * ctrl->cg_rz0[ph] || tot == 0.0) ctrl->cg_done[ph] = 1;
+    double *part = w.part + (int64_t)(t & 1) * 2 * w.part_cap;
+    part[2 * blockIdx.x] = rzn;
+    part[2 * blockIdx.x + 1] = rr;
   }
 }
 
@@ -355,12 +411,17 @@ void launch_pcg_gram_init(const T *G, int64_t cap, const int64_t *count_dev,
 }
 template <typename T>
 void launch_pcg_gram_step(const T *G, int64_t cap, const int64_t *count_dev,
-                          T *y, CgWork<T> &w, double tol, Ctrl *ctrl, int ph,
-                          int respect_done, hipStream_t st) {
-  const unsigned nb = (unsigned)((cap + (PG_NT / WAVE) - 1) / (PG_NT / WAVE));
-  hipLaunchKernelGGL(pcg_step_kernel<T>, dim3(nb), dim3(PG_NT), 0, st, G, cap,
-                     count_dev, y, w, tol, ctrl, ph, respect_done);
+                          T *y, CgWork<T> &w, int step, double tol,
+                          Ctrl *ctrl, int ph, int respect_done,
+                          hipStream_t st) {
+  const int nb_a = (int)((cap + PG_ROWS - 1) / PG_ROWS);
+  const int nb_b = (int)((cap + PG_NT - 1) / PG_NT);
+  hipLaunchKernelGGL(pcg_step_a<T>, dim3(nb_a), dim3(PG_NT), 0, st, G, cap,
+                     count_dev, w, step, nb_b, tol, ctrl, ph, respect_done);
+  hipLaunchKernelGGL(pcg_step_b<T>, dim3(nb_b), dim3(PG_NT), 0, st, G, cap,
+                     count_dev, y, w, step, nb_a, ctrl, ph, respect_done);
 }
+int64_t pcg_cap_max() { return PG_LDS_MAX; }
 
 // ------------------------------------------------------------ thin updates
 // out[i] (+)= sign * sum_a coef_a * M[list_a * ldm + i] over a chunk of the
@@ -483,15 +544,18 @@ sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
   __shared__ double sh[SC_NT / WAVE];
   constexpr int SPB = SC_NT / G;
   const int lg = threadIdx.x & (G - 1);
-  const int64_t s = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  const int64_t slot = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  int64_t s = 0, br = 0, co = 0;
   T acc = 0;
-  if (s < A.rows) {
-    const int64_t e0 = A.ptr[s], e1 = A.ptr[s + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * phat[A.idx[e]];
+  if (slot < A.rows) {
+    vrow(A, slot, s, br, co);
+    const T *ph = phat + co;
+    const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * ph[A.idx[e]];
   }
   acc = group_sum<G>(acc);
   double qq = 0.0;
-  if (s < A.rows && lg == 0) {
+  if (slot < A.rows && lg == 0) {
     q[s] = acc;
     qq = (double)acc * (double)acc;
   }
@@ -534,9 +598,11 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
   const int64_t a = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
   T acc = 0;
   if (a < c) {
-    const int64_t col = U[a];
-    const int64_t e0 = At.ptr[col], e1 = At.ptr[col + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * q[At.idx[e]];
+    int64_t bc, ro;
+    gsplit(At, (int64_t)U[a], bc, ro);
+    const T *qv = q + ro;
+    const int64_t e0 = At.ptr[bc], e1 = At.ptr[bc + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * qv[At.idx[e]];
   }
   acc = group_sum<G>(acc);
   double ss = 0.0;
@@ -623,14 +689,17 @@ sc_wide_row(Csr<T> At, const T *__restrict__ phat, T *__restrict__ u,
   const double alpha = ctrl->cg_alpha[1];
   constexpr int SPB = SC_NT / G;
   const int lg = threadIdx.x & (G - 1);
-  const int64_t s = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  const int64_t slot = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  int64_t s = 0, br = 0, co = 0;
   T acc = 0;
-  if (s < At.rows) {
-    const int64_t e0 = At.ptr[s], e1 = At.ptr[s + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * phat[At.idx[e]];
+  if (slot < At.rows) {
+    vrow(At, slot, s, br, co);
+    const T *ph = phat + co;
+    const int64_t e0 = At.ptr[br], e1 = At.ptr[br + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * ph[At.idx[e]];
   }
   acc = group_sum<G>(acc);
-  if (s < At.rows && lg == 0) {
+  if (slot < At.rows && lg == 0) {
     if (alpha != 0.0) x[s] += (T)alpha * u[s];
     u[s] = acc;
   }
@@ -653,9 +722,11 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
   const int64_t a = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
   T acc = 0;
   if (a < c) {
-    const int64_t row = J[a];
-    const int64_t e0 = A.ptr[row], e1 = A.ptr[row + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * u[A.idx[e]];
+    int64_t brw, co;
+    gsplit(A, (int64_t)J[a], brw, co);
+    const T *uv = u + co;
+    const int64_t e0 = A.ptr[brw], e1 = A.ptr[brw + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * uv[A.idx[e]];
   }
   acc = group_sum<G>(acc);
   double pv = 0.0;
@@ -798,8 +869,8 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                                         CgWork<T> &, Ctrl *, int, int,        \
                                         hipStream_t);                         \
   template void launch_pcg_gram_step<T>(const T *, int64_t, const int64_t *, \
-                                        T *, CgWork<T> &, double, Ctrl *,     \
-                                        int, int, hipStream_t);               \
+                                        T *, CgWork<T> &, int, double,       \
+                                        Ctrl *, int, int, hipStream_t);       \
   template void launch_col_update<T>(const T *, int64_t, int64_t,            \
                                      const int32_t *, const int64_t *,       \
                                      int64_t, const T *, T *, T *, Ctrl *,   \

@@ -97,6 +97,10 @@ struct Engine {
   Reduce red;
   double *part = nullptr;     // row-residual partials
   double floor = 0.0;         // relative weight floor of the block draws
+  int32_t *seltmp = nullptr;  // per-system draws before packing (batch)
+  int64_t *selcnt = nullptr;  // per-system draw counts (batch)
+  int nseg = 0;               // systems (0: a single system)
+  SegInfo *seg = nullptr;
 };
 
 }  // namespace
@@ -125,6 +129,15 @@ struct rgdbek_ctx {
   Engine<float> e32;          // inner engine of the mixed form
   Ctrl *ctrl = nullptr;
   Ctrl *hctrl = nullptr;      // pinned host mirror
+  // batch of independent systems (block-diagonal storage); nseg == 0 for a
+  // single system
+  int nseg = 0;
+  SegInfo *seg = nullptr;     // per-system state, forward engines
+  SegInfo *seg_t = nullptr;   // per-system state, adjoint engine
+  std::vector<SegInfo> hseg;
+  int64_t rep = 1;            // right-hand sides sharing one stored A
+  int64_t bm = 0, bn = 0;     // stored (base) dimensions of A
+  int32_t *fixed = nullptr;   // systems accepted by an FP64 test (mixed form)
   double *xref = nullptr, *x64 = nullptr, *z64 = nullptr, *zero64 = nullptr,
          *t64 = nullptr;
   // captured graphs, keyed by (engine, key1, stop)
@@ -218,11 +231,15 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
                                 thin_update_scratch(e.n, e.kr)));
     for (CgWork<T> *cw : {&e.cgc, &e.cgr}) {
       const int64_t cap = (cw == &e.cgc) ? e.kc : e.kr;
+      cw->cap = cap;
       cw->res = P.alloc<T>(cap);
-      cw->p = P.alloc<T>(cap);
+      cw->p = P.alloc<T>(2 * cap);
       cw->v = P.alloc<T>(cap);
       cw->zz = P.alloc<T>(cap);
-      cw->part = P.alloc<double>(cap / 4 + 64);
+      cw->pv = P.alloc<double>(cap / 4 + 64);
+      cw->part_cap = cap / 256 + 2;
+      cw->part = P.alloc<double>(4 * cw->part_cap);
+      cw->rzs = P.alloc<double>(2);
     }
   } else {
     // CSR / CSC views; the adjoint swaps them
@@ -240,6 +257,9 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       vrT = t1;
       vcT = t2;
     }
+    a.rep = at.rep = h->rep;
+    a.brows = at.bcols = transpose ? h->bn : h->bm;
+    a.bcols = at.brows = transpose ? h->bm : h->bn;
     a.rows = e.m; a.cols = e.n; a.nnz = h->nnz;
     a.ptr = transpose ? h->csc_ptr : h->csr_ptr;
     a.idx = transpose ? h->csc_idx : h->csr_idx;
@@ -248,8 +268,8 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     at.ptr = transpose ? h->csr_ptr : h->csc_ptr;
     at.idx = transpose ? h->csr_idx : h->csc_idx;
     at.val = vcT;
-    const double mr = e.m ? (double)h->nnz / (double)e.m : 1.0;
-    const double mc = e.n ? (double)h->nnz / (double)e.n : 1.0;
+    const double mr = a.brows ? (double)h->nnz / (double)a.brows : 1.0;
+    const double mc = a.bcols ? (double)h->nnz / (double)a.bcols : 1.0;
     a.group = pick_group(mr);
     at.group = pick_group(mc);
     // the long-segment lists were built with these same limits (the
@@ -295,7 +315,14 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   e.sel.blk = P.alloc<int32_t>(select_scratch_blocks(dmax) + 64);
   e.red.part = P.alloc<double>(1024);
   e.red.cap = 1024;
-  e.part = P.alloc<double>(2 * (dmax / 4 + 1024) + 2 * (h->csr_nlong + h->csc_nlong));
+  if (h->nseg) {
+    e.seltmp = P.alloc<int32_t>(std::max(e.kc, e.kr) + 64);
+    e.selcnt = P.alloc<int64_t>(h->nseg + 1);
+    e.nseg = h->nseg;
+    e.seg = transpose ? h->seg_t : h->seg;
+  }
+  e.part = P.alloc<double>(2 * (dmax / 4 + 1024) +
+                           2 * (h->csr_nlong + h->csc_nlong) * h->rep);
   e.ready = true;
 }
 
@@ -321,8 +348,15 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
   const int64_t *cntJ = cntU + 1;
   const T *off = o.use_off ? e.off : nullptr;
 
-  if (o.stop == RGDBEK_STOP_ERR_REF)
-    launch_err_ref<T>(e.n, e.x, o.xref, o.xbase, e.red, c, 1, st);
+  const int ns = e.nseg;
+  if (o.stop == RGDBEK_STOP_ERR_REF) {
+    if (ns) {
+      launch_seg_err_ref<T>(e.x, o.xref, o.xbase, e.seg, ns, c, 1, st);
+      launch_seg_fold(e.seg, ns, c, 0, p.max_iter, 0, st);
+    } else {
+      launch_err_ref<T>(e.n, e.x, o.xref, o.xbase, e.red, c, 1, st);
+    }
+  }
   // ---- column phase: g = A^T z (+ t), eps^z, select U, project z
   if (e.dense) {
     launch_dense_fused<T>(e.arm, e.x, e.z, e.dw, off, e.kappa, e.g, e.eps_z,
@@ -332,8 +366,12 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     a.v = e.z; a.g = e.g; a.off = off; a.eps = e.eps_z; a.nrm = e.kappa;
     launch_segdot<T>(e.csc, EPI_COLRES, a, c, 1, st);
   }
-  launch_select<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0, e.sel,
-                   e.U, c, 1, st);
+  if (ns)
+    launch_select_seg<T>(e.eps_z, e.seg, ns, 0, e.floor, p.seed, o.key1, 0,
+                         e.sel.keys, e.seltmp, e.selcnt, e.U, c, 1, st);
+  else
+    launch_select<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0,
+                     e.sel, e.U, c, 1, st);
   const bool chol_c = p.solver == RGDBEK_SOLVER_CHOL ||
                       (p.solver == RGDBEK_SOLVER_AUTO && e.kc <= 256);
   const bool chol_r = p.solver == RGDBEK_SOLVER_CHOL ||
@@ -350,7 +388,7 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_pcg_gram_init<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, c, 0, 1,
                               st);
       for (int k = 0; k < maxs; ++k)
-        launch_pcg_gram_step<T>(e.GU, e.kc, cntU, e.y, e.cgc, itol, c, 0, 1,
+        launch_pcg_gram_step<T>(e.GU, e.kc, cntU, e.y, e.cgc, k, itol, c, 0, 1,
                                 st);
     }
     launch_col_update<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.y, e.z,
@@ -370,10 +408,20 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     a.nrm = e.rho; a.part = e.part;
     nparts = launch_segdot<T>(e.csr, EPI_ROWRES, a, c, 1, st);
   }
-  if (o.stop == RGDBEK_STOP_RSE || o.stop == RGDBEK_STOP_RES_EXT)
-    launch_stop_rowres(e.part, nparts, c, st);
-  launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1, e.sel,
-                   e.J, c, 1, st);
+  if (o.stop == RGDBEK_STOP_RSE || o.stop == RGDBEK_STOP_RES_EXT) {
+    if (ns) {
+      launch_seg_stop_rowres<T>(e.r, e.z, e.seg, ns, o.stop, c, 1, st);
+      launch_seg_fold(e.seg, ns, c, 0, p.max_iter, 0, st);
+    } else {
+      launch_stop_rowres(e.part, nparts, c, st);
+    }
+  }
+  if (ns)
+    launch_select_seg<T>(e.eps_x, e.seg, ns, 1, e.floor, p.seed, o.key1, 1,
+                         e.sel.keys, e.seltmp, e.selcnt, e.J, c, 1, st);
+  else
+    launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1,
+                     e.sel, e.J, c, 1, st);
   if (e.dense) {
     if (e.aat)
       launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
@@ -396,7 +444,7 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_pcg_gram_init<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, c, 1, 1,
                               st);
       for (int k = 0; k < maxs; ++k)
-        launch_pcg_gram_step<T>(e.GJ, e.kr, cntJ, e.w, e.cgr, itol, c, 1, 1,
+        launch_pcg_gram_step<T>(e.GJ, e.kr, cntJ, e.w, e.cgr, k, itol, c, 1, 1,
                                 st);
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
@@ -405,7 +453,8 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     launch_sparse_rowproj<T>(e.csr, e.csc, e.J, cntJ, e.kr, e.r, e.rho, e.x,
                              e.scr, maxs, itol, c, 1, st);
   }
-  launch_end_iter(c, st);
+  if (ns) launch_seg_fold(e.seg, ns, c, 1, p.max_iter, 0, st);
+  else launch_end_iter(c, st);
 }
 
 int graph_iters(const rgdbek_ctx *h) {
@@ -531,13 +580,25 @@ rgdbek_status solve64(rgdbek_ctx *h, Engine<double> &e, int which,
   ctrl_reset(h, it0, h->p.max_iter, stop, h->p.tol);
   if (stop == RGDBEK_STOP_ERR_REF) launch_set_ref2<double>(e.n, x_ref, h->ctrl, st);
   else launch_set_ref2<double>(e.m, e.b, h->ctrl, st);
+  if (e.nseg) {
+    launch_seg_reset(e.seg, e.nseg, it0, 0, nullptr, st);
+    if (stop == RGDBEK_STOP_ERR_REF) launch_seg_ref2<double>(x_ref, e.seg, e.nseg, 1, st);
+    else launch_seg_ref2<double>(e.b, e.seg, e.nseg, 0, st);
+  }
   IterOpts o;
   o.key1 = key1;
   o.stop = stop;
   o.xref = stop == RGDBEK_STOP_ERR_REF ? x_ref : nullptr;
   run_loop<double>(h, e, which, o);
-  if (stop == RGDBEK_STOP_ERR_REF)
-    launch_err_ref<double>(e.n, e.x, x_ref, nullptr, e.red, h->ctrl, 0, st);
+  if (stop == RGDBEK_STOP_ERR_REF) {
+    if (e.nseg) {
+      launch_seg_err_ref<double>(e.x, x_ref, nullptr, e.seg, e.nseg, h->ctrl,
+                                 0, st);
+      launch_seg_fold(e.seg, e.nseg, h->ctrl, 0, h->p.max_iter, 1, st);
+    } else {
+      launch_err_ref<double>(e.n, e.x, x_ref, nullptr, e.red, h->ctrl, 0, st);
+    }
+  }
   HIPCHK(hipMemcpyAsync(x, e.x, sizeof(double) * e.n, hipMemcpyDeviceToDevice, st));
   if (z_io)
     HIPCHK(hipMemcpyAsync(z_io, e.z, sizeof(double) * e.m, hipMemcpyDeviceToDevice, st));
@@ -575,6 +636,10 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
   check_b(h, b, E.m);
   HIPCHK(hipMemcpyAsync(E.b, b, sizeof(double) * E.m, hipMemcpyDeviceToDevice, st));
   launch_axpby<double, double>(E.n, 0.0, h->x64, 0.0, (const double *)nullptr, st);
+  if (E.nseg) {
+    HIPCHK(hipMemsetAsync(h->fixed, 0, sizeof(int32_t) * E.nseg, st));
+    launch_seg_reset(E.seg, E.nseg, 0, 0, nullptr, st);
+  }
   int64_t total_it = 0, outer = 0;
   const int max_outer = 12;
   double metric = 0.0, prev_metric = 1e300;
@@ -601,7 +666,20 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
       a.v = h->z64; a.g = h->t64; a.eps = E.eps_z; a.nrm = E.kappa;
       launch_segdot<double>(E.csc, EPI_COLRES, a, h->ctrl, 0, st);
     }
-    if (stop == RGDBEK_STOP_ERR_REF) {
+    if (E.nseg && stop != RGDBEK_STOP_NONE) {
+      launch_seg_reset(E.seg, E.nseg, 0, 1, nullptr, st);
+      if (stop == RGDBEK_STOP_ERR_REF) {
+        launch_seg_ref2<double>(x_ref, E.seg, E.nseg, 1, st);
+        launch_seg_err_ref<double>(h->x64, x_ref, nullptr, E.seg, E.nseg,
+                                   h->ctrl, 0, st);
+      } else {
+        launch_seg_ref2<double>(E.b, E.seg, E.nseg, 0, st);
+        launch_seg_stop_rowres<double>(h->z64, h->zero64, E.seg, E.nseg,
+                                       stop, h->ctrl, 0, st);
+      }
+      launch_seg_fold(E.seg, E.nseg, h->ctrl, 0, h->p.max_iter, 1, st);
+      launch_seg_converged(E.seg, E.nseg, h->fixed, st);
+    } else if (stop == RGDBEK_STOP_ERR_REF) {
       launch_set_ref2<double>(E.n, x_ref, h->ctrl, st);
       launch_err_ref<double>(E.n, h->x64, x_ref, nullptr, E.red, h->ctrl, 0, st);
     } else if (stop == RGDBEK_STOP_RSE) {
@@ -610,10 +688,14 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
     }
     ctrl_fetch(h);
     metric = h->hctrl->metric;
+    if (E.nseg && stop != RGDBEK_STOP_NONE && h->hctrl->converged) {
+      converged = true;
+      break;
+    }
     if (trace_on())
       std::fprintf(stderr, "[rgdbek] pass %lld fp64 metric %.3e (inner its so far %lld)\n",
                    (long long)outer, metric, (long long)total_it);
-    if (stop != RGDBEK_STOP_NONE && metric <= h->p.tol) {
+    if (!E.nseg && stop != RGDBEK_STOP_NONE && metric <= h->p.tol) {
       converged = true;
       break;
     }
@@ -633,6 +715,11 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
                istop == RGDBEK_STOP_ERR_REF ? h->p.tol : 0.0);
     if (istop == RGDBEK_STOP_ERR_REF) launch_set_ref2<double>(E.n, x_ref, h->ctrl, st);
     else launch_set_ref2<double>(E.m, E.b, h->ctrl, st);
+    if (E.nseg) {
+      launch_seg_reset(E.seg, E.nseg, 0, 1, h->fixed, st);
+      if (istop == RGDBEK_STOP_ERR_REF) launch_seg_ref2<double>(x_ref, E.seg, E.nseg, 1, st);
+      else launch_seg_ref2<double>(E.b, E.seg, E.nseg, 0, st);
+    }
     IterOpts o;
     o.key1 = 0;
     o.stop = istop;
@@ -769,6 +856,10 @@ void build_longs(rgdbek_ctx *h, const int64_t *ptr_dev, int64_t rows,
 void create_impl(rgdbek_ctx *h, const rgdbek_matrix *A) {
   hipStream_t st = h->st;
   Pool &P = h->pool;
+  if (h->dense && std::max(h->kc, h->kr) > pcg_cap_max())
+    throw ApiError{RGDBEK_ERR_UNSUPPORTED,
+                   "dense blocks larger than " + std::to_string(pcg_cap_max()) +
+                       " are not supported"};
   h->ctrl = P.alloc<Ctrl>(1);
   HIPCHK(hipHostMalloc((void **)&h->hctrl, sizeof(Ctrl), hipHostMallocDefault));
   int *flag = P.alloc<int>(1);
@@ -831,6 +922,12 @@ void create_impl(rgdbek_ctx *h, const rgdbek_matrix *A) {
   HIPCHK(hipMemcpyAsync(&hv, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (hv) throw ApiError{RGDBEK_ERR_NUMERIC, "matrix values contain NaN/Inf"};
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// Work space and engines for the (virtual) dimensions h->m x h->n.
+void build_engines(rgdbek_ctx *h) {
+  Pool &P = h->pool;
   h->xref = P.alloc<double>(std::max(h->m, h->n) + 64);
   build_engine<double>(h, h->e64, false);
   if (h->p.precision == RGDBEK_PREC_MIXED_F32) {
@@ -840,7 +937,26 @@ void create_impl(rgdbek_ctx *h, const rgdbek_matrix *A) {
     h->zero64 = P.alloc<double>(h->m + 64);
     h->t64 = P.alloc<double>(h->n + 64);
   }
-  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipStreamSynchronize(h->st));
+}
+
+// Device copies of the per-system state (forward and adjoint orientation).
+void upload_segments(rgdbek_ctx *h) {
+  const int ns = h->nseg;
+  h->seg = h->pool.alloc<SegInfo>(ns);
+  h->seg_t = h->pool.alloc<SegInfo>(ns);
+  h->fixed = h->pool.alloc<int32_t>(ns);
+  std::vector<SegInfo> t(h->hseg);
+  for (auto &g : t) {
+    std::swap(g.row_off, g.col_off);
+    std::swap(g.nrow, g.ncol);
+    std::swap(g.kc, g.kr);
+    std::swap(g.kc_off, g.kr_off);
+  }
+  HIPCHK(hipMemcpy(h->seg, h->hseg.data(), sizeof(SegInfo) * ns,
+                   hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->seg_t, t.data(), sizeof(SegInfo) * ns,
+                   hipMemcpyHostToDevice));
 }
 
 void destroy_impl(rgdbek_ctx *h) {
@@ -943,7 +1059,10 @@ rgdbek_status rgdbek_create(const rgdbek_matrix *A, const rgdbek_params *p,
       h->own_stream = true;
     }
     HIPCHK(hipStreamSynchronize(h->user_st));
+    h->bm = h->m;
+    h->bn = h->n;
     create_impl(h, A);
+    build_engines(h);
     return RGDBEK_OK;
   });
   if (s != RGDBEK_OK) {
@@ -953,6 +1072,216 @@ rgdbek_status rgdbek_create(const rgdbek_matrix *A, const rgdbek_params *p,
   }
   *out = h;
   return RGDBEK_OK;
+}
+
+rgdbek_status rgdbek_create_batched(const rgdbek_matrix *A, int64_t nsys,
+                                    const int64_t *row_off,
+                                    const int64_t *col_off,
+                                    const rgdbek_params *p, void *stream,
+                                    rgdbek_handle *out) {
+  g_global_err.clear();
+  if (!out) { set_err(nullptr, "out is NULL"); return RGDBEK_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (!A || !p || !row_off || !col_off || nsys < 1 || nsys > (1 << 20)) {
+    set_err(nullptr, "A, p, row_off, col_off required and 1 <= nsys <= 2^20");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (A->layout != RGDBEK_CSR) {
+    set_err(nullptr, "batched systems are stored block-diagonally in CSR");
+    return RGDBEK_ERR_UNSUPPORTED;
+  }
+  if (row_off[0] != 0 || col_off[0] != 0 || row_off[nsys] != A->m ||
+      col_off[nsys] != A->n) {
+    set_err(nullptr, "row_off/col_off must start at 0 and end at m/n");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  for (int64_t s = 0; s < nsys; ++s)
+    if (row_off[s + 1] <= row_off[s] || col_off[s + 1] <= col_off[s]) {
+      set_err(nullptr, "every system needs at least one row and one column");
+      return RGDBEK_ERR_INVALID_ARG;
+    }
+  rgdbek_params q = *p;
+  std::vector<SegInfo> segs(nsys);
+  int64_t kc_tot = 0, kr_tot = 0;
+  auto bs = [&](int64_t kfix, int64_t d) -> int64_t {
+    if (kfix > 0) return std::min<int64_t>(kfix, d);
+    int64_t k = (int64_t)std::floor(p->eta * (double)d + 0.5);
+    return std::min<int64_t>(d, std::max<int64_t>(1, k));
+  };
+  for (int64_t s = 0; s < nsys; ++s) {
+    SegInfo g{};
+    g.row_off = row_off[s];
+    g.nrow = row_off[s + 1] - row_off[s];
+    g.col_off = col_off[s];
+    g.ncol = col_off[s + 1] - col_off[s];
+    g.kc = bs(p->k_col, g.ncol);
+    g.kr = bs(p->k_row, g.nrow);
+    g.kc_off = kc_tot;
+    g.kr_off = kr_tot;
+    kc_tot += g.kc;
+    kr_tot += g.kr;
+    segs[s] = g;
+  }
+  q.k_col = kc_tot;
+  q.k_row = kr_tot;
+  rgdbek_ctx *h = new (std::nothrow) rgdbek_ctx();
+  if (!h) { set_err(nullptr, "host allocation failed"); return RGDBEK_ERR_OUT_OF_MEMORY; }
+  h->m = A->m;
+  h->n = A->n;
+  h->dense = false;
+  h->nnz = A->nnz;
+  h->p = q;
+  h->user_st = (hipStream_t)stream;
+  h->nseg = (int)nsys;
+  h->hseg = segs;
+  rgdbek_status st = guarded(nullptr, [&]() {
+    int64_t kc, kr;
+    validate_params(&q, h->m, h->n, &kc, &kr);
+    h->kc = kc_tot;
+    h->kr = kr_tot;
+    if (!A->row_ptr || (!A->col_idx && A->nnz > 0) || !A->values || A->nnz < 0 ||
+        A->nnz > INT32_MAX || A->m > INT32_MAX || A->n > INT32_MAX)
+      throw ApiError{RGDBEK_ERR_INVALID_ARG, "CSR arrays and sizes required"};
+    // block-diagonal structure: every row's columns inside its system
+    std::vector<int64_t> rp(A->m + 1);
+    std::vector<int32_t> ci(A->nnz);
+    HIPCHK(hipMemcpy(rp.data(), A->row_ptr, 8 * (A->m + 1), hipMemcpyDeviceToHost));
+    if (A->nnz)
+      HIPCHK(hipMemcpy(ci.data(), A->col_idx, 4 * A->nnz, hipMemcpyDeviceToHost));
+    for (int64_t s = 0; s < nsys; ++s)
+      for (int64_t i = row_off[s]; i < row_off[s + 1]; ++i)
+        for (int64_t e = rp[i]; e < rp[i + 1] && e < A->nnz; ++e)
+          if (ci[e] < col_off[s] || ci[e] >= col_off[s + 1])
+            throw ApiError{RGDBEK_ERR_INVALID_ARG,
+                           "row " + std::to_string(i) + " leaves its system's columns"};
+    if (h->user_st) {
+      h->st = h->user_st;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    h->bm = h->m;
+    h->bn = h->n;
+    create_impl(h, A);
+    upload_segments(h);
+    build_engines(h);
+    return RGDBEK_OK;
+  });
+  if (st != RGDBEK_OK) {
+    destroy_impl(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return RGDBEK_OK;
+}
+
+rgdbek_status rgdbek_create_multirhs(const rgdbek_matrix *A, int64_t nrhs,
+                                     const rgdbek_params *p, void *stream,
+                                     rgdbek_handle *out) {
+  g_global_err.clear();
+  if (!out) { set_err(nullptr, "out is NULL"); return RGDBEK_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (!A || !p || nrhs < 1 || nrhs > 4096) {
+    set_err(nullptr, "A and p required, 1 <= nrhs <= 4096");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (A->layout != RGDBEK_CSR) {
+    set_err(nullptr, "right-hand-side batches share a CSR matrix");
+    return RGDBEK_ERR_UNSUPPORTED;
+  }
+  if (A->m <= 0 || A->n <= 0 || A->m * nrhs > INT32_MAX ||
+      A->n * nrhs > INT32_MAX || !A->values || !A->row_ptr ||
+      (!A->col_idx && A->nnz > 0) || A->nnz < 0 || A->nnz > INT32_MAX) {
+    set_err(nullptr, "CSR arrays required; nrhs * m and nrhs * n < 2^31");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  auto bs = [&](int64_t kfix, int64_t d) -> int64_t {
+    if (kfix > 0) return std::min<int64_t>(kfix, d);
+    int64_t k = (int64_t)std::floor(p->eta * (double)d + 0.5);
+    return std::min<int64_t>(d, std::max<int64_t>(1, k));
+  };
+  const int64_t kc = bs(p->k_col, A->n), kr = bs(p->k_row, A->m);
+  std::vector<SegInfo> segs(nrhs);
+  for (int64_t s = 0; s < nrhs; ++s) {
+    SegInfo g{};
+    g.row_off = s * A->m; g.nrow = A->m;
+    g.col_off = s * A->n; g.ncol = A->n;
+    g.kc = kc; g.kr = kr;
+    g.kc_off = s * kc; g.kr_off = s * kr;
+    segs[s] = g;
+  }
+  rgdbek_params q = *p;
+  q.k_col = kc;
+  q.k_row = kr;
+  rgdbek_ctx *h = new (std::nothrow) rgdbek_ctx();
+  if (!h) { set_err(nullptr, "host allocation failed"); return RGDBEK_ERR_OUT_OF_MEMORY; }
+  h->m = A->m;
+  h->n = A->n;
+  h->bm = A->m;
+  h->bn = A->n;
+  h->dense = false;
+  h->nnz = A->nnz;
+  h->p = q;
+  h->user_st = (hipStream_t)stream;
+  h->nseg = (int)nrhs;
+  h->rep = nrhs;
+  h->hseg = segs;
+  rgdbek_status st = guarded(nullptr, [&]() {
+    int64_t k1, k2;
+    validate_params(&q, A->m, A->n, &k1, &k2);
+    if (h->user_st) {
+      h->st = h->user_st;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+    HIPCHK(hipStreamSynchronize(h->user_st));
+    create_impl(h, A);
+    // the batch sees I_nrhs (x) A: replicate the norms, widen the dimensions
+    double *rho = h->pool.alloc<double>(A->m * nrhs, false);
+    double *kap = h->pool.alloc<double>(A->n * nrhs, false);
+    launch_replicate(h->rho, A->m, nrhs, rho, h->st);
+    launch_replicate(h->kappa, A->n, nrhs, kap, h->st);
+    h->rho = rho;
+    h->kappa = kap;
+    h->m = A->m * nrhs;
+    h->n = A->n * nrhs;
+    h->kc = kc * nrhs;
+    h->kr = kr * nrhs;
+    upload_segments(h);
+    build_engines(h);
+    return RGDBEK_OK;
+  });
+  if (st != RGDBEK_OK) {
+    destroy_impl(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return RGDBEK_OK;
+}
+
+rgdbek_status rgdbek_batch_info(rgdbek_handle h, int64_t *iterations,
+                                double *metric, int32_t *converged) {
+  if (!h) return RGDBEK_ERR_INVALID_ARG;
+  if (!h->nseg) {
+    set_err(h, "not a batched handle");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  return guarded(h, [&]() {
+    std::vector<SegInfo> g(h->nseg);
+    HIPCHK(hipMemcpyAsync(g.data(), h->seg, sizeof(SegInfo) * h->nseg,
+                          hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (int s = 0; s < h->nseg; ++s) {
+      if (iterations) iterations[s] = g[s].iters_run;
+      if (metric) metric[s] = g[s].metric;
+      if (converged) converged[s] = g[s].converged;
+    }
+    return RGDBEK_OK;
+  });
 }
 
 rgdbek_status rgdbek_solve(rgdbek_handle h, const void *b, void *x,
@@ -1039,7 +1368,8 @@ rgdbek_status rgdbek_grad_pattern(rgdbek_handle h, const void *r,
                                 (const double *)lam, (const double *)w,
                                 (const double *)x, (double *)dA_values, h->st);
     else
-      launch_grad_pattern_csr(h->m, h->csr_ptr, h->csr_idx, (const double *)r,
+      launch_grad_pattern_csr(h->bm, h->bn, h->rep, h->csr_ptr, h->csr_idx,
+                              (const double *)r,
                               (const double *)lam, (const double *)w,
                               (const double *)x, (double *)dA_values, h->st);
     HIPCHK(hipStreamSynchronize(h->st));

@@ -132,15 +132,16 @@ __device__ __forceinline__ int64_t compact_chunk(const uint64_t *keys,
 }
 
 // ------------------------------------------------ one-workgroup selection
-// keys: scratch of d entries.  Writes out[0..count) and ctrl->sel_count[ph].
+// One workgroup of 1024 threads draws the block from d weights.  keys:
+// scratch of d entries; writes out[0..count) (local indices), returns count
+// (the same value in every thread); raises *numeric on a bad weight.
 template <typename T>
-__global__ void __launch_bounds__(1024)
-sel_small(const T *__restrict__ eps, int64_t d, int64_t k, double floor,
-          uint64_t seed, uint64_t key1, int ph, uint32_t phase, uint32_t sys,
-          uint64_t *__restrict__ keys, int32_t *__restrict__ out, Ctrl *ctrl,
-          int respect_done) {
+__device__ int64_t select_wg(const T *__restrict__ eps, int64_t d, int64_t k,
+                             double floor, uint64_t seed, uint64_t key1,
+                             uint64_t it, uint32_t phase, uint32_t sys,
+                             uint64_t *__restrict__ keys,
+                             int32_t *__restrict__ out, int *numeric) {
   constexpr int NT = 1024;
-  if (respect_done && ctrl_done(ctrl)) return;
   __shared__ unsigned hist[256];
   __shared__ int64_t sh64[NT / WAVE];
   __shared__ int wtot[NT / WAVE];
@@ -148,7 +149,11 @@ sel_small(const T *__restrict__ eps, int64_t d, int64_t k, double floor,
   __shared__ int64_t s_krem, s_tidx;
   __shared__ int s_done;
   __shared__ double shmax[NT / WAVE];
-  const uint64_t it = (uint64_t)ctrl->it;
+  constexpr int SS = 2048;        // samples
+  constexpr int SW = 64;          // bracket half-width in sample ranks
+  constexpr int SCAND = 8192;     // largest bracket sorted in LDS
+  __shared__ uint64_t s_samp_key[SCAND];
+  __shared__ int32_t s_cand_idx[SCAND];
   double mx = 0.0;
   for (int64_t j = threadIdx.x; j < d; j += NT) {
     const double e = (double)eps[j];
@@ -174,15 +179,110 @@ sel_small(const T *__restrict__ eps, int64_t d, int64_t k, double floor,
       }
     }
   }
-  if (bad) atomicOr(&ctrl->numeric, 1);
+  if (bad) atomicOr(numeric, 1);
   pos = block_sum_i64<NT>(pos, sh64);
   __syncthreads();   // keys visible to the whole workgroup
 
   uint64_t lo, tkey;
   int64_t tidx;
+  bool resolved = false;
   if (pos <= k) {
     lo = SENT; tkey = SENT; tidx = -1;
+    resolved = true;
   } else {
+    // Sample select: sort SS keys taken at fixed positions, bracket the rank
+    // k by sample ranks +-SW, count the keys below and inside the bracket,
+    // gather the bracket in index order and sort it.  Any miss falls back
+    // to the radix select below (same result, slower).
+    uint64_t *sk = s_samp_key;
+    const int64_t p_est = (k * SS) / d;
+    for (int i = threadIdx.x; i < SS; i += NT)
+      sk[i] = keys[((int64_t)i * d) / SS];
+    __syncthreads();
+    for (int size = 2; size <= SS; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < SS; i += NT) {
+          const int q = i ^ stride;
+          if (q > i) {
+            const uint64_t a = sk[i], b = sk[q];
+            if ((a > b) == ((i & size) == 0)) { sk[i] = b; sk[q] = a; }
+          }
+        }
+        __syncthreads();
+      }
+    const int64_t il = p_est - SW, ih = p_est + SW;
+    const uint64_t wlo = il <= 0 ? 0ull : sk[il];
+    const uint64_t whi = ih >= SS ? SENT - 1 : sk[ih];
+    __syncthreads();
+    int64_t clt = 0, cwin = 0;
+    for (int64_t j = threadIdx.x; j < d; j += NT) {
+      const uint64_t kk = keys[j];
+      if (kk == SENT) continue;
+      clt += kk < wlo;
+      cwin += (kk >= wlo && kk <= whi);
+    }
+    clt = block_sum_i64<NT>(clt, sh64);
+    cwin = block_sum_i64<NT>(cwin, sh64);
+    if (clt < k && k <= clt + cwin && cwin <= SCAND) {
+      // gather the bracket in index order (ballot compaction)
+      uint64_t *ck = s_samp_key;
+      int32_t *ci = s_cand_idx;
+      int64_t off = 0;
+      for (int64_t base = 0; base < d; base += NT) {
+        const int64_t j = base + threadIdx.x;
+        const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+        bool f = false;
+        uint64_t kk = 0;
+        if (j < d) {
+          kk = keys[j];
+          f = kk != SENT && kk >= wlo && kk <= whi;
+        }
+        const uint64_t mask = __ballot(f);
+        __syncthreads();
+        if (lane == 0) wtot[wv] = __popcll(mask);
+        __syncthreads();
+        int wb = 0, tot = 0;
+        for (int i = 0; i < NT / WAVE; ++i) {
+          if (i < wv) wb += wtot[i];
+          tot += wtot[i];
+        }
+        if (f) {
+          const int64_t slot = off + wb + __popcll(mask & ((1ull << lane) - 1ull));
+          ck[slot] = kk;
+          ci[slot] = (int32_t)j;
+        }
+        off += tot;
+      }
+      int np2 = 1;
+      while (np2 < cwin) np2 <<= 1;
+      for (int64_t i = cwin + threadIdx.x; i < np2; i += NT) {
+        ck[i] = SENT;
+        ci[i] = INT32_MAX;
+      }
+      __syncthreads();
+      for (int size = 2; size <= np2; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          for (int i = threadIdx.x; i < np2; i += NT) {
+            const int q = i ^ stride;
+            if (q > i) {
+              const uint64_t a = ck[i], b = ck[q];
+              const int32_t ai = ci[i], bi = ci[q];
+              const bool gt = (a > b) || (a == b && ai > bi);
+              if (gt == ((i & size) == 0)) {
+                ck[i] = b; ck[q] = a; ci[i] = bi; ci[q] = ai;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      tkey = ck[k - clt - 1];
+      tidx = ci[k - clt - 1];
+      lo = tkey;
+      resolved = true;
+      __syncthreads();
+    }
+  }
+  if (!resolved) {
     // MSB-first radix select of the k-th smallest key, 8 bits per pass.
     if (threadIdx.x == 0) { s_prefix = 0; s_krem = k; s_done = 0; }
     int shift = 64;
@@ -255,7 +355,71 @@ sel_small(const T *__restrict__ eps, int64_t d, int64_t k, double floor,
   int64_t off = 0;
   for (int64_t base = 0; base < d; base += NT)
     off += compact_chunk<NT>(keys, base, d, lo, tkey, tidx, out, off, wtot);
-  if (threadIdx.x == 0) ctrl->sel_count[ph] = off;
+  return off;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+sel_small(const T *__restrict__ eps, int64_t d, int64_t k, double floor,
+          uint64_t seed, uint64_t key1, int ph, uint32_t phase, uint32_t sys,
+          uint64_t *__restrict__ keys, int32_t *__restrict__ out, Ctrl *ctrl,
+          int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t cnt = select_wg<T>(eps, d, k, floor, seed, key1,
+                                   (uint64_t)ctrl->it, phase, sys, keys, out,
+                                   &ctrl->numeric);
+  if (threadIdx.x == 0) ctrl->sel_count[ph] = cnt;
+}
+
+// Per-system draws of a batch: workgroup s draws from the weights of system
+// s (eps[off_s .. off_s + d_s)) with its own block size, iteration counter
+// and generator stream (system id in counter word 3); a finished system
+// draws nothing.  Local indices go to tmp[koff_s ..]; counts to cnt[s].
+template <typename T>
+__global__ void __launch_bounds__(1024)
+sel_seg(const T *__restrict__ eps, const SegInfo *__restrict__ seg, int ph,
+        double floor, uint64_t seed, uint64_t key1, uint32_t phase,
+        uint64_t *__restrict__ keys, int32_t *__restrict__ tmp,
+        int64_t *__restrict__ cnt, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const SegInfo &g = seg[blockIdx.x];
+  if (g.done) {
+    if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
+    return;
+  }
+  const int64_t off = ph == 0 ? g.col_off : g.row_off;
+  const int64_t d = ph == 0 ? g.ncol : g.nrow;
+  const int64_t k = ph == 0 ? g.kc : g.kr;
+  const int64_t ko = ph == 0 ? g.kc_off : g.kr_off;
+  const int64_t c = select_wg<T>(eps + off, d, k, floor, seed, key1,
+                                 (uint64_t)g.it, phase, (uint32_t)blockIdx.x,
+                                 keys + off, tmp + ko, &ctrl->numeric);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+}
+
+// Concatenate the per-system draws into one list of global indices and set
+// Ctrl::sel_count[ph] to the total.
+__global__ void __launch_bounds__(256)
+sel_seg_pack(const SegInfo *__restrict__ seg, int nseg, int ph,
+             const int32_t *__restrict__ tmp, const int64_t *__restrict__ cnt,
+             int32_t *__restrict__ out, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ int64_t sh64[256 / WAVE];
+  const int s = blockIdx.x;
+  int64_t before = 0, total = 0;
+  for (int q = threadIdx.x; q < nseg; q += 256) {
+    total += cnt[q];
+    if (q < s) before += cnt[q];
+  }
+  before = block_sum_i64<256>(before, sh64);
+  total = block_sum_i64<256>(total, sh64);
+  const SegInfo &g = seg[s];
+  const int64_t off = ph == 0 ? g.col_off : g.row_off;
+  const int64_t ko = ph == 0 ? g.kc_off : g.kr_off;
+  const int64_t c = cnt[s];
+  for (int64_t a = threadIdx.x; a < c; a += 256)
+    out[before + a] = (int32_t)(tmp[ko + a] + off);
+  if (s == 0 && threadIdx.x == 0) ctrl->sel_count[ph] = total;
 }
 
 // ------------------------------------------------ multi-workgroup selection
@@ -644,5 +808,28 @@ template void launch_select<float>(const float *, int64_t, int64_t, double,
 int64_t select_scratch_blocks(int64_t d) {
   return (d + SEL_CHUNK - 1) / SEL_CHUNK;
 }
+
+template <typename T>
+void launch_select_seg(const T *eps, const SegInfo *seg, int nseg, int ph,
+                       double floor, uint64_t seed, uint64_t key1,
+                       uint32_t phase, uint64_t *keys, int32_t *tmp,
+                       int64_t *cnt, int32_t *out, Ctrl *ctrl,
+                       int respect_done, hipStream_t st) {
+  hipLaunchKernelGGL(sel_seg<T>, dim3(nseg), dim3(1024), 0, st, eps, seg, ph,
+                     floor, seed, key1, phase, keys, tmp, cnt, ctrl,
+                     respect_done);
+  hipLaunchKernelGGL(sel_seg_pack, dim3(nseg), dim3(256), 0, st, seg, nseg, ph,
+                     tmp, cnt, out, ctrl, respect_done);
+}
+template void launch_select_seg<double>(const double *, const SegInfo *, int,
+                                        int, double, uint64_t, uint64_t,
+                                        uint32_t, uint64_t *, int32_t *,
+                                        int64_t *, int32_t *, Ctrl *, int,
+                                        hipStream_t);
+template void launch_select_seg<float>(const float *, const SegInfo *, int,
+                                       int, double, uint64_t, uint64_t,
+                                       uint32_t, uint64_t *, int32_t *,
+                                       int64_t *, int32_t *, Ctrl *, int,
+                                       hipStream_t);
 
 }  // namespace rg

@@ -55,16 +55,22 @@ segdot_kernel(Csr<T> A, SegArgs<T> a, Ctrl *ctrl, int respect_done) {
   const bool listed = (a.list != nullptr);
   const int64_t nseg = listed ? *a.count_dev : A.rows;
   bool active = slot < nseg;
-  int64_t s = 0;
+  int64_t s = 0, br = 0, co = 0;
   T acc = (T)0;
   if (active) {
-    s = listed ? (int64_t)a.list[slot] : slot;
-    const int64_t e0 = A.ptr[s], e1 = A.ptr[s + 1];
+    if (listed) {
+      s = (int64_t)a.list[slot];
+      gsplit(A, s, br, co);
+    } else {
+      vrow(A, slot, s, br, co);
+    }
+    const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
     if (!listed && A.long_limit > 0 && e1 - e0 > A.long_limit) {
       active = false;   // handled by segdot_long
     } else {
+      const T *v = a.v + co;
       for (int64_t e = e0 + lg; e < e1; e += G)
-        acc += A.val[e] * a.v[A.idx[e]];
+        acc += A.val[e] * v[A.idx[e]];
     }
   }
   acc = group_sum<G>(acc);
@@ -88,11 +94,14 @@ segdot_long(Csr<T> A, SegArgs<T> a, int64_t part_base, Ctrl *ctrl,
             int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   __shared__ double sh[SEG_NT / WAVE];
-  const int64_t s = A.longs[blockIdx.x];
-  const int64_t e0 = A.ptr[s], e1 = A.ptr[s + 1];
+  const int64_t li = blockIdx.x / A.rep, rs = blockIdx.x - li * A.rep;
+  const int64_t br = A.longs[li];
+  const int64_t s = rs * A.brows + br;
+  const T *v = a.v + rs * A.bcols;
+  const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
   T acc = (T)0;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += SEG_NT)
-    acc += A.val[e] * a.v[A.idx[e]];
+    acc += A.val[e] * v[A.idx[e]];
   const double tot = block_sum<SEG_NT>((double)acc, sh);
   double pb = 0.0, pr = 0.0;
   if (threadIdx.x == 0) seg_epilogue<T>(EPI, a, s, s, (T)tot, pb, pr);
@@ -124,10 +133,10 @@ static int segdot_dispatch(const Csr<T> &A, const SegArgs<T> &a, Ctrl *ctrl,
     nparts = nb;
   }
   if (!a.list && A.nlong > 0) {
-    hipLaunchKernelGGL((segdot_long<T, EPI>), dim3((unsigned)A.nlong),
+    hipLaunchKernelGGL((segdot_long<T, EPI>), dim3((unsigned)(A.nlong * A.rep)),
                        dim3(SEG_NT), 0, st, A, a, (int64_t)nparts, ctrl,
                        respect_done);
-    nparts += (int)A.nlong;
+    nparts += (int)(A.nlong * A.rep);
   }
   return nparts;
 }

@@ -221,25 +221,43 @@ void launch_csr_to_csc(int64_t m, int64_t n, int64_t nnz, const int64_t *rp,
 
 // ------------------------------------------------------------ gradient
 __global__ void __launch_bounds__(256)
-grad_csr_kernel(int64_t m, const int64_t *__restrict__ rp,
-                const int32_t *__restrict__ ci, const double *__restrict__ r,
-                const double *__restrict__ lam, const double *__restrict__ w,
-                const double *__restrict__ x, double *__restrict__ dA) {
+grad_csr_kernel(int64_t m, int64_t n, int64_t rep,
+                const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                const double *__restrict__ r, const double *__restrict__ lam,
+                const double *__restrict__ w, const double *__restrict__ x,
+                double *__restrict__ dA) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
   if (i >= m) return;
-  const double ri = lam ? r[i] : 0.0, wi = w[i];
   for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += WAVE) {
-    const int32_t j = ci[e];
-    dA[e] = (lam ? ri * lam[j] : 0.0) - wi * x[j];
+    const int64_t j = ci[e];
+    double acc = 0.0;
+    for (int64_t s = 0; s < rep; ++s) {
+      const int64_t gi = s * m + i, gj = s * n + j;
+      acc += (lam ? r[gi] * lam[gj] : 0.0) - w[gi] * x[gj];
+    }
+    dA[e] = acc;
   }
 }
-void launch_grad_pattern_csr(int64_t m, const int64_t *rp, const int32_t *ci,
+void launch_grad_pattern_csr(int64_t m, int64_t n, int64_t rep,
+                             const int64_t *rp, const int32_t *ci,
                              const double *r, const double *lam,
                              const double *w, const double *x, double *dA,
                              hipStream_t st) {
   hipLaunchKernelGGL(grad_csr_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256),
-                     0, st, m, rp, ci, r, lam, w, x, dA);
+                     0, st, m, n, rep, rp, ci, r, lam, w, x, dA);
+}
+__global__ void replicate_kernel(const double *__restrict__ in, int64_t len,
+                                 int64_t rep, double *__restrict__ out) {
+  const int64_t tot = len * rep;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < tot;
+       t += (int64_t)gridDim.x * 256)
+    out[t] = in[t % len];
+}
+void launch_replicate(const double *in, int64_t len, int64_t rep, double *out,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(replicate_kernel, dim3(grid_for(len * rep, 256, 8192)),
+                     dim3(256), 0, st, in, len, rep, out);
 }
 __global__ void __launch_bounds__(256)
 grad_dense_kernel(int64_t m, int64_t n, const double *__restrict__ r,

@@ -168,6 +168,121 @@ class Solver:
         self.close()
 
 
+class BatchSolver(Solver):
+    """Many independent sparse systems solved together (block-diagonal CSR
+    with global indices; system s owns rows row_off[s]:row_off[s+1] and
+    columns col_off[s]:col_off[s+1]).  Vectors are the systems' vectors
+    concatenated.  Keyword arguments as for Solver (eta/k_col/k_row give
+    each system's block sizes)."""
+
+    def __init__(self, csr, row_off, col_off, *, eta=0.1, k_col=0, k_row=0,
+                 tol=1e-8, stop="err_ref", max_iter=10000, seed=0,
+                 precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
+                 graph=True, weight_floor=0.0, stream=None):
+        lib = B.load()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        rp, ci, val = csr
+        _need_cuda(rp, "row_ptr", torch.int64)
+        _need_cuda(ci, "col_idx", torch.int32)
+        _need_cuda(val, "values")
+        ro = (ctypes.c_int64 * len(row_off))(*[int(v) for v in row_off])
+        co = (ctypes.c_int64 * len(col_off))(*[int(v) for v in col_off])
+        self.nsys = len(row_off) - 1
+        m, n = int(row_off[-1]), int(col_off[-1])
+        mat = B.Matrix()
+        mat.m, mat.n, mat.nnz = m, n, val.numel()
+        mat.layout = B.CSR
+        mat.row_ptr, mat.col_idx, mat.values = _ptr(rp), _ptr(ci), _ptr(val)
+        mat.value_type = B.F64 if val.dtype == torch.float64 else B.F32
+        p = B.Params()
+        B.check(lib.rgdbek_params_default(ctypes.byref(p)))
+        p.k_col, p.k_row, p.eta, p.tol = k_col, k_row, eta, tol
+        p.stop = B.STOP_NAMES[stop] if isinstance(stop, str) else int(stop)
+        p.precision = (B.PREC_NAMES[precision] if isinstance(precision, str)
+                       else int(precision))
+        p.max_iter, p.seed = max_iter, seed
+        p.inner_max, p.inner_tol, p.graph_iters = inner_max, inner_tol, graph_iters
+        p.flags = B.FLAG_GRAPH if graph else 0
+        p.weight_floor = float(weight_floor)
+        self.m, self.n, self.params, self.stream = m, n, p, stream
+        st = lib.rgdbek_create_batched(ctypes.byref(mat), self.nsys, ro, co,
+                                       ctypes.byref(p), _stream(stream),
+                                       ctypes.byref(self._h))
+        B.check(st, None)
+
+    def batch_info(self):
+        it = (ctypes.c_int64 * self.nsys)()
+        met = (ctypes.c_double * self.nsys)()
+        cv = (ctypes.c_int32 * self.nsys)()
+        B.check(self._lib.rgdbek_batch_info(self._h, it, met, cv), self._h)
+        return list(it), list(met), list(cv)
+
+
+class MultiRhsSolver(BatchSolver):
+    """One sparse matrix, many right-hand sides (RHS-major vectors:
+    b[s*m + i], x[s*n + j]); A is stored once and every pass over it serves
+    all right-hand sides."""
+
+    def __init__(self, csr, shape, nrhs, *, eta=0.1, k_col=0, k_row=0,
+                 tol=1e-8, stop="err_ref", max_iter=10000, seed=0,
+                 precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
+                 graph=True, weight_floor=0.0, stream=None):
+        lib = B.load()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        rp, ci, val = csr
+        _need_cuda(rp, "row_ptr", torch.int64)
+        _need_cuda(ci, "col_idx", torch.int32)
+        _need_cuda(val, "values")
+        m, n = shape
+        mat = B.Matrix()
+        mat.m, mat.n, mat.nnz = m, n, val.numel()
+        mat.layout = B.CSR
+        mat.row_ptr, mat.col_idx, mat.values = _ptr(rp), _ptr(ci), _ptr(val)
+        mat.value_type = B.F64 if val.dtype == torch.float64 else B.F32
+        p = B.Params()
+        B.check(lib.rgdbek_params_default(ctypes.byref(p)))
+        p.k_col, p.k_row, p.eta, p.tol = k_col, k_row, eta, tol
+        p.stop = B.STOP_NAMES[stop] if isinstance(stop, str) else int(stop)
+        p.precision = (B.PREC_NAMES[precision] if isinstance(precision, str)
+                       else int(precision))
+        p.max_iter, p.seed = max_iter, seed
+        p.inner_max, p.inner_tol, p.graph_iters = inner_max, inner_tol, graph_iters
+        p.flags = B.FLAG_GRAPH if graph else 0
+        p.weight_floor = float(weight_floor)
+        self.nsys = int(nrhs)
+        self.base_shape = (int(m), int(n))
+        self.m, self.n, self.params, self.stream = m * nrhs, n * nrhs, p, stream
+        st = lib.rgdbek_create_multirhs(ctypes.byref(mat), int(nrhs),
+                                        ctypes.byref(p), _stream(stream),
+                                        ctypes.byref(self._h))
+        B.check(st, None)
+
+
+def block_diagonal(mats):
+    """Concatenate scipy sparse systems into block-diagonal CSR arrays with
+    global indices; returns (row_ptr, col_idx, values, row_off, col_off)."""
+    import numpy as np
+    import scipy.sparse as sp
+    rps, cis, vals = [], [], []
+    row_off, col_off = [0], [0]
+    nnz = 0
+    for a in mats:
+        c = sp.csr_matrix(a)
+        c.sort_indices()
+        rps.append(c.indptr[1:] + nnz if rps else c.indptr + nnz)
+        cis.append(c.indices.astype(np.int64) + col_off[-1])
+        vals.append(c.data)
+        nnz += c.nnz
+        row_off.append(row_off[-1] + c.shape[0])
+        col_off.append(col_off[-1] + c.shape[1])
+    rp = np.concatenate(rps).astype(np.int64)
+    ci = np.concatenate(cis).astype(np.int32)
+    v = np.concatenate(vals)
+    return rp, ci, v, row_off, col_off
+
+
 def select(eps, k, seed=0, it=0, phase=0, sys=0, key1=0, floor=1e-20,
            stream=None):
     """Block draw on given weights (device FP64 tensor): ascending int32

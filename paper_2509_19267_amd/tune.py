@@ -36,11 +36,29 @@ def store(layout, m, n, choice):
         pass
 
 
+def _time_solve(a, b, x_ref, choice, *, stream, tol, precision, reps):
+    from .solver import Solver
+    s = Solver(a, k_col=choice["k_col"], k_row=choice["k_row"],
+               gram_aat=choice.get("gram_aat", False), stop="err_ref",
+               tol=tol, max_iter=5000, precision=precision, stream=stream,
+               inner_tol=choice.get("inner_tol", 0.0),
+               inner_max=choice.get("inner_max", 0))
+    ts, ok, its = [], True, 0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        _, info = s.solve(b, x_ref=x_ref)
+        ts.append(time.perf_counter() - t0)
+        ok = ok and bool(info["converged"])
+        its = info["iterations"]
+    s.close()
+    return min(ts), ok, its
+
+
 def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
                grid=None, precision="fp64", reps=2):
-    """Sweep (k_col, k_row, gram_aat) for a dense A (device tensors);
-    returns and caches the fastest choice."""
-    from .solver import Solver
+    """Sweep block sizes (k_col, k_row, A A^T precomputed or not), then the
+    inner CG tolerance and step cap, for a dense A (device tensors); returns
+    and caches the fastest converging choice."""
     m, n = a.shape
     if grid is None:
         fr = [0.02, 0.05, 0.1, 0.2]
@@ -49,30 +67,36 @@ def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
             for frw in fr:
                 kc = max(1, int(fc * n))
                 kr = max(1, min(int(frw * n), m))
-                grid.append((kc, kr, kr > 256))
+                grid.append(dict(k_col=kc, k_row=kr, gram_aat=kr > 256,
+                                 inner_tol=1e-10, inner_max=48))
     best = None
-    for kc, kr, aat in grid:
+    for ch in grid:
         try:
-            s = Solver(a, k_col=kc, k_row=kr, gram_aat=aat, stop="err_ref",
-                       tol=tol, max_iter=5000, precision=precision,
-                       stream=stream)
+            t, ok, its = _time_solve(a, b, x_ref, ch, stream=stream, tol=tol,
+                                     precision=precision, reps=reps)
         except Exception as e:  # noqa: BLE001
-            log(f"tune {kc},{kr},{aat}: create failed: {e}")
+            log(f"tune {ch}: failed: {e}")
             continue
-        ts = []
-        ok = True
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            _, info = s.solve(b, x_ref=x_ref)
-            ts.append(time.perf_counter() - t0)
-            ok = ok and bool(info["converged"])
-        s.close()
-        t = min(ts)
-        log(f"tune k_col={kc} k_row={kr} gram_aat={aat}: {1e3*t:.1f} ms "
-            f"({info['iterations']} it, converged={ok})")
+        log(f"tune {ch}: {1e3*t:.1f} ms ({its} it, converged={ok})")
         if ok and (best is None or t < best[0]):
-            best = (t, dict(k_col=kc, k_row=kr, gram_aat=aat))
+            best = (t, ch)
     if best is None:
         raise RuntimeError("no configuration converged")
+    base = best[1]
+    for itol in [1e-14, 1e-10, 1e-8, 1e-6]:
+        for imax in [16, 24, 32, 48, 64]:
+            ch = dict(base, inner_tol=itol, inner_max=imax)
+            if ch == base:
+                continue
+            try:
+                t, ok, its = _time_solve(a, b, x_ref, ch, stream=stream,
+                                         tol=tol, precision=precision,
+                                         reps=reps)
+            except Exception as e:  # noqa: BLE001
+                log(f"tune {ch}: failed: {e}")
+                continue
+            log(f"tune {ch}: {1e3*t:.1f} ms ({its} it, converged={ok})")
+            if ok and t < best[0]:
+                best = (t, ch)
     store("dense", m, n, best[1])
     return best[1]

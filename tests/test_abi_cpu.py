@@ -34,6 +34,23 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) <= set(B.SIGNATURES)
 
 
+def declared_arities():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for name, args in re.findall(r"\b(rgdbek_[a-z_]+)\s*\(([^)]*)\)\s*;", text):
+        args = args.strip()
+        out[name] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_header_arity():
+    ar = declared_arities()
+    assert len(ar) >= 12
+    for name, n in ar.items():
+        assert len(B.SIGNATURES[name][1]) == n, name
+
+
 def test_struct_layouts_match_header_sizes():
     # int64 x3 + int32 x2 + 3 pointers
     assert ctypes.sizeof(B.Matrix) == 3 * 8 + 2 * 4 + 3 * 8
@@ -73,6 +90,7 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     assert lib.rgdbek_solve(None, None, None, None, None) == B.ERR_INVALID_ARG
     cnt = ctypes.c_int64()
     assert lib.rgdbek_select(None, 10, 2, 0.0, 0, 0, 0, 0, 0, None, ctypes.byref(cnt), None) == B.ERR_INVALID_ARG
+    assert lib.rgdbek_apply(None, 0, None, None, None, None) == B.ERR_INVALID_ARG
 
 
 def test_product_path_has_no_fallback():
@@ -87,3 +105,19 @@ def test_product_path_has_no_fallback():
             mod.load()
     finally:
         mod._lib, mod.LIB_PATH = saved
+
+
+def test_block_diagonal_concatenation():
+    import numpy as np
+    import scipy.sparse as sp
+    import workloads
+    from paper_2509_19267_amd import block_diagonal
+    ps = workloads.laplacian_batch(count=4, n_min=60, n_max=300, seed=3)
+    rp, ci, v, ro, co = block_diagonal([p.a for p in ps])
+    a = sp.csr_matrix((v, ci, rp), shape=(ro[-1], co[-1]))
+    want = sp.block_diag([p.a for p in ps]).tocsr()
+    assert abs(a - want).max() == 0.0
+    assert rp.dtype == np.int64 and ci.dtype == np.int32
+    for s in range(4):
+        blk = a[ro[s]:ro[s + 1]]
+        assert blk.indices.min() >= co[s] and blk.indices.max() < co[s + 1]

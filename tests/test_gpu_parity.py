@@ -381,3 +381,175 @@ def test_mixed_sparse_consistent(rg):
     assert info["converged"] == 1
     assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
     s.close()
+
+
+# ------------------------------------------------------------ batches
+def batch_tensors(ps):
+    rp, ci, v, ro, co = rg_block_diagonal([p.a for p in ps])
+    return ((torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(),
+             torch.as_tensor(v).cuda()), ro, co)
+
+
+def rg_block_diagonal(mats):
+    from paper_2509_19267_amd import block_diagonal
+    return block_diagonal(mats)
+
+
+def test_batch_trajectory_per_system(rg):
+    # each system's iterate equals the oracle run on that system alone with
+    # its own block sizes and generator stream (system id s)
+    ps = workloads.laplacian_batch(count=6, n_min=300, n_max=900, seed=21)
+    csr, ro, co = batch_tensors(ps)
+    b = np.concatenate([p.b for p in ps])
+    s = rg.BatchSolver(csr, ro, co, eta=0.1, stop="none", max_iter=3,
+                       inner_max=300, graph_iters=1)
+    x, info = s.solve(dev(b))
+    x = x.cpu().numpy()
+    for i, p in enumerate(ps):
+        xo, _, _ = rgdbek(p.a, p.b, eta=0.1, max_iter=3, sys=i)
+        xs = x[co[i]:co[i + 1]]
+        print(f"batch system {i} n={p.a.shape[1]} rel={rel(xs, xo):.2e}", flush=True)
+        assert rel(xs, xo) <= TRAJ_TOL
+    s.close()
+
+
+def test_batch_solution_per_system(rg):
+    ps = workloads.laplacian_batch(count=12, n_min=200, n_max=3000, seed=22)
+    csr, ro, co = batch_tensors(ps)
+    b = np.concatenate([p.b for p in ps])
+    xs = np.concatenate([p.x_star for p in ps])
+    s = rg.BatchSolver(csr, ro, co, eta=0.1, stop="err_ref", tol=1e-10,
+                       max_iter=5000, inner_max=200)
+    x, info = s.solve(dev(b), x_ref=dev(xs))
+    its, met, conv = s.batch_info()
+    print("batch solve", info, its, flush=True)
+    assert info["converged"] == 1 and all(conv)
+    x = x.cpu().numpy()
+    for i, p in enumerate(ps):
+        assert rel(x[co[i]:co[i + 1]], p.x_star) <= 1e-10
+        xo, _, io = rgdbek(p.a, p.b, eta=0.1, max_iter=5000, sys=i,
+                           stop="err_ref", tol=1e-10, x_ref=p.x_star)
+        assert abs(its[i] - io.iterations) <= 1
+    s.close()
+
+
+def test_batch_mixed_refinement(rg):
+    ps = workloads.laplacian_batch(count=8, n_min=500, n_max=5000, seed=23)
+    csr, ro, co = batch_tensors(ps)
+    b = np.concatenate([p.b for p in ps])
+    xs = np.concatenate([p.x_star for p in ps])
+    csr32 = (csr[0], csr[1], csr[2].to(torch.float32))
+    s = rg.BatchSolver(csr32, ro, co, eta=0.1, stop="err_ref", tol=1e-10,
+                       max_iter=20000, inner_max=200, precision="mixed_f32")
+    x, info = s.solve(dev(b), x_ref=dev(xs))
+    its, met, conv = s.batch_info()
+    print("batch mixed", info, flush=True)
+    assert info["converged"] == 1 and all(conv)
+    x = x.cpu().numpy()
+    for i, p in enumerate(ps):
+        assert rel(x[co[i]:co[i + 1]], p.x_star) <= 1e-10
+    s.close()
+
+
+def test_batch_rejects_coupled_rows(rg):
+    ps = workloads.laplacian_batch(count=2, n_min=50, n_max=80, seed=24)
+    (rp, ci, v), ro, co = batch_tensors(ps)
+    ci = ci.clone()
+    ci[0] = co[1]          # row of system 0 pointing into system 1
+    ci_sorted_ok = ci      # first entry of the row: still increasing
+    with pytest.raises(rg.RgdbekError) as ei:
+        rg.BatchSolver((rp, ci_sorted_ok, v), ro, co, eta=0.1)
+    assert ei.value.status == 1
+
+
+# ------------------------------------------------------------ many RHS
+def test_multirhs_trajectory_per_rhs(rg):
+    p = workloads.sparse_powerlaw(3000, 1500, mean_len=10, max_len=100, seed=31)
+    rng = np.random.default_rng(1)
+    R = 6
+    xs = rng.standard_normal((R, 1500))
+    bs = np.stack([p.a @ x for x in xs])
+    s = rg.MultiRhsSolver(csr_tensors(p.a), p.a.shape, R, eta=0.1,
+                          stop="none", max_iter=3, inner_max=300,
+                          graph_iters=1)
+    x, info = s.solve(dev(bs.ravel()))
+    x = x.cpu().numpy().reshape(R, 1500)
+    for r in range(R):
+        xo, _, _ = rgdbek(p.a, bs[r], eta=0.1, max_iter=3, sys=r)
+        print(f"rhs {r} rel={rel(x[r], xo):.2e}", flush=True)
+        assert rel(x[r], xo) <= TRAJ_TOL
+    s.close()
+
+
+def tikhonov_blur(npix, mu):
+    import scipy.sparse as sp
+    a = workloads.blur_operator(npix=npix, dtype=np.float64)
+    n = a.shape[0]
+    return sp.vstack([a, np.sqrt(mu) * sp.identity(n)]).tocsr()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_f32"])
+def test_multirhs_blur_tikhonov_solution(rg, precision):
+    npix, R, mu = 32, 8, 1e-2
+    aa = tikhonov_blur(npix, mu)
+    n = npix * npix
+    xt = workloads.generators.smooth_fields(npix, R, seed=5, corr=3.0).T
+    bs = np.stack([np.concatenate([aa[:n] @ x, np.zeros(n)]) for x in xt])
+    xls = np.stack([np.linalg.lstsq(aa.toarray(), b, rcond=None)[0] for b in bs])
+    rp, ci, v = csr_tensors(aa)
+    if precision == "mixed_f32":
+        v = v.to(torch.float32)
+    s = rg.MultiRhsSolver((rp, ci, v), aa.shape, R, eta=0.1, stop="err_ref",
+                          tol=1e-10, max_iter=20000, inner_max=200,
+                          precision=precision)
+    x, info = s.solve(dev(bs.ravel()), x_ref=dev(xls.ravel()))
+    its, met, conv = s.batch_info()
+    print(f"blur {precision}", info, its, flush=True)
+    assert info["converged"] == 1 and all(conv)
+    x = x.cpu().numpy().reshape(R, n)
+    for r in range(R):
+        assert rel(x[r], xls[r]) <= 1e-10
+    s.close()
+
+
+def test_multirhs_gradient_layer(rg):
+    # differentiable deblurring layer: x_s = A^+ b_s for every right-hand
+    # side, loss L = sum_s <c_s, x_s>; dL/db and dL/dA (pattern, summed over
+    # right-hand sides) against the pinv reference and central differences
+    from oracle.refsol import grad_reference
+    npix, R, mu = 16, 3, 1e-2
+    aa = tikhonov_blur(npix, mu)
+    m, n = aa.shape
+    rng = np.random.default_rng(7)
+    bs = rng.standard_normal((R, m))
+    cs = rng.standard_normal((R, n))
+    rp, ci, v = csr_tensors(aa)
+    v = v.requires_grad_(True)
+    b_t = dev(bs.ravel()).requires_grad_(True)
+    s = rg.MultiRhsSolver((rp, ci, v.detach()), aa.shape, R, eta=0.2,
+                          stop="res_ext", tol=1e-13, max_iter=20000,
+                          inner_max=200)
+    x = rg.solve(s, v, b_t, least_squares=True)
+    (x * dev(cs.ravel())).sum().backward()
+    ad = aa.toarray()
+    rows = np.repeat(np.arange(m), np.diff(aa.indptr))
+    da_want = np.zeros(aa.nnz)
+    db_want = []
+    for r in range(R):
+        da, db = grad_reference(ad, bs[r], cs[r])
+        da_want += da[rows, aa.indices]
+        db_want.append(db)
+    assert rel(b_t.grad.cpu().numpy(), np.concatenate(db_want)) <= 1e-9
+    assert rel(v.grad.cpu().numpy(), da_want) <= 1e-9
+    # central differences on three stored entries
+    h = 1e-6
+    for e in [0, aa.nnz // 2, aa.nnz - 1]:
+        vals = []
+        for sgn in (1, -1):
+            a2 = aa.copy()
+            a2.data[e] += sgn * h
+            vals.append(sum(cs[r] @ np.linalg.lstsq(a2.toarray(), bs[r], rcond=None)[0]
+                            for r in range(R)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - v.grad[e].item()) <= 1e-6 * max(1.0, abs(fd))
+    s.close()
