@@ -112,6 +112,10 @@ typedef struct {
                             (1e-20 for FP64 weights, 1e-6 for the FP32 inner
                             iterations of the mixed form); < 0 = exact
                             zero test only                                  */
+  int32_t tile_rows;     /* rows per workgroup tile of the dense residual
+                            pass (rounded up to 16); 0 = sized so one grid
+                            round fills the device                          */
+  int32_t reserved;      /* must be 0                                       */
 } rgdbek_params;
 
 /* Dense block solvers: AUTO picks Cholesky for blocks up to 256 and

@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
                 ("max_iter", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("inner_max", ctypes.c_int32), ("graph_iters", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("solver", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("weight_floor", ctypes.c_double)]
+                ("flags", ctypes.c_int32), ("weight_floor", ctypes.c_double),
+                ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -137,7 +137,7 @@ seg_fold_kernel(SegInfo *seg, int nseg, Ctrl *ctrl, int end_iter,
     ctrl->iters_run = its;
     ctrl->converged = all_conv;
     if (end_iter) ctrl->it += 1;
-    if (all_done || ctrl->numeric) ctrl->done = 1;
+    if (all_done || ctrl->numeric || ctrl->sync_fail) ctrl->done = 1;
   }
 }
 

@@ -35,6 +35,12 @@ struct Ctrl {
   // inner solver state (one per phase)
   double cg_rz[2], cg_rz0[2], cg_alpha[2], cg_beta[2];
   int32_t cg_done[2], cg_steps[2];
+  uint64_t sel_bar[2];    // grid-barrier arrivals of the persistent selection
+  uint64_t sel_barbase[2];
+  uint64_t cg_bar[2];     // grid-barrier arrivals of the persistent PCG
+  uint64_t cg_barbase[2]; // arrivals completed by earlier launches
+  int32_t sync_fail;      // a grid-barrier wait timed out
+  int32_t pad0;
   unsigned ticket[8];     // last-block tickets (reset by the last block)
 };
 
@@ -147,5 +153,39 @@ __device__ __forceinline__ bool last_block(unsigned *ticket) {
 __device__ __forceinline__ bool ctrl_done(const Ctrl *c) {
   return ld_agent(&c->done) != 0;
 }
+
+// Grid barrier of a persistent launch (every workgroup resident): arrivals
+// are counted in a 64-bit counter that only grows; barrier number b of a
+// launch completes when the counter reaches base + b * gridDim.x.  Thread 0
+// releases the workgroup's writes at agent scope, arrives, polls, and
+// acquires.  Polls are bounded (GRID_SPIN_MAX, seconds): a timed-out wait
+// sets *fail, which also ends the waits of the other workgroups, so the
+// launch always drains.
+constexpr int64_t GRID_SPIN_MAX = 1ll << 22;
+// Arrive at barrier number `target` (counter value after every workgroup
+// arrived); returns false after a timed-out wait.
+__device__ __forceinline__ bool grid_barrier(uint64_t *ctr, uint64_t target,
+                                             int32_t *fail) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, (uint64_t)1, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    int64_t spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > GRID_SPIN_MAX || ld_agent(fail) != 0) { ok = 0; break; }
+    }
+    if (!ok) st_agent(fail, 1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
 
 }  // namespace rg

@@ -13,7 +13,22 @@ namespace rg {
 // ------------------------------------------------------------ selection
 constexpr int64_t SEL_SMALL_MAX = 65536;  // one workgroup up to this size
 
+// Global scratch of the persistent (one-launch) selection.
+struct SelPersist {
+  unsigned gh[6][2048];           // digit histograms, one per radix level
+  uint64_t ckey[4096];            // candidates of the final bucket
+  int64_t cidx[4096];
+  double gmax[1024];              // per-workgroup largest weight
+  int64_t cnt[1024];              // per-workgroup taken / tie counts
+  unsigned long long gpos, ncand; // positive weights, candidates gathered
+  int64_t tidx;                   // tie index found by its owner
+};
+// Largest d the persistent selection takes for `ncu` compute units (0: none).
+int64_t select_persist_max(int ncu);
+
 struct SelectScratch {
+  SelPersist *pers = nullptr; // persistent selection scratch
+  int ncu = 0;                // compute units (grid bound of that launch)
   uint64_t *keys = nullptr;   // d keys
   unsigned *hist = nullptr;   // 2048 bins (zeroed at allocation)
   uint64_t *ckey = nullptr;   // 4096 candidate keys
@@ -147,11 +162,13 @@ int launch_segdot(const Csr<T> &A, int epi, const SegArgs<T> &a, Ctrl *ctrl,
 template <typename T>
 struct DenseWork {
   T *qpart = nullptr;        // nch * rows
-  T *gpart = nullptr;        // nrb * ld
-  int nch = 0, nrb = 0;
+  T *gpart = nullptr;        // nrg * ld
+  int nch = 0, nrg = 0;      // column chunks, row tiles
+  int rpw = 0;               // rows per row tile
 };
 template <typename T>
-void dense_work_shape(const Dense<T> &A, int *nch, int *nrb);
+void dense_work_shape(const Dense<T> &A, int tile_rows, int target_wgs,
+                      int *nch, int *nrg, int *rpw);
 template <typename T>
 void launch_dense_fused(const Dense<T> &A, const T *x, const T *z,
                         DenseWork<T> &w, const T *off, const double *kappa,
@@ -212,7 +229,18 @@ struct CgWork {
   double *part = nullptr;    // 2 parities x 2 x part_cap (<r,zz>, <r,r>)
   int64_t part_cap = 0;      // cap/256 + 1
   double *rzs = nullptr;     // rz by step parity (2)
+  T *v2 = nullptr;           // persistent PCG: G p by step parity (2 * cap)
+  double *pv2 = nullptr;     // persistent PCG: <p, v> partials (2 * grid)
 };
+// Persistent PCG (one launch per projection): largest Gram dimension and
+// grid size for a given dimension.
+int64_t pcg_persist_cap(bool f64);
+int pcg_persist_grid(int64_t cap, int ncu);
+template <typename T>
+void launch_pcg_persist(const T *G, int64_t cap, const int64_t *count_dev,
+                        const T *hsrc, const int32_t *hlist, T *y,
+                        CgWork<T> &w, int grid, int max_steps, double tol,
+                        Ctrl *ctrl, int ph, int respect_done, hipStream_t st);
 // largest Gram dimension the PCG kernels accept (direction staged in LDS)
 int64_t pcg_cap_max();
 template <typename T>

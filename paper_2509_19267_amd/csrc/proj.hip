@@ -423,6 +423,135 @@ void launch_pcg_gram_step(const T *G, int64_t cap, const int64_t *count_dev,
 }
 int64_t pcg_cap_max() { return PG_LDS_MAX; }
 
+// ------------------------------------------------------------ persistent PCG
+// The whole Jacobi-preconditioned CG of one block projection in one launch of
+// P co-resident workgroups (P <= compute units).  Workgroup w owns rows
+// [w*rpw, (w+1)*rpw) of G and of y.  Every workgroup keeps the full direction
+// p, residual res and diagonal of G in LDS and updates them redundantly
+// (O(c) work per step, identical bits in every workgroup); per step only the
+// product v = G p on the owned rows and a partial of <p, v> are exchanged,
+// through double-buffered global arrays and one grid barrier.  The stopping
+// test ||res|| <= tol ||h|| is evaluated identically by every workgroup, so
+// all leave the loop together.  The barrier waits are bounded: after
+// GRID_SPIN_MAX polls a workgroup raises Ctrl::sync_fail and leaves, so the
+// launch always drains.
+constexpr int PP_NT = 256;
+constexpr int PP_RPW = 16;                       // rows of G per workgroup
+template <typename T> struct PpCap;
+template <> struct PpCap<double> { static constexpr int64_t v = 4096; };
+template <> struct PpCap<float> { static constexpr int64_t v = 8192; };
+
+template <typename T>
+__global__ void __launch_bounds__(PP_NT)
+pcg_persist_kernel(const T *__restrict__ G, int64_t ldg,
+                   const int64_t *__restrict__ cnt, const T *__restrict__ hsrc,
+                   const int32_t *__restrict__ hl, T *__restrict__ y,
+                   T *__restrict__ vbuf, double *__restrict__ pvbuf,
+                   int64_t cap, int max_steps, double tol, Ctrl *ctrl, int ph,
+                   int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  constexpr int64_t CAP = PpCap<T>::v;
+  __shared__ T ps[CAP], rs[CAP], dg[CAP];
+  __shared__ double sh[PP_NT / WAVE];
+  const int64_t c = *cnt;
+  const int P = (int)gridDim.x;
+  const int64_t rpw = (c + P - 1) / P;
+  const int64_t r0 = (int64_t)blockIdx.x * rpw;
+  const int64_t r1 = r0 + rpw < c ? r0 + rpw : c;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t a = threadIdx.x; a < c; a += PP_NT) {
+    const T h = hl ? hsrc[hl[a]] : hsrc[a];
+    const T d = G[a * ldg + a];
+    const T z = d > (T)0 ? h / d : (T)0;
+    rs[a] = h;
+    dg[a] = d;
+    ps[a] = z;
+    rz += (double)h * (double)z;
+    rr += (double)h * (double)h;
+  }
+  for (int64_t a = r0 + threadIdx.x; a < r1; a += PP_NT) y[a] = (T)0;
+  rz = block_sum<PP_NT>(rz, sh);
+  rr = block_sum<PP_NT>(rr, sh);
+  const double rr0 = rr;
+  const uint64_t base = ctrl->cg_barbase[ph];
+  int nbar = 0, t = 0;
+  bool run = !(rr0 == 0.0 || c == 0);
+  while (run && t < max_steps) {
+    const int par = t & 1;
+    T *vb = vbuf + (int64_t)par * cap;
+    double *pvb = pvbuf + (int64_t)par * P;
+    double pvp = 0.0;
+    for (int64_t row = r0 + wv; row < r1; row += PP_NT / WAVE) {
+      const T *gr = G + row * ldg;
+      T s = (T)0;
+      for (int64_t b = lane; b < c; b += WAVE) s += gr[b] * ps[b];
+      s = wave_sum(s);
+      if (lane == 0) {
+        vb[row] = s;
+        pvp += (double)s * (double)ps[row];
+      }
+    }
+    pvp = block_sum<PP_NT>(pvp, sh);
+    if (threadIdx.x == 0) pvb[blockIdx.x] = pvp;
+    ++nbar;
+    if (!grid_barrier(&ctrl->cg_bar[ph], base + (uint64_t)nbar * P,
+                      &ctrl->sync_fail))
+      return;
+    double pv = 0.0;
+    for (int b = threadIdx.x; b < P; b += PP_NT) pv += ld_agent(&pvb[b]);
+    pv = block_sum<PP_NT>(pv, sh);
+    const double alpha = pv != 0.0 ? rz / pv : 0.0;
+    for (int64_t a = r0 + threadIdx.x; a < r1; a += PP_NT)
+      y[a] += (T)alpha * ps[a];
+    double rz1 = 0.0;
+    rr = 0.0;
+    for (int64_t a = threadIdx.x; a < c; a += PP_NT) {
+      const T r = rs[a] - (T)alpha * ld_agent(&vb[a]);
+      rs[a] = r;
+      const T z = dg[a] > (T)0 ? r / dg[a] : (T)0;
+      rz1 += (double)r * (double)z;
+      rr += (double)r * (double)r;
+    }
+    rz1 = block_sum<PP_NT>(rz1, sh);
+    rr = block_sum<PP_NT>(rr, sh);
+    ++t;
+    if (rr <= tol * tol * rr0 || rz == 0.0 || pv == 0.0) break;
+    const double beta = rz1 / rz;
+    rz = rz1;
+    for (int64_t a = threadIdx.x; a < c; a += PP_NT) {
+      const T z = dg[a] > (T)0 ? rs[a] / dg[a] : (T)0;
+      ps[a] = z + (T)beta * ps[a];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->cg_barbase[ph] = base + (uint64_t)nbar * P;
+    ctrl->cg_steps[ph] = t;
+    ctrl->cg_done[ph] = 1;
+  }
+}
+
+int64_t pcg_persist_cap(bool f64) {
+  return f64 ? PpCap<double>::v : PpCap<float>::v;
+}
+int pcg_persist_grid(int64_t cap, int ncu) {
+  int64_t p = (cap + PP_RPW - 1) / PP_RPW;
+  if (p > ncu) p = ncu;
+  if (p < 1) p = 1;
+  return (int)p;
+}
+
+template <typename T>
+void launch_pcg_persist(const T *G, int64_t cap, const int64_t *count_dev,
+                        const T *hsrc, const int32_t *hlist, T *y,
+                        CgWork<T> &w, int grid, int max_steps, double tol,
+                        Ctrl *ctrl, int ph, int respect_done, hipStream_t st) {
+  hipLaunchKernelGGL(pcg_persist_kernel<T>, dim3(grid), dim3(PP_NT), 0, st, G,
+                     cap, count_dev, hsrc, hlist, y, w.v2, w.pv2, cap,
+                     max_steps, tol, ctrl, ph, respect_done);
+}
+
 // ------------------------------------------------------------ thin updates
 // out[i] (+)= sign * sum_a coef_a * M[list_a * ldm + i] over a chunk of the
 // list per blockIdx.y, partials combined in fixed order by upd_finish.
@@ -871,6 +1000,10 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
   template void launch_pcg_gram_step<T>(const T *, int64_t, const int64_t *, \
                                         T *, CgWork<T> &, int, double,       \
                                         Ctrl *, int, int, hipStream_t);       \
+  template void launch_pcg_persist<T>(const T *, int64_t, const int64_t *,   \
+                                      const T *, const int32_t *, T *,       \
+                                      CgWork<T> &, int, int, double, Ctrl *, \
+                                      int, int, hipStream_t);                 \
   template void launch_col_update<T>(const T *, int64_t, int64_t,            \
                                      const int32_t *, const int64_t *,       \
                                      int64_t, const T *, T *, T *, Ctrl *,   \

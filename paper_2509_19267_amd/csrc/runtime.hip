@@ -50,6 +50,7 @@ int pick_group(double mean_len) {
 // Device allocation list owned by a handle.
 struct Pool {
   std::vector<void *> ptrs;
+  hipStream_t st = nullptr;   // zero-fills are ordered on this stream
   template <typename T>
   T *alloc(int64_t count, bool zero = true) {
     if (count <= 0) count = 1;
@@ -63,7 +64,7 @@ struct Pool {
                          " bytes failed"};
     }
     ptrs.push_back(p);
-    if (zero) HIPCHK(hipMemset(p, 0, sizeof(T) * (size_t)count));
+    if (zero) HIPCHK(hipMemsetAsync(p, 0, sizeof(T) * (size_t)count, st));
     return (T *)p;
   }
   void release() {
@@ -110,6 +111,7 @@ struct rgdbek_ctx {
   bool dense = false;
   rgdbek_params p{};
   int64_t kc = 0, kr = 0;
+  int ncu = 256;                  // compute units of the device
   hipStream_t user_st = nullptr;  // caller's stream (inputs are ordered on it)
   hipStream_t st = nullptr;       // the stream all work is enqueued on
   bool own_stream = false;        // st was created by the handle
@@ -202,12 +204,13 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     }
     e.arm = Dense<T>{e.m, e.n, ld, rm};
     e.acm = Dense<T>{e.n, e.m, ldc, cm};
-    int nch, nrb;
-    dense_work_shape<T>(e.arm, &nch, &nrb);
+    int nch, nrg, rpw;
+    dense_work_shape<T>(e.arm, h->p.tile_rows, 4 * h->ncu, &nch, &nrg, &rpw);
     e.dw.nch = nch;
-    e.dw.nrb = nrb;
+    e.dw.nrg = nrg;
+    e.dw.rpw = rpw;
     e.dw.qpart = P.alloc<T>((int64_t)nch * e.m);
-    e.dw.gpart = P.alloc<T>((int64_t)nrb * ld);
+    e.dw.gpart = P.alloc<T>((int64_t)nrg * ld);
     // Gram of all columns (A^T A) when the column blocks are large enough to
     // be worth a gather; rows: A A^T only on request.
     const bool gram_cols = e.kc > 64 && e.n <= 8192;
@@ -240,6 +243,8 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       cw->part_cap = cap / 256 + 2;
       cw->part = P.alloc<double>(4 * cw->part_cap);
       cw->rzs = P.alloc<double>(2);
+      cw->v2 = P.alloc<T>(2 * cap);
+      cw->pv2 = P.alloc<double>(2 * pcg_persist_grid(cap, h->ncu));
     }
   } else {
     // CSR / CSC views; the adjoint swaps them
@@ -309,6 +314,8 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   e.J = P.alloc<int32_t>(e.kr + 64);
   const int64_t dmax = std::max(e.m, e.n);
   e.sel.keys = P.alloc<uint64_t>(dmax + 64, false);
+  e.sel.pers = P.alloc<SelPersist>(1);
+  e.sel.ncu = h->ncu;
   e.sel.hist = P.alloc<unsigned>(2048);
   e.sel.ckey = P.alloc<uint64_t>(4096);
   e.sel.cidx = P.alloc<int64_t>(4096);
@@ -334,6 +341,24 @@ struct IterOpts {
   const double *xbase = nullptr;  // ERR_REF on xbase + x (mixed inner loop)
   bool use_off = false;           // column offset (refinement correction)
 };
+
+// Gram solve of a dense block projection: the persistent one-launch PCG when
+// the block fits its LDS staging, else two launches per CG step.
+template <typename T>
+void pcg_solve(rgdbek_ctx *h, const T *G, int64_t cap, const int64_t *cnt,
+               const T *hsrc, const int32_t *hl, T *y, CgWork<T> &w, int maxs,
+               double itol, int ph) {
+  const bool f64 = std::is_same<T, double>::value;
+  if (cap <= pcg_persist_cap(f64)) {
+    launch_pcg_persist<T>(G, cap, cnt, hsrc, hl, y, w,
+                          pcg_persist_grid(cap, h->ncu), maxs, itol, h->ctrl,
+                          ph, 1, h->st);
+    return;
+  }
+  launch_pcg_gram_init<T>(G, cap, cnt, hsrc, hl, y, w, h->ctrl, ph, 1, h->st);
+  for (int k = 0; k < maxs; ++k)
+    launch_pcg_gram_step<T>(G, cap, cnt, y, w, k, itol, h->ctrl, ph, 1, h->st);
+}
 
 template <typename T>
 void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
@@ -385,11 +410,7 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     if (chol_c && e.kc <= CHOL_MAX) {
       launch_chol_solve<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, 1, c, 0, 1, st);
     } else {
-      launch_pcg_gram_init<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, c, 0, 1,
-                              st);
-      for (int k = 0; k < maxs; ++k)
-        launch_pcg_gram_step<T>(e.GU, e.kc, cntU, e.y, e.cgc, k, itol, c, 0, 1,
-                                st);
+      pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0);
     }
     launch_col_update<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.y, e.z,
                          e.upd, c, 1, st);
@@ -441,11 +462,7 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
     } else {
-      launch_pcg_gram_init<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, c, 1, 1,
-                              st);
-      for (int k = 0; k < maxs; ++k)
-        launch_pcg_gram_step<T>(e.GJ, e.kr, cntJ, e.w, e.cgr, k, itol, c, 1, 1,
-                                st);
+      pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1);
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
     }
@@ -524,7 +541,11 @@ rgdbek_status finish_status(rgdbek_ctx *h, rgdbek_info *info, double secs,
                             int64_t outer) {
   Ctrl &c = *h->hctrl;
   rgdbek_status s = RGDBEK_OK;
-  if (c.numeric) {
+  if (c.sync_fail) {
+    s = RGDBEK_ERR_DEVICE;
+    set_err(h, "a grid-barrier wait of the block solver timed out (the "
+               "workgroups of one launch were not all resident)");
+  } else if (c.numeric) {
     s = RGDBEK_ERR_NUMERIC;
     set_err(h, "NaN, negative or infinite residual weight during the solve");
   } else if (!c.converged && h->p.stop != RGDBEK_STOP_NONE) {
@@ -620,6 +641,8 @@ rgdbek_status solve64(rgdbek_ctx *h, Engine<double> &e, int which,
 // passes instead would freeze FP32 rounding in its null(A^T) component and
 // stall the refinement.  An inner pass ends when the global stop test holds
 // on x + dx, or when its metric has not improved by 5% for 4 graphs.
+constexpr double MIXED_PASS_DROP = 1e-5;
+
 rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
                           const double *x_ref_user, rgdbek_info *info) {
   auto t0 = std::chrono::steady_clock::now();
@@ -644,7 +667,7 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
   const int max_outer = 12;
   double metric = 0.0, prev_metric = 1e300;
   bool converged = false;
-  int numeric = 0;
+  int numeric = 0, sync_fail = 0;
   for (outer = 1; outer <= max_outer; ++outer) {
     // z = b - A x and the stop metric, then t = A^T z (FP64 passes)
     ctrl_reset(h, 0, 1, stop, h->p.tol);
@@ -710,9 +733,15 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
     const int istop = (stop == RGDBEK_STOP_ERR_REF) ? RGDBEK_STOP_ERR_REF
                       : (stop == RGDBEK_STOP_NONE ? RGDBEK_STOP_NONE
                                                   : RGDBEK_STOP_RES_EXT);
-    // inner RES_EXT runs with tol 0: it only feeds the stall detector
-    ctrl_reset(h, total_it, h->p.max_iter - total_it, istop,
-               istop == RGDBEK_STOP_ERR_REF ? h->p.tol : 0.0);
+    // inner RES_EXT runs with tol 0: it only feeds the stall detector.  An
+    // inner ERR_REF pass stops at the global tolerance or once it has cut
+    // the error of this pass by MIXED_PASS_DROP: FP32 rounding of the
+    // correction limits one pass to roughly u_32 * cond(A), so iterating
+    // further only burns iterations the next pass redoes in FP64 context.
+    const double itol = istop == RGDBEK_STOP_ERR_REF
+                            ? std::max(h->p.tol, MIXED_PASS_DROP * metric)
+                            : 0.0;
+    ctrl_reset(h, total_it, h->p.max_iter - total_it, istop, itol);
     if (istop == RGDBEK_STOP_ERR_REF) launch_set_ref2<double>(E.n, x_ref, h->ctrl, st);
     else launch_set_ref2<double>(E.m, E.b, h->ctrl, st);
     if (E.nseg) {
@@ -756,9 +785,10 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
     ctrl_fetch(h);
     total_it += h->hctrl->iters_run;
     numeric |= h->hctrl->numeric;
+    sync_fail |= h->hctrl->sync_fail;
     launch_axpby<double, float>(E.n, 1.0, h->x64, 1.0, F.x, st);
     launch_axpby<double, float>(E.m, 1.0, h->z64, 1.0, F.z, st);
-    if (numeric || stop == RGDBEK_STOP_NONE) {
+    if (numeric || sync_fail || stop == RGDBEK_STOP_NONE) {
       if (stop == RGDBEK_STOP_NONE) converged = true;
       break;
     }
@@ -773,6 +803,7 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
   c.metric = metric;
   c.converged = converged ? 1 : 0;
   c.numeric = numeric;
+  c.sync_fail = sync_fail;
   return finish_status(h, info, secs, outer > max_outer ? max_outer : outer);
 }
 
@@ -811,6 +842,17 @@ void validate_params(const rgdbek_params *p, int64_t m, int64_t n,
   if (p->inner_max < 0 || p->inner_max > 4096 || p->graph_iters < 0 ||
       p->graph_iters > 1024)
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "inner_max/graph_iters out of range"};
+  if (p->tile_rows < 0 || p->tile_rows > (1 << 20) || p->reserved != 0)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG,
+                   "tile_rows must lie in [0, 2^20] and reserved must be 0"};
+}
+
+// Compute units of the current device (sizes the dense pass grid).
+int device_cus() {
+  int dev = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  return ncu > 0 ? ncu : 256;
 }
 
 // CSR structure check on the host (copies row_ptr and col_idx).
@@ -1058,7 +1100,9 @@ rgdbek_status rgdbek_create(const rgdbek_matrix *A, const rgdbek_params *p,
       HIPCHK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
       h->own_stream = true;
     }
+    h->pool.st = h->st;
     HIPCHK(hipStreamSynchronize(h->user_st));
+    h->ncu = device_cus();
     h->bm = h->m;
     h->bn = h->n;
     create_impl(h, A);
@@ -1160,7 +1204,9 @@ rgdbek_status rgdbek_create_batched(const rgdbek_matrix *A, int64_t nsys,
       HIPCHK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
       h->own_stream = true;
     }
+    h->pool.st = h->st;
     HIPCHK(hipStreamSynchronize(h->user_st));
+    h->ncu = device_cus();
     h->bm = h->m;
     h->bn = h->n;
     create_impl(h, A);
@@ -1237,7 +1283,9 @@ rgdbek_status rgdbek_create_multirhs(const rgdbek_matrix *A, int64_t nrhs,
       HIPCHK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
       h->own_stream = true;
     }
+    h->pool.st = h->st;
     HIPCHK(hipStreamSynchronize(h->user_st));
+    h->ncu = device_cus();
     create_impl(h, A);
     // the batch sees I_nrhs (x) A: replicate the norms, widen the dimensions
     double *rho = h->pool.alloc<double>(A->m * nrhs, false);
@@ -1433,8 +1481,11 @@ rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
   }
   hipStream_t st = (hipStream_t)stream;
   Pool P;
+  P.st = st;
   rgdbek_status s = guarded(nullptr, [&]() {
     SelectScratch sc;
+    sc.pers = P.alloc<SelPersist>(1);
+    sc.ncu = device_cus();
     sc.keys = P.alloc<uint64_t>(d + 64, false);
     sc.hist = P.alloc<unsigned>(2048);
     sc.ckey = P.alloc<uint64_t>(4096);
@@ -1449,6 +1500,8 @@ rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
     *out_count = hc.sel_count[0];
+    if (hc.sync_fail)
+      throw ApiError{RGDBEK_ERR_DEVICE, "a grid-barrier wait timed out"};
     if (hc.numeric)
       throw ApiError{RGDBEK_ERR_NUMERIC, "weights must be finite and >= 0"};
     return RGDBEK_OK;

@@ -762,12 +762,393 @@ sel_write(const uint64_t *__restrict__ keys, int64_t d,
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->sel_count[ph] = total;
 }
 
+// ------------------------------------------------ persistent selection
+// One launch of P co-resident workgroups; workgroup w owns indices
+// [w*L, (w+1)*L) with L = KPT*SP_NT and keeps their keys in registers
+// (thread t holds the Philox groups t, t + SP_NT, ... of its chunk, four
+// consecutive indices each).  Grid barriers separate: the max-reduction;
+// keys + histogram of the top 11 key bits; each further radix level (11, 11,
+// 11, 11, 9 bits) while the bucket holding rank k is larger than SP_CAND;
+// the gather of that bucket (every workgroup then finds the same k-th pair
+// (key, index) in LDS); the per-workgroup taken counts.  The taken indices
+// are written in ascending order from per-workgroup offsets.  Same draw and
+// same predicate as the other forms, so the same block, bit for bit.
+constexpr int SP_NT = 256;
+constexpr int SP_CAND = 4096;
+constexpr int SP_MAXG = 1024;
+
+__device__ __forceinline__ int sp_shift(int lev) { return lev < 5 ? 53 - 11 * lev : 0; }
+__device__ __forceinline__ int sp_width(int lev) { return lev < 5 ? 11 : 9; }
+
+// exclusive prefix of v over the workgroup (thread order); *tot = sum
+__device__ __forceinline__ int64_t sp_scan(int64_t v, int64_t *sh, int64_t *tot) {
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  int64_t inc = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int64_t u = __shfl_up(inc, o, WAVE);
+    if (lane >= o) inc += u;
+  }
+  __syncthreads();
+  if (lane == WAVE - 1) sh[wv] = inc;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < SP_NT / WAVE; ++i) {
+    if (i < wv) before += sh[i];
+    all += sh[i];
+  }
+  *tot = all;
+  return before + inc - v;
+}
+
+template <typename T, int KPT>
+__global__ void __launch_bounds__(SP_NT)
+sel_persist_kernel(const T *__restrict__ eps, int64_t d, int64_t k,
+                   double floor, uint64_t seed, uint64_t key1, uint32_t phase,
+                   uint32_t sys, int ph, SelPersist *sp,
+                   int32_t *__restrict__ out, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  constexpr int NG = KPT / 4;
+  __shared__ unsigned hist[2048];
+  __shared__ uint64_t s_ck[SP_CAND];
+  __shared__ int32_t s_ci[SP_CAND];
+  __shared__ double shd[SP_NT / WAVE];
+  __shared__ int64_t sh64[SP_NT / WAVE];
+  __shared__ int64_t s_b, s_acc, s_cb, s_tidx;
+  __shared__ uint64_t s_tkey;
+  const int P = (int)gridDim.x;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int64_t L = (int64_t)KPT * SP_NT;
+  const int64_t base = (int64_t)blockIdx.x * L;
+  const uint64_t it = (uint64_t)ctrl->it;
+  const uint64_t bbase = ctrl->sel_barbase[ph];
+  uint64_t nbar = 0;
+  uint64_t *bar = &ctrl->sel_bar[ph];
+  int32_t *fail = &ctrl->sync_fail;
+
+  if (blockIdx.x == 0) {
+    unsigned *gh = &sp->gh[0][0];
+    for (int i = tid; i < 6 * 2048; i += SP_NT) gh[i] = 0u;
+    if (tid == 0) { sp->gpos = 0ull; sp->ncand = 0ull; sp->tidx = -1; }
+  }
+  // 1. largest finite weight
+  double mx = 0.0;
+#pragma unroll
+  for (int i = 0; i < NG; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = base + 4 * ((int64_t)i * SP_NT + tid) + q;
+      if (j < d) {
+        const double e = (double)eps[j];
+        if (e <= 1.7976931348623157e308) mx = e > mx ? e : mx;
+      }
+    }
+  mx = wave_max(mx);
+  if (lane == 0) shd[wv] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < SP_NT / WAVE; ++i) mx = shd[i] > mx ? shd[i] : mx;
+    sp->gmax[blockIdx.x] = mx;
+  }
+  if (!grid_barrier(bar, bbase + (++nbar) * P, fail)) return;
+  double gm = 0.0;
+  for (int b = tid; b < P; b += SP_NT) {
+    const double v = ld_agent(&sp->gmax[b]);
+    gm = v > gm ? v : gm;
+  }
+  gm = wave_max(gm);
+  __syncthreads();
+  if (lane == 0) shd[wv] = gm;
+  __syncthreads();
+  gm = 0.0;
+  for (int i = 0; i < SP_NT / WAVE; ++i) gm = shd[i] > gm ? shd[i] : gm;
+  const double cut = floor > 0.0 ? floor * gm : 0.0;
+
+  // 2. keys and the top-digit histogram
+  for (int i = tid; i < 2048; i += SP_NT) hist[i] = 0u;
+  __syncthreads();
+  uint64_t key[KPT];
+  int bad = 0;
+  int64_t pos = 0;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    const int64_t g = base / 4 + (int64_t)i * SP_NT + tid;
+    if (g * 4 < d) {
+      const P4 r = philox4x64_10((uint64_t)g, it, phase, sys, seed, key1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = g * 4 + q;
+        uint64_t kk = SENT;
+        if (j < d) kk = make_key((double)eps[j], r.v[q], cut, &bad);
+        key[4 * i + q] = kk;
+        if (kk != SENT) {
+          ++pos;
+          atomicAdd(&hist[kk >> 53], 1u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) key[4 * i + q] = SENT;
+    }
+  }
+  if (bad) atomicOr(&ctrl->numeric, 1);
+  pos = block_sum_i64<SP_NT>(pos, sh64);
+  for (int i = tid; i < 2048; i += SP_NT)
+    if (hist[i]) atomicAdd(&sp->gh[0][i], hist[i]);
+  if (tid == 0 && pos) atomicAdd(&sp->gpos, (unsigned long long)pos);
+  if (!grid_barrier(bar, bbase + (++nbar) * P, fail)) return;
+
+  // 3. threshold pair (tkey, tidx) and bound lo
+  uint64_t lo, tkey;
+  int64_t tidx;
+  const int64_t gpos = (int64_t)ld_agent(&sp->gpos);
+  if (gpos <= k) {
+    lo = SENT; tkey = SENT; tidx = -1;
+  } else {
+    uint64_t prefix = 0;
+    int64_t krem = k;
+    int lev = 0;
+    while (true) {
+      const int sh = sp_shift(lev), wd = sp_width(lev);
+      const int nb = 1 << wd;
+      for (int i = tid; i < nb; i += SP_NT) hist[i] = ld_agent(&sp->gh[lev][i]);
+      __syncthreads();
+      if (wv == 0) {
+        // bucket holding rank krem: lane sums of nb/64 bins, wave scan
+        const int per = nb / WAVE;
+        int64_t ls = 0;
+        for (int i = 0; i < per; ++i) ls += hist[lane * per + i];
+        int64_t inc = ls;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+          const int64_t u = __shfl_up(inc, o, WAVE);
+          if (lane >= o) inc += u;
+        }
+        const int64_t exc = inc - ls;
+        if (exc < krem && krem <= inc) {
+          int64_t acc = exc;
+          int b = lane * per;
+          for (;; ++b) {
+            if (acc + (int64_t)hist[b] >= krem) break;
+            acc += hist[b];
+          }
+          s_b = b;
+          s_acc = acc;
+          s_cb = hist[b];
+        }
+      }
+      __syncthreads();
+      prefix = (prefix << wd) | (uint64_t)s_b;
+      krem -= s_acc;
+      const int64_t cb = s_cb;
+      __syncthreads();
+      if (cb == krem) {
+        lo = (prefix + 1ull) << sh;
+        tkey = SENT; tidx = -1;
+        break;
+      }
+      if (cb <= SP_CAND) {
+        // gather the bucket, then every workgroup ranks it in LDS
+#pragma unroll
+        for (int i = 0; i < NG; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint64_t kk = key[4 * i + q];
+            if (kk != SENT && (kk >> sh) == prefix) {
+              const unsigned long long slot = atomicAdd(&sp->ncand, 1ull);
+              if (slot < (unsigned long long)SP_CAND) {
+                sp->ckey[slot] = kk;
+                sp->cidx[slot] = base + 4 * ((int64_t)i * SP_NT + tid) + q;
+              }
+            }
+          }
+        if (!grid_barrier(bar, bbase + (++nbar) * P, fail)) return;
+        const int nc = (int)cb;
+        for (int i = tid; i < nc; i += SP_NT) {
+          s_ck[i] = ld_agent(&sp->ckey[i]);
+          s_ci[i] = (int32_t)ld_agent(&sp->cidx[i]);
+        }
+        if (nc <= SP_NT) {
+          __syncthreads();
+          if (tid < nc) {
+            const uint64_t a = s_ck[tid];
+            const int32_t ai = s_ci[tid];
+            int64_t rank = 0;
+            for (int u = 0; u < nc; ++u) {
+              const uint64_t b = s_ck[u];
+              rank += (b < a) || (b == a && s_ci[u] < ai);
+            }
+            if (rank == krem - 1) { s_tkey = a; s_tidx = ai; }
+          }
+          __syncthreads();
+        } else {
+          int np2 = 1;
+          while (np2 < nc) np2 <<= 1;
+          for (int i = nc + tid; i < np2; i += SP_NT) {
+            s_ck[i] = SENT;
+            s_ci[i] = INT32_MAX;
+          }
+          __syncthreads();
+          for (int size = 2; size <= np2; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+              for (int i = tid; i < np2; i += SP_NT) {
+                const int q = i ^ stride;
+                if (q > i) {
+                  const uint64_t a = s_ck[i], b = s_ck[q];
+                  const int32_t ai = s_ci[i], bi = s_ci[q];
+                  const bool gt = (a > b) || (a == b && ai > bi);
+                  if (gt == ((i & size) == 0)) {
+                    s_ck[i] = b; s_ck[q] = a; s_ci[i] = bi; s_ci[q] = ai;
+                  }
+                }
+              }
+              __syncthreads();
+            }
+          if (tid == 0) { s_tkey = s_ck[krem - 1]; s_tidx = s_ci[krem - 1]; }
+          __syncthreads();
+        }
+        tkey = s_tkey;
+        tidx = s_tidx;
+        lo = tkey;
+        break;
+      }
+      if (sh == 0) {
+        // more than SP_CAND equal keys: the krem-th of them in index order
+        tkey = prefix;
+        int64_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < KPT; ++i) mine += key[i] == tkey;
+        mine = block_sum_i64<SP_NT>(mine, sh64);
+        if (tid == 0) sp->cnt[blockIdx.x] = mine;
+        if (!grid_barrier(bar, bbase + (++nbar) * P, fail)) return;
+        int64_t before = 0;
+        for (int b = tid; b < (int)blockIdx.x; b += SP_NT) before += ld_agent(&sp->cnt[b]);
+        before = block_sum_i64<SP_NT>(before, sh64);
+        if (before < krem && krem <= before + mine) {
+          int64_t seen = before;
+          for (int i = 0; i < NG; ++i) {
+            int64_t c = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c += key[4 * i + q] == tkey;
+            int64_t tot;
+            const int64_t ex = sp_scan(c, sh64, &tot);
+            int64_t r = seen + ex;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (key[4 * i + q] == tkey) {
+                if (r == krem - 1)
+                  st_agent(&sp->tidx, base + 4 * ((int64_t)i * SP_NT + tid) + q);
+                ++r;
+              }
+            seen += tot;
+          }
+        }
+        if (!grid_barrier(bar, bbase + (++nbar) * P, fail)) return;
+        tidx = ld_agent(&sp->tidx);
+        lo = tkey;
+        break;
+      }
+      // histogram of the next digit inside the bucket
+      const int nsh = sp_shift(lev + 1), nwd = sp_width(lev + 1);
+      for (int i = tid; i < (1 << nwd); i += SP_NT) hist[i] = 0u;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < KPT; ++i) {
+        const uint64_t kk = key[i];
+        if (kk != SENT && (kk >> sh) == prefix)
+          atomicAdd(&hist[(kk >> nsh) & ((1u << nwd) - 1u)], 1u);
+      }
+      __syncthreads();
+      for (int i = tid; i < (1 << nwd); i += SP_NT)
+        if (hist[i]) atomicAdd(&sp->gh[lev + 1][i], hist[i]);
+      if (!grid_barrier(bar, bbase + (++nbar) * P, fail)) return;
+      ++lev;
+    }
+  }
+
+  // 4. counts per workgroup, then ordered compaction
+  int64_t mine = 0;
+#pragma unroll
+  for (int i = 0; i < NG; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      mine += take(key[4 * i + q], base + 4 * ((int64_t)i * SP_NT + tid) + q,
+                   lo, tkey, tidx);
+  mine = block_sum_i64<SP_NT>(mine, sh64);
+  if (tid == 0) sp->cnt[blockIdx.x] = mine;
+  if (!grid_barrier(bar, bbase + (++nbar) * P, fail)) return;
+  int64_t before = 0, total = 0;
+  for (int b = tid; b < P; b += SP_NT) {
+    const int64_t v = ld_agent(&sp->cnt[b]);
+    total += v;
+    if (b < (int)blockIdx.x) before += v;
+  }
+  before = block_sum_i64<SP_NT>(before, sh64);
+  total = block_sum_i64<SP_NT>(total, sh64);
+  int64_t off = before;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    int64_t c = 0;
+    bool f[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = base + 4 * ((int64_t)i * SP_NT + tid) + q;
+      f[q] = take(key[4 * i + q], j, lo, tkey, tidx);
+      c += f[q];
+    }
+    int64_t tot;
+    int64_t r = off + sp_scan(c, sh64, &tot);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (f[q]) out[r++] = (int32_t)(base + 4 * ((int64_t)i * SP_NT + tid) + q);
+    off += tot;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    ctrl->sel_count[ph] = total;
+    ctrl->sel_barbase[ph] = bbase + nbar * (uint64_t)P;
+  }
+}
+
+// keys per thread and grid of the persistent selection (kpt 0: not taken)
+static void sel_persist_shape(int64_t d, int ncu, int *kpt, int *grid) {
+  *kpt = 0;
+  *grid = 0;
+  if (ncu <= 0) return;
+  const int64_t lim = ncu < SP_MAXG ? ncu : SP_MAXG;
+  for (int kk : {4, 16}) {
+    const int64_t L = (int64_t)kk * SP_NT;
+    const int64_t g = (d + L - 1) / L;
+    if (g <= lim) { *kpt = kk; *grid = (int)(g < 1 ? 1 : g); return; }
+  }
+}
+int64_t select_persist_max(int ncu) {
+  const int64_t lim = ncu < SP_MAXG ? ncu : SP_MAXG;
+  return ncu > 0 ? lim * 16 * SP_NT : 0;
+}
+// smallest d that takes the persistent form (below: one workgroup)
+constexpr int64_t SP_MIN_D = 4096;
+
 // ------------------------------------------------ launcher
 template <typename T>
 void launch_select(const T *eps, int64_t d, int64_t k, double floor,
                    uint64_t seed, uint64_t key1, uint32_t phase, uint32_t sys,
                    int ph, SelectScratch &s, int32_t *out, Ctrl *ctrl,
                    int respect_done, hipStream_t st) {
+  int kpt = 0, grid = 0;
+  if (s.pers && d >= SP_MIN_D) sel_persist_shape(d, s.ncu, &kpt, &grid);
+  if (kpt == 4) {
+    hipLaunchKernelGGL((sel_persist_kernel<T, 4>), dim3(grid), dim3(SP_NT), 0,
+                       st, eps, d, k, floor, seed, key1, phase, sys, ph,
+                       s.pers, out, ctrl, respect_done);
+    return;
+  }
+  if (kpt == 16) {
+    hipLaunchKernelGGL((sel_persist_kernel<T, 16>), dim3(grid), dim3(SP_NT),
+                       0, st, eps, d, k, floor, seed, key1, phase, sys, ph,
+                       s.pers, out, ctrl, respect_done);
+    return;
+  }
   if (d <= SEL_SMALL_MAX) {
     hipLaunchKernelGGL(sel_small<T>, dim3(1), dim3(1024), 0, st, eps, d, k,
                        floor, seed, key1, ph, phase, sys, s.keys, out, ctrl,

@@ -163,40 +163,62 @@ template int launch_segdot<float>(const Csr<float> &, int,
                                   hipStream_t);
 
 // ------------------------------------------------------------ dense pass
+typedef double df_d2 __attribute__((ext_vector_type(2)));
+typedef float df_f4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Vec;
-template <> struct Vec<double> { using type = double2; static constexpr int n = 2; };
-template <> struct Vec<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec<double> { using type = df_d2; static constexpr int n = 2; };
+template <> struct Vec<float> { using type = df_f4; static constexpr int n = 4; };
 
 constexpr int DF_NT = 256;     // 4 waves
-constexpr int DF_RB = 128;     // rows per workgroup
 constexpr int DF_NL = 4;       // 16-byte loads per lane per row
 constexpr int DF_RG = 4;       // rows in flight per wave
+constexpr int DF_RSTEP = (DF_NT / WAVE) * DF_RG;   // rows per workgroup sweep
 
 template <typename T>
 constexpr int df_cb() { return WAVE * Vec<T>::n * DF_NL; }
 
+// Work split of the fused pass: column chunks of df_cb() columns (one per
+// grid column) times row tiles of `rpw` rows (one per grid row).  With
+// tile_rows = 0 the tile height is chosen so that the grid holds about
+// `target_wgs` workgroups of equal size (one full round on the device),
+// which keeps the last round from running half empty.
 template <typename T>
-void dense_work_shape(const Dense<T> &A, int *nch, int *nrb) {
-  *nch = (int)((A.ld + df_cb<T>() - 1) / df_cb<T>());
-  *nrb = (int)((A.rows + DF_RB - 1) / DF_RB);
+void dense_work_shape(const Dense<T> &A, int tile_rows, int target_wgs,
+                      int *nch, int *nrg, int *rpw) {
+  const int64_t cb = df_cb<T>();
+  *nch = (int)((A.ld + cb - 1) / cb);
+  int64_t r;
+  if (tile_rows > 0) {
+    r = tile_rows;
+  } else {
+    int64_t want = target_wgs / *nch;
+    if (want < 1) want = 1;
+    r = (A.rows + want - 1) / want;
+  }
+  r = (r + DF_RSTEP - 1) / DF_RSTEP * DF_RSTEP;
+  if (r < DF_RSTEP) r = DF_RSTEP;
+  *rpw = (int)r;
+  *nrg = (int)((A.rows + r - 1) / r);
+  if (*nrg < 1) *nrg = 1;
 }
-template void dense_work_shape<double>(const Dense<double> &, int *, int *);
-template void dense_work_shape<float>(const Dense<float> &, int *, int *);
+template void dense_work_shape<double>(const Dense<double> &, int, int, int *,
+                                       int *, int *);
+template void dense_work_shape<float>(const Dense<float> &, int, int, int *,
+                                      int *, int *);
 
 template <typename T>
-__device__ __forceinline__ T vget(const typename Vec<T>::type &v, int i);
-template <>
-__device__ __forceinline__ double vget<double>(const double2 &v, int i) {
-  return i == 0 ? v.x : v.y;
-}
-template <>
-__device__ __forceinline__ float vget<float>(const float4 &v, int i) {
-  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+__device__ __forceinline__ T vget(const typename Vec<T>::type &v, int i) {
+  return v[i];
 }
 
+// One workgroup: columns [c0, c0 + df_cb()) of rows [r0, r0 + rpw).  Each
+// wave streams DF_RG rows at a time with DF_NL 16-byte loads per lane per
+// row; q_i partials are wave sums (one per row and column chunk), g_j
+// partials stay in registers over the whole tile and are summed over the
+// four waves in LDS (one per column and row tile).
 template <typename T>
 __global__ void __launch_bounds__(DF_NT)
-dense_fused_kernel(Dense<T> A, const T *__restrict__ x,
+dense_fused_kernel(Dense<T> A, int rpw, const T *__restrict__ x,
                    const T *__restrict__ z, T *__restrict__ qpart,
                    T *__restrict__ gpart, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
@@ -206,7 +228,7 @@ dense_fused_kernel(Dense<T> A, const T *__restrict__ x,
   __shared__ T sg[DF_NT / WAVE][CB];
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const int64_t c0 = (int64_t)blockIdx.x * CB;
-  const int64_t r0 = (int64_t)blockIdx.y * DF_RB;
+  const int64_t r0 = (int64_t)blockIdx.y * rpw;
   const int64_t ld = A.ld;
   T xs[DF_NL][VN], ga[DF_NL][VN];
   bool cok[DF_NL];
@@ -220,8 +242,7 @@ dense_fused_kernel(Dense<T> A, const T *__restrict__ x,
       ga[t][v] = (T)0;
     }
   }
-  const int nw = DF_NT / WAVE;
-  for (int rr = wv * DF_RG; rr < DF_RB; rr += nw * DF_RG) {
+  for (int rr = wv * DF_RG; rr < rpw; rr += DF_RSTEP) {
     V av[DF_RG][DF_NL];
     T zr[DF_RG];
 #pragma unroll
@@ -232,7 +253,7 @@ dense_fused_kernel(Dense<T> A, const T *__restrict__ x,
       const V *row = reinterpret_cast<const V *>(A.a + (rok ? i : 0) * ld + c0);
 #pragma unroll
       for (int t = 0; t < DF_NL; ++t) {
-        if (rok && cok[t]) av[u][t] = row[t * WAVE + lane];
+        if (rok && cok[t]) av[u][t] = __builtin_nontemporal_load(&row[t * WAVE + lane]);
         else av[u][t] = V{};
       }
     }
@@ -262,29 +283,49 @@ dense_fused_kernel(Dense<T> A, const T *__restrict__ x,
     if (col < ld) {
       T s = (T)0;
 #pragma unroll
-      for (int w = 0; w < nw; ++w) s += sg[w][c];
+      for (int w = 0; w < DF_NT / WAVE; ++w) s += sg[w][c];
       gpart[(int64_t)blockIdx.y * ld + col] = s;
     }
   }
 }
 
+// Sums the partials in a fixed order.  The first ceil(cols/64) workgroups
+// handle 64 columns each, the four waves taking every fourth row tile and
+// meeting in LDS; the rest handle 256 rows each.
 template <typename T>
 __global__ void __launch_bounds__(256)
-dense_finalize(int64_t rows, int64_t cols, int64_t ld, int nch, int nrb,
-               const T *__restrict__ qpart, const T *__restrict__ gpart,
-               const T *__restrict__ off, const double *__restrict__ kappa,
-               T *__restrict__ g, T *__restrict__ eps, T *__restrict__ q,
-               Ctrl *ctrl, int respect_done) {
+dense_finalize(int64_t rows, int64_t cols, int64_t ld, int nch, int nrg,
+               int ncb, const T *__restrict__ qpart,
+               const T *__restrict__ gpart, const T *__restrict__ off,
+               const double *__restrict__ kappa, T *__restrict__ g,
+               T *__restrict__ eps, T *__restrict__ q, Ctrl *ctrl,
+               int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t < cols) {
-    T s = (T)0;
-    for (int b = 0; b < nrb; ++b) s += gpart[(int64_t)b * ld + t];
-    if (off) s += off[t];
-    g[t] = s;
-    const double k = kappa[t];
-    eps[t] = k > 0.0 ? (T)((double)s * (double)s / k) : (T)0;
+  if ((int)blockIdx.x < ncb) {
+    __shared__ T sh[4][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t t = (int64_t)blockIdx.x * WAVE + lane;
+    T s0 = (T)0, s1 = (T)0;
+    if (t < cols) {
+      int b = wv;
+      for (; b + 4 < nrg; b += 8) {
+        s0 += gpart[(int64_t)b * ld + t];
+        s1 += gpart[(int64_t)(b + 4) * ld + t];
+      }
+      if (b < nrg) s0 += gpart[(int64_t)b * ld + t];
+    }
+    sh[wv][lane] = s0 + s1;
+    __syncthreads();
+    if (wv == 0 && t < cols) {
+      T s = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+      if (off) s += off[t];
+      g[t] = s;
+      const double k = kappa[t];
+      eps[t] = k > 0.0 ? (T)((double)s * (double)s / k) : (T)0;
+    }
+    return;
   }
+  const int64_t t = (int64_t)(blockIdx.x - ncb) * 256 + threadIdx.x;
   if (t < rows) {
     T s = (T)0;
     for (int c = 0; c < nch; ++c) s += qpart[(int64_t)c * rows + t];
@@ -297,12 +338,14 @@ void launch_dense_fused(const Dense<T> &A, const T *x, const T *z,
                         DenseWork<T> &w, const T *off, const double *kappa,
                         T *g, T *eps, T *q, Ctrl *ctrl, int respect_done,
                         hipStream_t st) {
-  hipLaunchKernelGGL(dense_fused_kernel<T>, dim3(w.nch, w.nrb), dim3(DF_NT),
-                     0, st, A, x, z, w.qpart, w.gpart, ctrl, respect_done);
-  const int64_t mx = A.rows > A.cols ? A.rows : A.cols;
-  hipLaunchKernelGGL(dense_finalize<T>, dim3((unsigned)((mx + 255) / 256)),
-                     dim3(256), 0, st, A.rows, A.cols, A.ld, w.nch, w.nrb,
-                     w.qpart, w.gpart, off, kappa, g, eps, q, ctrl,
+  hipLaunchKernelGGL(dense_fused_kernel<T>, dim3(w.nch, w.nrg), dim3(DF_NT),
+                     0, st, A, w.rpw, x, z, w.qpart, w.gpart, ctrl,
+                     respect_done);
+  const int ncb = (int)((A.cols + WAVE - 1) / WAVE);
+  const int nrw = (int)((A.rows + 255) / 256);
+  hipLaunchKernelGGL(dense_finalize<T>, dim3((unsigned)(ncb + nrw)),
+                     dim3(256), 0, st, A.rows, A.cols, A.ld, w.nch, w.nrg,
+                     ncb, w.qpart, w.gpart, off, kappa, g, eps, q, ctrl,
                      respect_done);
 }
 template void launch_dense_fused<double>(const Dense<double> &, const double *,
@@ -466,7 +509,8 @@ __global__ void end_iter_kernel(Ctrl *ctrl) {
   if (threadIdx.x != 0 || ctrl->done) return;
   ctrl->it += 1;
   ctrl->iters_run += 1;
-  if (ctrl->iters_run >= ctrl->it_end || ctrl->numeric) ctrl->done = 1;
+  if (ctrl->iters_run >= ctrl->it_end || ctrl->numeric || ctrl->sync_fail)
+    ctrl->done = 1;
 }
 void launch_end_iter(Ctrl *ctrl, hipStream_t st) {
   hipLaunchKernelGGL(end_iter_kernel, dim3(1), dim3(64), 0, st, ctrl);

@@ -283,7 +283,9 @@ __global__ void axpby_kernel(int64_t n, double alpha, Ty *__restrict__ y,
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * 256) {
     const double xv = x ? (double)x[i] : 0.0;
-    y[i] = (Ty)(alpha * (double)y[i] + beta * xv);
+    // alpha == 0 overwrites y without reading it (y may hold anything)
+    const double yv = alpha != 0.0 ? alpha * (double)y[i] : 0.0;
+    y[i] = (Ty)(yv + beta * xv);
   }
 }
 template <typename Ty, typename Tx>

@@ -39,7 +39,7 @@ class Solver:
                  k_row=0, tol=1e-8, stop="err_ref", max_iter=10000, seed=0,
                  precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
                  solver=B.SOLVER_AUTO, graph=True, gram_aat=False,
-                 weight_floor=0.0, stream=None):
+                 weight_floor=0.0, tile_rows=0, stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -77,6 +77,7 @@ class Solver:
         p.inner_max, p.inner_tol, p.graph_iters = inner_max, inner_tol, graph_iters
         p.solver = int(solver)
         p.weight_floor = float(weight_floor)
+        p.tile_rows = int(tile_rows)
         p.flags = (B.FLAG_GRAPH if graph else 0) | (B.FLAG_GRAM_AAT if gram_aat else 0)
         self.m, self.n = int(m), int(n)
         self.params = p
