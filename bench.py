@@ -67,19 +67,45 @@ def probe(args):
         dst.copy_(src)
     torch.cuda.synchronize()
     log("copy: 1 GiB read + 1 GiB write per launch")
+    from paper_2509_19267_amd import tune
     rng = np.random.default_rng(0)
     m, n = args.m, args.n
     a = torch.as_tensor(rng.standard_normal((m, n))).to(dev)
-    s = rg.Solver(a, k_col=8, k_row=8, precision="mixed_f32")
-    for prec, dt in [("f64", torch.float64), ("f32", torch.float32)]:
+    for form, prec, dt in [("fp64", "f64", torch.float64),
+                           ("mixed_f32", "f32", torch.float32)]:
+        ch = tune.lookup("dense", m, n, form) or {}
+        s = rg.Solver(a, k_col=8, k_row=8, precision="mixed_f32",
+                      tile_rows=ch.get("tile_rows", 0))
         xv = torch.randn(n, dtype=dt, device=dev)
         zv = torch.randn(m, dtype=dt, device=dev)
         for _ in range(3):
             s.apply(xv, zv, precision=prec)
         torch.cuda.synchronize()
-        log(f"fused pass {prec}: 3 launches")
-    s.close()
+        log(f"fused pass {prec} (tile_rows {ch.get('tile_rows', 0)}): 3 launches")
+        s.close()
     print(json.dumps({"probe": "done", "m": m, "n": n}))
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dense_fused_pass_20000x5000_hbm.md")
+
+
+def counted_traffic(prec, tile_rows, m, n):
+    """HBM bytes per launch of the fused pass from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary (copy-calibrated); None when the summary is
+    for another shape or row tile."""
+    if (m, n) != (20000, 5000):
+        return None
+    try:
+        with open(TRAFFIC_FILE) as f:
+            line = [l for l in f if l.startswith("traffic_bytes_per_launch:")][0]
+    except (OSError, IndexError):
+        return None
+    tb, tr = line.split("tile_rows:")
+    vals = dict(kv.split("=") for kv in tb.split(":")[1].split())
+    tiles = dict(kv.split("=") for kv in tr.split())
+    if int(tiles.get(prec, -1)) != int(tile_rows or 0):
+        return None
+    return int(vals[prec])
 
 
 def main():
@@ -106,22 +132,29 @@ def main():
     xs = torch.as_tensor(prob.x_star).to(dev)
     stream = torch.cuda.Stream()
 
-    choice = tune.lookup("dense", args.m, args.n)
-    if args.kc and args.kr:
-        choice = dict(k_col=args.kc, k_row=args.kr, gram_aat=args.kr > 256,
+    form_list = args.forms.split(",")
+    choices = {}
+    for form in form_list:
+        ch = tune.lookup("dense", args.m, args.n, form)
+        if args.kc and args.kr:
+            ch = dict(k_col=args.kc, k_row=args.kr, gram_aat=args.kr > 256,
                       inner_tol=args.inner_tol, inner_max=args.inner_max)
-    if args.tune or choice is None:
-        choice = tune.tune_dense(a, b, xs, stream=stream, log=log)
-    log(f"block sizes {choice}")
+        if args.tune or ch is None:
+            ch = tune.tune_dense(a, b, xs, stream=stream, log=log,
+                                 precision=form)
+        choices[form] = ch
+        log(f"{form}: block sizes {ch}")
 
     forms = {}
     handles = {}
-    for form in args.forms.split(","):
+    for form in form_list:
+        choice = choices[form]
         kw = dict(k_col=choice["k_col"], k_row=choice["k_row"],
                   gram_aat=choice.get("gram_aat", False), stop="err_ref",
                   tol=args.tol, max_iter=20000, precision=form, stream=stream,
                   inner_tol=choice.get("inner_tol", 0.0),
-                  inner_max=choice.get("inner_max", 0))
+                  inner_max=choice.get("inner_max", 0),
+                  tile_rows=choice.get("tile_rows", 0))
         tc = time.time()
         s = rg.Solver(a, **kw)
         create_s = time.time() - tc
@@ -129,27 +162,28 @@ def main():
         for _ in range(args.warmup):
             s.solve(b, x_ref=xs)
         torch.cuda.synchronize()
-        times, its, errs = [], [], []
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
+        times, its, errs, evs = [], [], [], []
         torch.cuda.synchronize()
-        ev0.record(stream)
         for _ in range(args.steps):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
             t1 = time.perf_counter()
             x, info = s.solve(b, x_ref=xs)
             times.append(time.perf_counter() - t1)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            evs.append(ev0.elapsed_time(ev1))
             its.append(info["iterations"])
             errs.append(float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs)))
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ev_ms = ev0.elapsed_time(ev1) / args.steps
+        ev_ms = float(np.mean(evs))
         forms[form] = dict(ms_per_solve=1e3 * float(np.mean(times)),
                            ms_min=1e3 * float(np.min(times)),
                            ms_events=ev_ms, iterations=int(np.median(its)),
                            outer=int(info["outer_iterations"]),
                            rel_err=float(np.max(errs)),
                            converged=bool(info["converged"]),
-                           create_s=create_s)
+                           create_s=create_s, choice=choice)
         log(f"{form}: {forms[form]}")
 
     # roofline of the dominant kernel: the fused pass A x, A^T z (FP64 and,
@@ -187,17 +221,21 @@ def main():
     r = roof.get(dom)
     roofline = None
     if r:
+        dom_form = "mixed_f32" if dom == "f32" else "fp64"
+        traffic = counted_traffic(dom, choices.get(dom_form, {}).get("tile_rows", 0),
+                                  m, n)
         roofline = {"bound": "hbm", "achieved": round(r["gbs"], 1),
                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(r["gbs"] / PEAK_HBM_GBS, 4),
-                    "traffic": None,
+                    "traffic": traffic,
                     "kernel": f"dense_fused_kernel<{'float' if dom == 'f32' else 'double'}> (+finalize)",
                     "alg_bytes_per_launch": r["alg_bytes"],
                     "us_per_launch": round(r["us"], 2)}
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(prob, choice, forms.get("fp64", best)["iterations"])
+        ref_form = "fp64" if "fp64" in forms else best_form
+        cpu = cpu_baseline(prob, choices[ref_form], forms[ref_form]["iterations"])
 
     out = {
         "metric": METRIC, "value": round(best["ms_per_solve"], 3), "unit": "ms",
@@ -208,10 +246,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dense_least_squares_{m}x{n}", "m": m, "n": n,
                    "tol": args.tol, "form": best_form,
-                   "k_col": choice["k_col"], "k_row": choice["k_row"],
-                   "gram_aat": bool(choice.get("gram_aat", False)),
-                   "inner_tol": choice.get("inner_tol", 0.0),
-                   "inner_max": choice.get("inner_max", 0)},
+                   **{k: v for k, v in choices[best_form].items()}},
         "forms": forms,
         "speedup_mixed_vs_fp64": (round(forms["fp64"]["ms_per_solve"] /
                                         forms["mixed_f32"]["ms_per_solve"], 3)

@@ -244,7 +244,12 @@ rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
  * of the matrix; CSR: one CSR and one CSC pass.  precision RGDBEK_F64 uses
  * the FP64 storage (double vectors); RGDBEK_F32 the FP32 copy of a MIXED_F32
  * handle (float vectors).  All four pointers are device pointers.  Enqueued
- * on the handle's stream; returns without synchronising it (for timing). */
+ * on the handle's stream with no host synchronisation (for timing): ordered
+ * after the work already on the caller's stream, and the caller's stream is
+ * ordered after it (events), so results are ready for the caller's later
+ * work.  For a batched handle the products are those of the block-diagonal
+ * matrix; for a many-RHS handle those of I_nrhs (x) A (vectors of nrhs*n and
+ * nrhs*m entries, right-hand side major). */
 rgdbek_status rgdbek_apply(rgdbek_handle h, int32_t precision, const void *x,
                            const void *z, void *ax, void *atz);
 

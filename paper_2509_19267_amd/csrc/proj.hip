@@ -435,8 +435,9 @@ int64_t pcg_cap_max() { return PG_LDS_MAX; }
 // all leave the loop together.  The barrier waits are bounded: after
 // GRID_SPIN_MAX polls a workgroup raises Ctrl::sync_fail and leaves, so the
 // launch always drains.
-constexpr int PP_NT = 256;
+constexpr int PP_NT = 1024;                      // 16 waves: one row of G each
 constexpr int PP_RPW = 16;                       // rows of G per workgroup
+constexpr int PP_UNROLL = 8;                     // row loads in flight per lane
 template <typename T> struct PpCap;
 template <> struct PpCap<double> { static constexpr int64_t v = 4096; };
 template <> struct PpCap<float> { static constexpr int64_t v = 8192; };
@@ -485,7 +486,15 @@ pcg_persist_kernel(const T *__restrict__ G, int64_t ldg,
     for (int64_t row = r0 + wv; row < r1; row += PP_NT / WAVE) {
       const T *gr = G + row * ldg;
       T s = (T)0;
-      for (int64_t b = lane; b < c; b += WAVE) s += gr[b] * ps[b];
+      int64_t b = lane;
+      for (; b + (PP_UNROLL - 1) * WAVE < c; b += PP_UNROLL * WAVE) {
+        T gv[PP_UNROLL];
+#pragma unroll
+        for (int u = 0; u < PP_UNROLL; ++u) gv[u] = gr[b + u * WAVE];
+#pragma unroll
+        for (int u = 0; u < PP_UNROLL; ++u) s += gv[u] * ps[b + u * WAVE];
+      }
+      for (; b < c; b += WAVE) s += gr[b] * ps[b];
       s = wave_sum(s);
       if (lane == 0) {
         vb[row] = s;
@@ -553,10 +562,14 @@ void launch_pcg_persist(const T *G, int64_t cap, const int64_t *count_dev,
 }
 
 // ------------------------------------------------------------ thin updates
-// out[i] (+)= sign * sum_a coef_a * M[list_a * ldm + i] over a chunk of the
-// list per blockIdx.y, partials combined in fixed order by upd_finish.
+// out[i] (+)= sign * sum_a coef_a * M[list_a * ldm + i]: blockIdx.y takes a
+// chunk of UP_CHUNK list entries, each thread two consecutive i (one 16-byte
+// load per listed row when T is double; rows are padded, so i + 1 is always
+// inside the row), with UP_UNROLL rows in flight; partials are combined in a
+// fixed order by upd_finish.
 constexpr int UP_NT = 256;
-constexpr int UP_CHUNK = 128;
+constexpr int UP_CHUNK = 32;
+constexpr int UP_UNROLL = 8;
 template <typename T>
 __global__ void __launch_bounds__(UP_NT)
 upd_partial(const T *__restrict__ M, int64_t ldm, int64_t len,
@@ -564,15 +577,37 @@ upd_partial(const T *__restrict__ M, int64_t ldm, int64_t len,
             const T *__restrict__ coef, T *__restrict__ part, Ctrl *ctrl,
             int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
+  typedef T v2 __attribute__((ext_vector_type(2)));
   const int64_t c = *cnt;
-  const int64_t i = (int64_t)blockIdx.x * UP_NT + threadIdx.x;
   const int64_t a0 = (int64_t)blockIdx.y * UP_CHUNK;
-  int64_t a1 = a0 + UP_CHUNK;
-  if (a1 > c) a1 = c;
+  if (a0 >= c) return;
+  const int64_t a1 = a0 + UP_CHUNK < c ? a0 + UP_CHUNK : c;
+  const int64_t i = 2 * ((int64_t)blockIdx.x * UP_NT + threadIdx.x);
   if (i >= len) return;
-  T s = 0;
-  for (int64_t a = a0; a < a1; ++a) s += coef[a] * M[(int64_t)list[a] * ldm + i];
-  part[(int64_t)blockIdx.y * len + i] = s;
+  T s0 = 0, s1 = 0;
+  int64_t a = a0;
+  for (; a + UP_UNROLL <= a1; a += UP_UNROLL) {
+    v2 mv[UP_UNROLL];
+    T cf[UP_UNROLL];
+#pragma unroll
+    for (int u = 0; u < UP_UNROLL; ++u) {
+      mv[u] = *reinterpret_cast<const v2 *>(M + (int64_t)list[a + u] * ldm + i);
+      cf[u] = coef[a + u];
+    }
+#pragma unroll
+    for (int u = 0; u < UP_UNROLL; ++u) {
+      s0 += cf[u] * mv[u].x;
+      s1 += cf[u] * mv[u].y;
+    }
+  }
+  for (; a < a1; ++a) {
+    const v2 mv = *reinterpret_cast<const v2 *>(M + (int64_t)list[a] * ldm + i);
+    s0 += coef[a] * mv.x;
+    s1 += coef[a] * mv.y;
+  }
+  T *pp = part + (int64_t)blockIdx.y * len;
+  pp[i] = s0;
+  if (i + 1 < len) pp[i + 1] = s1;
 }
 template <typename T>
 __global__ void __launch_bounds__(UP_NT)
@@ -583,9 +618,18 @@ upd_finish(int64_t len, const int64_t *__restrict__ cnt, int nsplit,
   const int64_t i = (int64_t)blockIdx.x * UP_NT + threadIdx.x;
   if (i >= len) return;
   const int64_t c = *cnt;
-  const int ns = (int)((c + UP_CHUNK - 1) / UP_CHUNK);
+  int ns = (int)((c + UP_CHUNK - 1) / UP_CHUNK);
+  if (ns > nsplit) ns = nsplit;
   T s = 0;
-  for (int b = 0; b < ns && b < nsplit; ++b) s += part[(int64_t)b * len + i];
+  int b = 0;
+  for (; b + 8 <= ns; b += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u) * len + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; b < ns; ++b) s += part[(int64_t)b * len + i];
   out[i] += sign * s;
 }
 
@@ -594,11 +638,12 @@ static void thin_update(const T *M, int64_t ldm, int64_t len,
                         const int32_t *list, const int64_t *cnt, int64_t cap,
                         const T *coef, T *out, T sign, T *part, Ctrl *ctrl,
                         int respect_done, hipStream_t st) {
-  const unsigned gx = (unsigned)((len + UP_NT - 1) / UP_NT);
+  const unsigned gx = (unsigned)((len + 2 * UP_NT - 1) / (2 * UP_NT));
   const unsigned gy = (unsigned)((cap + UP_CHUNK - 1) / UP_CHUNK);
   hipLaunchKernelGGL(upd_partial<T>, dim3(gx, gy), dim3(UP_NT), 0, st, M, ldm,
                      len, list, cnt, coef, part, ctrl, respect_done);
-  hipLaunchKernelGGL(upd_finish<T>, dim3(gx), dim3(UP_NT), 0, st, len, cnt,
+  const unsigned gf = (unsigned)((len + UP_NT - 1) / UP_NT);
+  hipLaunchKernelGGL(upd_finish<T>, dim3(gf), dim3(UP_NT), 0, st, len, cnt,
                      (int)gy, part, sign, out, ctrl, respect_done);
 }
 

@@ -774,7 +774,7 @@ sel_write(const uint64_t *__restrict__ keys, int64_t d,
 // are written in ascending order from per-workgroup offsets.  Same draw and
 // same predicate as the other forms, so the same block, bit for bit.
 constexpr int SP_NT = 256;
-constexpr int SP_CAND = 4096;
+constexpr int SP_CAND = SP_NT;   // candidates ranked in LDS (one per thread)
 constexpr int SP_MAXG = 1024;
 
 __device__ __forceinline__ int sp_shift(int lev) { return lev < 5 ? 53 - 11 * lev : 0; }
@@ -949,18 +949,29 @@ sel_persist_kernel(const T *__restrict__ eps, int64_t d, int64_t k,
         break;
       }
       if (cb <= SP_CAND) {
-        // gather the bucket, then every workgroup ranks it in LDS
+        // gather the bucket (one slot reservation per workgroup), then every
+        // workgroup ranks the candidates in LDS by counting
+        int64_t mc = 0;
+#pragma unroll
+        for (int i = 0; i < KPT; ++i)
+          mc += (key[i] != SENT && (key[i] >> sh) == prefix);
+        int64_t wtot;
+        const int64_t wex = sp_scan(mc, sh64, &wtot);
+        if (tid == 0 && wtot > 0)
+          s_b = (int64_t)atomicAdd(&sp->ncand, (unsigned long long)wtot);
+        __syncthreads();
+        int64_t slot = s_b + wex;
 #pragma unroll
         for (int i = 0; i < NG; ++i)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const uint64_t kk = key[4 * i + q];
             if (kk != SENT && (kk >> sh) == prefix) {
-              const unsigned long long slot = atomicAdd(&sp->ncand, 1ull);
-              if (slot < (unsigned long long)SP_CAND) {
+              if (slot < SP_CAND) {
                 sp->ckey[slot] = kk;
                 sp->cidx[slot] = base + 4 * ((int64_t)i * SP_NT + tid) + q;
               }
+              ++slot;
             }
           }
         if (!grid_barrier(bar, bbase + (++nbar) * P, fail)) return;
@@ -969,45 +980,18 @@ sel_persist_kernel(const T *__restrict__ eps, int64_t d, int64_t k,
           s_ck[i] = ld_agent(&sp->ckey[i]);
           s_ci[i] = (int32_t)ld_agent(&sp->cidx[i]);
         }
-        if (nc <= SP_NT) {
-          __syncthreads();
-          if (tid < nc) {
-            const uint64_t a = s_ck[tid];
-            const int32_t ai = s_ci[tid];
-            int64_t rank = 0;
-            for (int u = 0; u < nc; ++u) {
-              const uint64_t b = s_ck[u];
-              rank += (b < a) || (b == a && s_ci[u] < ai);
-            }
-            if (rank == krem - 1) { s_tkey = a; s_tidx = ai; }
+        __syncthreads();
+        if (tid < nc) {
+          const uint64_t a = s_ck[tid];
+          const int32_t ai = s_ci[tid];
+          int64_t rank = 0;
+          for (int u = 0; u < nc; ++u) {
+            const uint64_t b = s_ck[u];
+            rank += (b < a) || (b == a && s_ci[u] < ai);
           }
-          __syncthreads();
-        } else {
-          int np2 = 1;
-          while (np2 < nc) np2 <<= 1;
-          for (int i = nc + tid; i < np2; i += SP_NT) {
-            s_ck[i] = SENT;
-            s_ci[i] = INT32_MAX;
-          }
-          __syncthreads();
-          for (int size = 2; size <= np2; size <<= 1)
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-              for (int i = tid; i < np2; i += SP_NT) {
-                const int q = i ^ stride;
-                if (q > i) {
-                  const uint64_t a = s_ck[i], b = s_ck[q];
-                  const int32_t ai = s_ci[i], bi = s_ci[q];
-                  const bool gt = (a > b) || (a == b && ai > bi);
-                  if (gt == ((i & size) == 0)) {
-                    s_ck[i] = b; s_ck[q] = a; s_ci[i] = bi; s_ci[q] = ai;
-                  }
-                }
-              }
-              __syncthreads();
-            }
-          if (tid == 0) { s_tkey = s_ck[krem - 1]; s_tidx = s_ci[krem - 1]; }
-          __syncthreads();
+          if (rank == krem - 1) { s_tkey = a; s_tidx = ai; }
         }
+        __syncthreads();
         tkey = s_tkey;
         tidx = s_tidx;
         lo = tkey;

@@ -1,10 +1,13 @@
 """Block-size autotuner.
 
 RGDBEK's block fraction trades per-iteration cost against iteration count
-(the remark on eta in Section 2).  The tuner times real solves on the
-problem at hand over a small grid of (k_col, k_row) and dense Gram options
-and keeps the fastest time-to-tolerance.  Results are cached per
-(layout, m, n) in tuned.json next to this file.
+(the remark on eta in Section 2), and the inner tolerance of the block
+projections trades inner steps against outer progress.  The tuner times
+real solves to the target tolerance on the problem at hand over a grid of
+(k_col, k_row), then over the inner tolerance and step cap, then over the
+row-tile height of the dense residual pass, for each arithmetic form, and
+keeps the fastest converging choice.  Results are cached per
+(layout, m, n, form) in tuned.json next to this file.
 """
 import json
 import os
@@ -22,13 +25,17 @@ def _load():
         return {}
 
 
-def lookup(layout, m, n):
-    return _load().get(f"{layout}:{m}x{n}")
+def _key(layout, m, n, form):
+    return f"{layout}:{m}x{n}:{form}"
 
 
-def store(layout, m, n, choice):
+def lookup(layout, m, n, form="fp64"):
+    return _load().get(_key(layout, m, n, form))
+
+
+def store(layout, m, n, form, choice):
     c = _load()
-    c[f"{layout}:{m}x{n}"] = choice
+    c[_key(layout, m, n, form)] = choice
     try:
         with open(CACHE, "w") as f:
             json.dump(c, f, indent=1, sort_keys=True)
@@ -42,61 +49,58 @@ def _time_solve(a, b, x_ref, choice, *, stream, tol, precision, reps):
                gram_aat=choice.get("gram_aat", False), stop="err_ref",
                tol=tol, max_iter=5000, precision=precision, stream=stream,
                inner_tol=choice.get("inner_tol", 0.0),
-               inner_max=choice.get("inner_max", 0))
+               inner_max=choice.get("inner_max", 0),
+               tile_rows=choice.get("tile_rows", 0))
     ts, ok, its = [], True, 0
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        _, info = s.solve(b, x_ref=x_ref)
-        ts.append(time.perf_counter() - t0)
-        ok = ok and bool(info["converged"])
-        its = info["iterations"]
-    s.close()
+    try:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _, info = s.solve(b, x_ref=x_ref)
+            ts.append(time.perf_counter() - t0)
+            ok = ok and bool(info["converged"])
+            its = info["iterations"]
+    finally:
+        s.close()
     return min(ts), ok, its
 
 
 def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
-               grid=None, precision="fp64", reps=2):
-    """Sweep block sizes (k_col, k_row, A A^T precomputed or not), then the
-    inner CG tolerance and step cap, for a dense A (device tensors); returns
-    and caches the fastest converging choice."""
+               precision="fp64", reps=2):
+    """Sweep the block sizes, the inner tolerance and step cap, and the row
+    tile of the fused pass for a dense A (device tensors) in one arithmetic
+    form; returns and caches the fastest converging choice."""
     m, n = a.shape
-    if grid is None:
-        fr = [0.02, 0.05, 0.1, 0.2]
-        grid = []
-        for fc in fr:
-            for frw in fr:
-                kc = max(1, int(fc * n))
-                kr = max(1, min(int(frw * n), m))
-                grid.append(dict(k_col=kc, k_row=kr, gram_aat=kr > 256,
-                                 inner_tol=1e-10, inner_max=48))
-    best = None
-    for ch in grid:
+
+    def run(ch, best):
         try:
             t, ok, its = _time_solve(a, b, x_ref, ch, stream=stream, tol=tol,
                                      precision=precision, reps=reps)
         except Exception as e:  # noqa: BLE001
-            log(f"tune {ch}: failed: {e}")
-            continue
-        log(f"tune {ch}: {1e3*t:.1f} ms ({its} it, converged={ok})")
+            log(f"tune {precision} {ch}: failed: {e}")
+            return best
+        log(f"tune {precision} {ch}: {1e3 * t:.1f} ms ({its} it, "
+            f"converged={ok})")
         if ok and (best is None or t < best[0]):
-            best = (t, ch)
+            return (t, dict(ch))
+        return best
+
+    best = None
+    for fc in [0.1, 0.2, 0.3, 0.4]:
+        for fr in [0.1, 0.2, 0.3, 0.4, 0.5]:
+            kc = max(1, min(int(fc * n), n))
+            kr = max(1, min(int(fr * n), m))
+            best = run(dict(k_col=kc, k_row=kr, gram_aat=kr > 256,
+                            inner_tol=0.1, inner_max=16), best)
     if best is None:
         raise RuntimeError("no configuration converged")
     base = best[1]
-    for itol in [1e-14, 1e-10, 1e-8, 1e-6]:
-        for imax in [16, 24, 32, 48, 64]:
+    for itol in [0.3, 0.1, 0.03, 0.01, 1e-3]:
+        for imax in [8, 16, 32]:
             ch = dict(base, inner_tol=itol, inner_max=imax)
-            if ch == base:
-                continue
-            try:
-                t, ok, its = _time_solve(a, b, x_ref, ch, stream=stream,
-                                         tol=tol, precision=precision,
-                                         reps=reps)
-            except Exception as e:  # noqa: BLE001
-                log(f"tune {ch}: failed: {e}")
-                continue
-            log(f"tune {ch}: {1e3*t:.1f} ms ({its} it, converged={ok})")
-            if ok and t < best[0]:
-                best = (t, ch)
-    store("dense", m, n, best[1])
+            if ch != base:
+                best = run(ch, best)
+    base = best[1]
+    for tr in [32, 64, 128, 256]:
+        best = run(dict(base, tile_rows=tr), best)
+    store("dense", m, n, precision, best[1])
     return best[1]
