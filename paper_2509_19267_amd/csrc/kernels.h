@@ -87,6 +87,16 @@ struct Csr {                 // CSR (or CSC viewed as CSR of the transpose)
   const int32_t *longs = nullptr;  // base segments longer than the limit
   int64_t nlong = 0;
   int64_t long_limit = 0;
+  // Merge-chunk plan of full passes (rep == 1): chunk c holds nonzeros
+  // [c*MP_CH, (c+1)*MP_CH) and owns the rows whose first nonzero position
+  // ptr[r] lies in it (mp_rs[c] .. mp_rs[c+1]-1; mp_rs[nchunk] = rows); rows
+  // spanning chunks are listed (mp_xrow, first/last chunk) and finished by a
+  // second launch from per-chunk head/lead partials.
+  const int32_t *mp_rs = nullptr;
+  int64_t mp_nchunk = 0;
+  const int32_t *mp_xrow = nullptr, *mp_xcs = nullptr, *mp_xce = nullptr;
+  int64_t mp_ncross = 0;
+  T *mp_head = nullptr, *mp_lead = nullptr;   // nchunk each
   // Replicated operator I_rep (x) A for many right-hand sides: the stored
   // matrix is the base (brows x bcols); rows = rep * brows virtual rows.
   // Virtual segments are visited in RHS-minor order (slot = i * rep + s) so
@@ -156,6 +166,10 @@ struct SegArgs {
 template <typename T>
 int launch_segdot(const Csr<T> &A, int epi, const SegArgs<T> &a, Ctrl *ctrl,
                   int respect_done, hipStream_t st);   // returns #partials
+// nonzeros per merge chunk (one wave); partial slots a full pass may use
+constexpr int64_t MP_CH = 256;
+int64_t segdot_max_parts(int64_t rows, int64_t nnz, int64_t nchunk,
+                         int64_t ncross, int64_t nlong, int64_t rep);
 
 // Dense fused pass: q = A x and g = A^T z from one read of A; then the
 // finalise step forms g (+ off), eps^z = g^2/kappa, and q.

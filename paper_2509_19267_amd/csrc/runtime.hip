@@ -48,6 +48,13 @@ int pick_group(double mean_len) {
 }
 
 // Device allocation list owned by a handle.
+// Nonzero-balanced chunking of one CSR (see Csr::mp_*), device arrays.
+struct MergePlan {
+  int32_t *rs = nullptr;                 // nchunk + 1 owned-row starts
+  int32_t *xrow = nullptr, *xcs = nullptr, *xce = nullptr;
+  int64_t nchunk = 0, ncross = 0;
+};
+
 struct Pool {
   std::vector<void *> ptrs;
   hipStream_t st = nullptr;   // zero-fills are ordered on this stream
@@ -125,6 +132,7 @@ struct rgdbek_ctx {
   double *csr_val = nullptr, *csc_val = nullptr;
   int32_t *csr_longs = nullptr, *csc_longs = nullptr;
   int64_t csr_nlong = 0, csc_nlong = 0;
+  MergePlan csr_mp, csc_mp;   // nonzero-balanced full-pass plans
   double *rho = nullptr, *kappa = nullptr;
   Engine<double> e64;
   Engine<double> e64t;        // adjoint system (A^T), built on demand
@@ -285,6 +293,20 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     a.nlong = transpose ? h->csc_nlong : h->csr_nlong;
     at.longs = transpose ? h->csr_longs : h->csc_longs;
     at.nlong = transpose ? h->csr_nlong : h->csc_nlong;
+    if (h->rep == 1) {
+      auto plan = [&](Csr<T> &c, const MergePlan &mp) {
+        c.mp_rs = mp.rs;
+        c.mp_nchunk = mp.nchunk;
+        c.mp_xrow = mp.xrow;
+        c.mp_xcs = mp.xcs;
+        c.mp_xce = mp.xce;
+        c.mp_ncross = mp.ncross;
+        c.mp_head = P.alloc<T>(mp.nchunk);
+        c.mp_lead = P.alloc<T>(mp.nchunk);
+      };
+      plan(a, transpose ? h->csc_mp : h->csr_mp);
+      plan(at, transpose ? h->csr_mp : h->csc_mp);
+    }
     e.csr = a;
     e.csc = at;
     for (int ph = 0; ph < 2; ++ph) {
@@ -328,8 +350,19 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     e.nseg = h->nseg;
     e.seg = transpose ? h->seg_t : h->seg;
   }
-  e.part = P.alloc<double>(2 * (dmax / 4 + 1024) +
-                           2 * (h->csr_nlong + h->csc_nlong) * h->rep);
+  {
+    int64_t np = 2 * (dmax / 4 + 1024) +
+                 2 * (h->csr_nlong + h->csc_nlong) * h->rep;
+    if (!e.dense) {
+      np = std::max(np, 2 * segdot_max_parts(h->bm, h->nnz, h->csr_mp.nchunk,
+                                             h->csr_mp.ncross, h->csr_nlong,
+                                             h->rep));
+      np = std::max(np, 2 * segdot_max_parts(h->bn, h->nnz, h->csc_mp.nchunk,
+                                             h->csc_mp.ncross, h->csc_nlong,
+                                             h->rep));
+    }
+    e.part = P.alloc<double>(np);
+  }
   e.ready = true;
 }
 
@@ -909,6 +942,47 @@ void build_longs(rgdbek_ctx *h, const int64_t *ptr_dev, int64_t rows,
                      hipMemcpyHostToDevice));
 }
 
+// Chunk c holds nonzeros [c*MP_CH, (c+1)*MP_CH); it owns the rows whose
+// first nonzero position lies in it (empty rows: the position of the next
+// nonzero; trailing empty rows: the last chunk).  Rows running past their
+// chunk are listed with their first and last chunk.
+void build_merge_plan(rgdbek_ctx *h, const int64_t *ptr_dev, int64_t rows,
+                      MergePlan *mp) {
+  std::vector<int64_t> rp(rows + 1);
+  HIPCHK(hipMemcpy(rp.data(), ptr_dev, sizeof(int64_t) * (rows + 1),
+                   hipMemcpyDeviceToHost));
+  const int64_t nnz = rp[rows];
+  const int64_t nch = std::max<int64_t>(1, (nnz + MP_CH - 1) / MP_CH);
+  std::vector<int32_t> rs(nch + 1);
+  for (int64_t c = 0; c < nch; ++c)
+    rs[c] = (int32_t)(std::lower_bound(rp.begin(), rp.begin() + rows,
+                                       c * MP_CH) - rp.begin());
+  rs[nch] = (int32_t)rows;
+  std::vector<int32_t> xr, xs, xe;
+  for (int64_t r = 0; r < rows; ++r) {
+    if (rp[r + 1] == rp[r]) continue;
+    const int64_t cs = rp[r] / MP_CH, ce = (rp[r + 1] - 1) / MP_CH;
+    if (ce > cs) {
+      xr.push_back((int32_t)r);
+      xs.push_back((int32_t)cs);
+      xe.push_back((int32_t)ce);
+    }
+  }
+  mp->nchunk = nch;
+  mp->ncross = (int64_t)xr.size();
+  auto up = [&](const std::vector<int32_t> &v) {
+    int32_t *d = h->pool.alloc<int32_t>(std::max<int64_t>(1, (int64_t)v.size()), false);
+    if (!v.empty())
+      HIPCHK(hipMemcpy(d, v.data(), sizeof(int32_t) * v.size(),
+                       hipMemcpyHostToDevice));
+    return d;
+  };
+  mp->rs = up(rs);
+  mp->xrow = up(xr);
+  mp->xcs = up(xs);
+  mp->xce = up(xe);
+}
+
 void create_impl(rgdbek_ctx *h, const rgdbek_matrix *A) {
   hipStream_t st = h->st;
   Pool &P = h->pool;
@@ -966,6 +1040,8 @@ void create_impl(rgdbek_ctx *h, const rgdbek_matrix *A) {
     const int gc = pick_group(h->n ? (double)h->nnz / h->n : 1.0);
     build_longs(h, h->csr_ptr, h->m, 32LL * gr, &h->csr_longs, &h->csr_nlong);
     build_longs(h, h->csc_ptr, h->n, 32LL * gc, &h->csc_longs, &h->csc_nlong);
+    build_merge_plan(h, h->csr_ptr, h->m, &h->csr_mp);
+    build_merge_plan(h, h->csc_ptr, h->n, &h->csc_mp);
     h->rho = P.alloc<double>(h->m);
     h->kappa = P.alloc<double>(h->n);
     Csr<double> a, at;

@@ -111,9 +111,154 @@ segdot_long(Csr<T> A, SegArgs<T> a, int64_t part_base, Ctrl *ctrl,
   }
 }
 
+// ------------------------------------------------------------ merge pass
+// Full passes (rep == 1) balanced by nonzeros, not by rows, so power-law row
+// lengths cost nothing extra: each wave streams one chunk of MP_CH nonzeros
+// (MP_K consecutive per lane: 16-byte index loads, coalesced value loads),
+// stages the products in LDS, and finishes the rows the chunk owns (those
+// whose first nonzero lies in it; empty rows included).  A row running past
+// its chunk leaves a head partial; every chunk leaves the lead partial of the
+// row entering it; mp_cross sums head + leads in chunk order for the listed
+// spanning rows.  Fixed summation order: deterministic.
+constexpr int MP_NT = 256;
+constexpr int MP_K = (int)(MP_CH / WAVE);
+constexpr int MP_WPB = MP_NT / WAVE;
+
+template <typename T>
+__device__ __forceinline__ void mp_finish(int epi, const SegArgs<T> &a,
+                                          int64_t r, T acc, double &pb,
+                                          double &pr) {
+  seg_epilogue<T>(epi, a, r, r, acc, pb, pr);
+}
+
+template <typename T, int EPI>
+__global__ void __launch_bounds__(MP_NT)
+mp_chunks(Csr<T> A, SegArgs<T> a, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ T sp[MP_WPB][MP_CH];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const int64_t c = (int64_t)blockIdx.x * MP_WPB + wv;
+  double pb = 0.0, pr = 0.0;
+  if (c < A.mp_nchunk) {
+    const int64_t e0 = c * MP_CH;
+    const int64_t eh = A.nnz < e0 + MP_CH ? A.nnz : e0 + MP_CH;   // data end
+    // products of this lane's MP_K consecutive nonzeros
+    const int64_t eb = e0 + (int64_t)lane * MP_K;
+    T pv[MP_K];
+    if (eh == e0 + MP_CH) {
+      // full chunk: one 16-byte index load and MP_K*sizeof(T) value bytes
+      typedef int32_t i4 __attribute__((ext_vector_type(MP_K)));
+      typedef T tv __attribute__((ext_vector_type(MP_K)));
+      const i4 ix = *reinterpret_cast<const i4 *>(A.idx + eb);
+      const tv vv = *reinterpret_cast<const tv *>(A.val + eb);
+#pragma unroll
+      for (int j = 0; j < MP_K; ++j) pv[j] = vv[j] * a.v[ix[j]];
+    } else {
+#pragma unroll
+      for (int j = 0; j < MP_K; ++j) {
+        const int64_t e = eb + j;
+        pv[j] = (T)0;
+        if (e < eh) pv[j] = A.val[e] * a.v[A.idx[e]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < MP_K; ++j) sp[wv][lane * MP_K + j] = pv[j];
+    // lead partial: the row that began before e0 and continues here
+    const int64_t rs = A.mp_rs[c], re = A.mp_rs[c + 1];
+    T lead = (T)0;
+    if (c > 0 && rs > 0) {
+      const int64_t pe = A.ptr[rs] - e0;     // where the entering row stops
+      const int64_t lim = pe < MP_CH ? pe : MP_CH;
+#pragma unroll
+      for (int j = 0; j < MP_K; ++j)
+        if (lane * MP_K + j < lim) lead += pv[j];
+    }
+    lead = wave_sum(lead);
+    if (lane == 0) A.mp_lead[c] = lead;
+    // the products of the whole wave are read back below: order the LDS
+    // stores before the loads (one wave, so a wave-scope fence suffices)
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // owned rows: lane-strided, each summed in element order from LDS
+    for (int64_t r = rs + lane; r < re; r += WAVE) {
+      const int64_t s0 = A.ptr[r] - e0, t0 = A.ptr[r + 1] - e0;
+      const int64_t t = t0 < MP_CH ? t0 : MP_CH;
+      T acc = (T)0;
+      for (int64_t q = s0; q < t; ++q) acc += sp[wv][q];
+      if (t0 > MP_CH) {
+        A.mp_head[c] = acc;                  // finished by mp_cross
+      } else {
+        mp_finish<T>(EPI, a, r, acc, pb, pr);
+      }
+    }
+  }
+  if (EPI == EPI_ROWRES) {
+    __shared__ double sh[MP_NT / WAVE];
+    pb = block_sum<MP_NT>(pb, sh);
+    pr = block_sum<MP_NT>(pr, sh);
+    if (threadIdx.x == 0) {
+      a.part[2 * blockIdx.x] = pb;
+      a.part[2 * blockIdx.x + 1] = pr;
+    }
+  }
+}
+
+template <typename T, int EPI>
+__global__ void __launch_bounds__(MP_NT)
+mp_cross(Csr<T> A, SegArgs<T> a, int64_t part_base, Ctrl *ctrl,
+         int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t x = (int64_t)blockIdx.x * MP_NT + threadIdx.x;
+  double pb = 0.0, pr = 0.0;
+  if (x < A.mp_ncross) {
+    const int64_t r = A.mp_xrow[x];
+    const int64_t cs = A.mp_xcs[x], ce = A.mp_xce[x];
+    T acc = A.mp_head[cs];
+    for (int64_t c = cs + 1; c <= ce; ++c) acc += A.mp_lead[c];
+    mp_finish<T>(EPI, a, r, acc, pb, pr);
+  }
+  if (EPI == EPI_ROWRES) {
+    __shared__ double sh[MP_NT / WAVE];
+    pb = block_sum<MP_NT>(pb, sh);
+    pr = block_sum<MP_NT>(pr, sh);
+    if (threadIdx.x == 0) {
+      a.part[2 * (part_base + blockIdx.x)] = pb;
+      a.part[2 * (part_base + blockIdx.x) + 1] = pr;
+    }
+  }
+}
+
+template <typename T, int EPI>
+static int merge_dispatch(const Csr<T> &A, const SegArgs<T> &a, Ctrl *ctrl,
+                          int respect_done, hipStream_t st) {
+  const int nb = (int)((A.mp_nchunk + MP_WPB - 1) / MP_WPB);
+  hipLaunchKernelGGL((mp_chunks<T, EPI>), dim3(nb), dim3(MP_NT), 0, st, A, a,
+                     ctrl, respect_done);
+  int nparts = nb;
+  if (A.mp_ncross > 0) {
+    const int nx = (int)((A.mp_ncross + MP_NT - 1) / MP_NT);
+    hipLaunchKernelGGL((mp_cross<T, EPI>), dim3(nx), dim3(MP_NT), 0, st, A, a,
+                       (int64_t)nb, ctrl, respect_done);
+    nparts += nx;
+  }
+  return nparts;
+}
+
+int64_t segdot_max_parts(int64_t rows, int64_t nnz, int64_t nchunk,
+                         int64_t ncross, int64_t nlong, int64_t rep) {
+  (void)nnz;
+  const int64_t seg = rows * rep + nlong * rep + 1024;   // G >= 1 lanes
+  const int64_t mer = (nchunk + MP_WPB - 1) / MP_WPB +
+                      (ncross + MP_NT - 1) / MP_NT + 16;
+  return seg > mer ? seg : mer;
+}
+
 template <typename T, int EPI>
 static int segdot_dispatch(const Csr<T> &A, const SegArgs<T> &a, Ctrl *ctrl,
                            int respect_done, hipStream_t st) {
+  if (!a.list && A.rep == 1 && A.mp_rs &&
+      (EPI == EPI_STORE || EPI == EPI_COLRES || EPI == EPI_ROWRES))
+    return merge_dispatch<T, EPI>(A, a, ctrl, respect_done, st);
   const int64_t nseg = a.list ? a.list_cap : A.rows;
   const int G = A.group;
   const int spb = SEG_NT / G;
