@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed_f32")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the sparse pass and batched-form measurements")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: a 1 GiB device copy (calibration) "
                          "and fused-pass launches only, no solves")
@@ -232,6 +234,15 @@ def main():
                     "alg_bytes_per_launch": r["alg_bytes"],
                     "us_per_launch": round(r["us"], 2)}
 
+    extras = None
+    if not args.no_extras:
+        for s in handles.values():
+            s.close()
+        handles = {}
+        del a, b, xs
+        torch.cuda.empty_cache()
+        extras = {"spmv": spmv_powerlaw(), "batched": batched_laplacian()}
+
     cpu = None
     if not args.no_cpu_baseline:
         ref_form = "fp64" if "fp64" in forms else best_form
@@ -254,10 +265,128 @@ def main():
         "roofline": roofline,
         "roofline_all": roof,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(out))
     for s in handles.values():
         s.close()
+
+
+def spmv_powerlaw(reps=20):
+    """Residual passes of the sparse path (CSR row pass + CSC column pass,
+    rgdbek_apply) on the 1,000,000 x 500,000 power-law matrix, FP64 and FP32,
+    timed with HIP events on the handle's stream."""
+    import torch
+    import paper_2509_19267_amd as rg
+    import workloads
+    p = workloads.sparse_powerlaw(1_000_000, 500_000, mean_len=10,
+                                  max_len=2000, seed=0)
+    m, n = p.a.shape
+    nnz = p.a.nnz
+    rp, ci, v = workloads.to_csr_arrays(p.a)
+    st = torch.cuda.Stream()
+    csr = (torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(),
+           torch.as_tensor(v).cuda())
+    s = rg.Solver(csr=csr, shape=(m, n), eta=0.1, precision="mixed_f32",
+                  stream=st)
+    out = {"workload": f"sparse_powerlaw_{m}x{n}", "nnz": int(nnz)}
+    for prec, dt, vb in [("f64", torch.float64, 8), ("f32", torch.float32, 4)]:
+        x = torch.randn(n, dtype=dt, device="cuda")
+        z = torch.randn(m, dtype=dt, device="cuda")
+        ax = torch.empty(m, dtype=dt, device="cuda")
+        atz = torch.empty(n, dtype=dt, device="cuda")
+        torch.cuda.synchronize()
+        for _ in range(3):
+            s.apply(x, z, ax, atz, precision=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            s.apply(x, z, ax, atz, precision=prec)
+        e1.record(st)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        # CSR pass: values + indices + row pointers + x + output; CSC pass
+        # likewise with the roles of m and n swapped
+        alg = 2 * nnz * (vb + 4) + 8 * (m + 1) + 8 * (n + 1) + 2 * vb * (m + n)
+        out[prec] = {"us_per_pair": round(us, 1), "alg_bytes": int(alg),
+                     "GB/s": round(alg / us / 1e3, 1),
+                     "frac": round(alg / us / 1e3 / PEAK_HBM_GBS, 4)}
+        log(f"sparse passes {prec}: {us:.1f} us per CSR+CSC pair, "
+            f"{alg / us / 1e3:.0f} GB/s")
+    s.close()
+    del csr
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_laplacian(count=16, itol=0.1, imax=16, tol=1e-8):
+    """Batched form vs the plain FP64 path on the same inputs: `count`
+    shifted 2-D Laplacians with 20% extra rows (n from 2000 to 20000,
+    values rounded to FP32 storage, planted x*), time to ||x - x*|| <= tol
+    ||x*|| for every system: one batched FP64 solve, one batched mixed solve
+    (FP32 values, FP64 refinement), and the systems one by one with the
+    single-system FP64 solver.  Inner projections: tolerance itol, at most
+    imax CG steps (the same for all three)."""
+    import torch
+    import paper_2509_19267_amd as rg
+    from paper_2509_19267_amd import block_diagonal
+    import workloads
+    ps = workloads.laplacian_batch(count=count, n_min=2000, n_max=20000, seed=0)
+    mats = []
+    for p in ps:
+        a = p.a.copy()
+        a.data = a.data.astype(np.float32).astype(np.float64)
+        mats.append(a)
+    bs = [a @ p.x_star for a, p in zip(mats, ps)]
+    rp, ci, v, ro, co = block_diagonal(mats)
+    csr = (torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(),
+           torch.as_tensor(v).cuda())
+    b = torch.as_tensor(np.concatenate(bs)).cuda()
+    xs_np = np.concatenate([p.x_star for p in ps])
+    xs = torch.as_tensor(xs_np).cuda()
+
+    def timed(s, bb, xr):
+        s.solve(bb, x_ref=xr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = s.solve(bb, x_ref=xr)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, x, info
+
+    out = {"workload": f"laplacian_batch_{count}", "sum_n": int(sum(a.shape[1] for a in mats)),
+           "tol": tol, "inner_tol": itol, "inner_max": imax}
+    for form, c in [("fp64", csr), ("mixed_f32", (csr[0], csr[1], csr[2].to(torch.float32)))]:
+        s = rg.BatchSolver(c, ro, co, eta=0.1, stop="err_ref", tol=tol,
+                           max_iter=50000, inner_max=imax, inner_tol=itol,
+                           precision=form)
+        dt, x, info = timed(s, b, xs)
+        s.close()
+        err = float(np.linalg.norm(x.cpu().numpy() - xs_np) / np.linalg.norm(xs_np))
+        out[f"{form}_batched_ms"] = round(1e3 * dt, 1)
+        out[f"{form}_batched_iterations"] = int(info["iterations"])
+        out[f"{form}_batched_converged"] = bool(info["converged"])
+        out[f"{form}_batched_rel_err"] = err
+        log(f"batched {form}: {1e3 * dt:.1f} ms, {info['iterations']} iterations")
+    tot, its = 0.0, 0
+    for a, bb, p in zip(mats, bs, ps):
+        r0, c0, v0 = workloads.to_csr_arrays(a)
+        s = rg.Solver(csr=(torch.as_tensor(r0).cuda(), torch.as_tensor(c0).cuda(),
+                           torch.as_tensor(v0).cuda()), shape=a.shape, eta=0.1,
+                      stop="err_ref", tol=tol, max_iter=50000, inner_max=imax,
+                      inner_tol=itol)
+        dt, x, info = timed(s, torch.as_tensor(bb).cuda(),
+                            torch.as_tensor(p.x_star).cuda())
+        s.close()
+        tot += dt
+        its += int(info["iterations"])
+    out["fp64_one_by_one_ms"] = round(1e3 * tot, 1)
+    out["fp64_one_by_one_iterations"] = its
+    out["speedup_batched_fp64_vs_one_by_one"] = round(tot * 1e3 / out["fp64_batched_ms"], 3)
+    out["speedup_batched_mixed_vs_one_by_one"] = round(tot * 1e3 / out["mixed_f32_batched_ms"], 3)
+    log(f"one by one fp64: {1e3 * tot:.1f} ms")
+    return out
 
 
 def cpu_baseline(prob, choice, gpu_iters, budget_s=20.0):

@@ -48,13 +48,15 @@ void launch_select(const T *eps, int64_t d, int64_t k, double floor,
 
 // Per-system draws for a block-diagonal batch (one workgroup per system);
 // the concatenated global index list goes to out, its length to
-// Ctrl::sel_count[ph].  tmp/cnt: scratch (sum of block sizes / nseg).
+// Ctrl::sel_count[ph].  dmax: the largest system dimension of the phase;
+// segmax/tmp/cnt: scratch (nseg / sum of block sizes / nseg).
 template <typename T>
 void launch_select_seg(const T *eps, const SegInfo *seg, int nseg, int ph,
-                       double floor, uint64_t seed, uint64_t key1,
-                       uint32_t phase, uint64_t *keys, int32_t *tmp,
-                       int64_t *cnt, int32_t *out, Ctrl *ctrl,
-                       int respect_done, hipStream_t st);
+                       int64_t dmax, double floor, uint64_t seed,
+                       uint64_t key1, uint32_t phase, uint64_t *keys,
+                       double *segmax, int32_t *tmp, int64_t *cnt,
+                       int32_t *out, Ctrl *ctrl, int respect_done,
+                       hipStream_t st);
 
 // Per-system control of a batch (batch.hip): reference norms, state reset,
 // ERR_REF / RSE / RES_EXT per system, and the fold into Ctrl.

@@ -14,6 +14,8 @@
 // Sparse blocks: matrix-free CGLS (columns, z updated as the CGLS residual)
 // and CGNE on A^J A^J^T (rows), the wide products streaming the full CSR/CSC
 // with a direction vector that is zero outside the block.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -708,6 +710,8 @@ void launch_list_resid(const T *Arm, int64_t ld, int64_t len,
 //         v = A^J u, alpha = rz / <p, v>                [narrow, last block]
 //         res -= alpha v, zz = res/rho, beta, p = zz + beta p
 constexpr int SC_NT = 256;
+constexpr unsigned SC_MAXB = 512;   // blocks of a launch that ends in a ticket
+constexpr int SC_UNROLL = 8;        // loads in flight in one-block list walks
 
 template <typename T, int G>
 __global__ void __launch_bounds__(SC_NT)
@@ -718,20 +722,25 @@ sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
   __shared__ double sh[SC_NT / WAVE];
   constexpr int SPB = SC_NT / G;
   const int lg = threadIdx.x & (G - 1);
-  const int64_t slot = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
-  int64_t s = 0, br = 0, co = 0;
-  T acc = 0;
-  if (slot < A.rows) {
-    vrow(A, slot, s, br, co);
-    const T *ph = phat + co;
-    const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * ph[A.idx[e]];
-  }
-  acc = group_sum<G>(acc);
   double qq = 0.0;
-  if (slot < A.rows && lg == 0) {
-    q[s] = acc;
-    qq = (double)acc * (double)acc;
+  // grid-stride over row segments: a bounded grid keeps the final ticket
+  // and the partials to reduce few
+  for (int64_t slot0 = (int64_t)blockIdx.x * SPB; slot0 < A.rows;
+       slot0 += (int64_t)gridDim.x * SPB) {
+    const int64_t slot = slot0 + threadIdx.x / G;
+    int64_t s = 0, br = 0, co = 0;
+    T acc = 0;
+    if (slot < A.rows) {
+      vrow(A, slot, s, br, co);
+      const T *ph = phat + co;
+      const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
+      for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * ph[A.idx[e]];
+    }
+    acc = group_sum<G>(acc);
+    if (slot < A.rows && lg == 0) {
+      q[s] = acc;
+      qq += (double)acc * (double)acc;
+    }
   }
   qq = block_sum<SC_NT>(qq, sh);
   if (threadIdx.x == 0) st_agent(&part[blockIdx.x], qq);
@@ -766,24 +775,27 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
   const int64_t i0 = (int64_t)blockIdx.x * per;
   for (int64_t i = i0 + threadIdx.x; i < i0 + per && i < m; i += SC_NT)
     z[i] -= (T)alpha * q[i];
-  // narrow part
+  // narrow part (grid-stride over the listed columns)
   constexpr int SPB = SC_NT / G;
   const int lg = threadIdx.x & (G - 1);
-  const int64_t a = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
-  T acc = 0;
-  if (a < c) {
-    int64_t bc, ro;
-    gsplit(At, (int64_t)U[a], bc, ro);
-    const T *qv = q + ro;
-    const int64_t e0 = At.ptr[bc], e1 = At.ptr[bc + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * qv[At.idx[e]];
-  }
-  acc = group_sum<G>(acc);
   double ss = 0.0;
-  if (a < c && lg == 0) {
-    const T sv = sres[a] - (T)alpha * acc;
-    sres[a] = sv;
-    ss = (double)sv * (double)sv;
+  for (int64_t a0 = (int64_t)blockIdx.x * SPB; a0 < c;
+       a0 += (int64_t)gridDim.x * SPB) {
+    const int64_t a = a0 + threadIdx.x / G;
+    T acc = 0;
+    if (a < c) {
+      int64_t bc, ro;
+      gsplit(At, (int64_t)U[a], bc, ro);
+      const T *qv = q + ro;
+      const int64_t e0 = At.ptr[bc], e1 = At.ptr[bc + 1];
+      for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * qv[At.idx[e]];
+    }
+    acc = group_sum<G>(acc);
+    if (a < c && lg == 0) {
+      const T sv = sres[a] - (T)alpha * acc;
+      sres[a] = sv;
+      ss += (double)sv * (double)sv;
+    }
   }
   ss = block_sum<SC_NT>(ss, sh);
   if (threadIdx.x == 0) st_agent(&part[blockIdx.x], ss);
@@ -793,10 +805,24 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
   tot = block_sum<SC_NT>(tot, sh);
   const double gam = ctrl->cg_rz[0];
   const double beta = gam > 0.0 ? tot / gam : 0.0;
-  for (int64_t k = threadIdx.x; k < c; k += SC_NT) {
-    const T pv = ld_agent(&sres[k]) + (T)beta * p[k];
-    p[k] = pv;
-    phat[U[k]] = pv;
+  // one block walks the whole list: keep SC_UNROLL loads in flight
+  for (int64_t k0 = threadIdx.x; k0 < c; k0 += SC_UNROLL * SC_NT) {
+    T sv[SC_UNROLL], po[SC_UNROLL];
+    int32_t ix[SC_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SC_UNROLL; ++u) {
+      const int64_t k = k0 + (int64_t)u * SC_NT;
+      if (k < c) { sv[u] = ld_agent(&sres[k]); po[u] = p[k]; ix[u] = U[k]; }
+    }
+#pragma unroll
+    for (int u = 0; u < SC_UNROLL; ++u) {
+      const int64_t k = k0 + (int64_t)u * SC_NT;
+      if (k < c) {
+        const T pv = sv[u] + (T)beta * po[u];
+        p[k] = pv;
+        phat[ix[u]] = pv;
+      }
+    }
   }
   if (threadIdx.x == 0) {
     ctrl->cg_rz[0] = tot;
@@ -810,12 +836,14 @@ __global__ void __launch_bounds__(SC_NT)
 sc_init(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
         const T *__restrict__ rhs_src, const double *__restrict__ jac,
         T *__restrict__ sres, T *__restrict__ zz_or_null, T *__restrict__ p,
-        T *__restrict__ phat, Ctrl *ctrl, int ph, int respect_done) {
+        T *__restrict__ phat, double *__restrict__ part, Ctrl *ctrl, int ph,
+        int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   __shared__ double sh[SC_NT / WAVE];
   const int64_t c = *cnt;
   double rz = 0.0, rr = 0.0;
-  for (int64_t a = threadIdx.x; a < c; a += SC_NT) {
+  for (int64_t a = (int64_t)blockIdx.x * SC_NT + threadIdx.x; a < c;
+       a += (int64_t)gridDim.x * SC_NT) {
     const int64_t l = list[a];
     const T h = rhs_src[l];
     sres[a] = h;
@@ -829,6 +857,19 @@ sc_init(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
     phat[l] = zz;
     rz += (double)h * (double)zz;
     rr += (double)h * (double)h;
+  }
+  rz = block_sum<SC_NT>(rz, sh);
+  rr = block_sum<SC_NT>(rr, sh);
+  if (threadIdx.x == 0) {
+    st_agent(&part[2 * blockIdx.x], rz);
+    st_agent(&part[2 * blockIdx.x + 1], rr);
+  }
+  if (!last_block(&ctrl->ticket[6])) return;
+  rz = 0.0;
+  rr = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += SC_NT) {
+    rz += ld_agent(&part[2 * b]);
+    rr += ld_agent(&part[2 * b + 1]);
   }
   rz = block_sum<SC_NT>(rz, sh);
   rr = block_sum<SC_NT>(rr, sh);
@@ -893,20 +934,23 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
   const int64_t c = *cnt;
   constexpr int SPB = SC_NT / G;
   const int lg = threadIdx.x & (G - 1);
-  const int64_t a = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
-  T acc = 0;
-  if (a < c) {
-    int64_t brw, co;
-    gsplit(A, (int64_t)J[a], brw, co);
-    const T *uv = u + co;
-    const int64_t e0 = A.ptr[brw], e1 = A.ptr[brw + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * uv[A.idx[e]];
-  }
-  acc = group_sum<G>(acc);
   double pv = 0.0;
-  if (a < c && lg == 0) {
-    v[a] = acc;
-    pv = (double)acc * (double)p[a];
+  for (int64_t a0 = (int64_t)blockIdx.x * SPB; a0 < c;
+       a0 += (int64_t)gridDim.x * SPB) {
+    const int64_t a = a0 + threadIdx.x / G;
+    T acc = 0;
+    if (a < c) {
+      int64_t brw, co;
+      gsplit(A, (int64_t)J[a], brw, co);
+      const T *uv = u + co;
+      const int64_t e0 = A.ptr[brw], e1 = A.ptr[brw + 1];
+      for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * uv[A.idx[e]];
+    }
+    acc = group_sum<G>(acc);
+    if (a < c && lg == 0) {
+      v[a] = acc;
+      pv += (double)acc * (double)p[a];
+    }
   }
   pv = block_sum<SC_NT>(pv, sh);
   if (threadIdx.x == 0) st_agent(&part[blockIdx.x], pv);
@@ -917,22 +961,48 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
   const double rz = ctrl->cg_rz[1];
   const double alpha = tot != 0.0 ? rz / tot : 0.0;
   double rz1 = 0.0, rr = 0.0;
-  for (int64_t k = threadIdx.x; k < c; k += SC_NT) {
-    const T r = res[k] - (T)alpha * ld_agent(&v[k]);
-    res[k] = r;
-    const double dj = rho[J[k]];
-    const T zv = dj > 0.0 ? (T)((double)r / dj) : (T)0;
-    zz[k] = zv;
-    rz1 += (double)r * (double)zv;
-    rr += (double)r * (double)r;
+  // one block walks the whole list: keep SC_UNROLL loads in flight
+  for (int64_t k0 = threadIdx.x; k0 < c; k0 += SC_UNROLL * SC_NT) {
+    T rv[SC_UNROLL], vv[SC_UNROLL];
+    double dj[SC_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SC_UNROLL; ++u) {
+      const int64_t k = k0 + (int64_t)u * SC_NT;
+      if (k < c) { rv[u] = res[k]; vv[u] = ld_agent(&v[k]); dj[u] = rho[J[k]]; }
+    }
+#pragma unroll
+    for (int u = 0; u < SC_UNROLL; ++u) {
+      const int64_t k = k0 + (int64_t)u * SC_NT;
+      if (k < c) {
+        const T r = rv[u] - (T)alpha * vv[u];
+        res[k] = r;
+        const T zv = dj[u] > 0.0 ? (T)((double)r / dj[u]) : (T)0;
+        zz[k] = zv;
+        rz1 += (double)r * (double)zv;
+        rr += (double)r * (double)r;
+      }
+    }
   }
   rz1 = block_sum<SC_NT>(rz1, sh);
   rr = block_sum<SC_NT>(rr, sh);
   const double beta = rz != 0.0 ? rz1 / rz : 0.0;
-  for (int64_t k = threadIdx.x; k < c; k += SC_NT) {
-    const T pn = zz[k] + (T)beta * p[k];
-    p[k] = pn;
-    phat[J[k]] = pn;
+  for (int64_t k0 = threadIdx.x; k0 < c; k0 += SC_UNROLL * SC_NT) {
+    T zv[SC_UNROLL], po[SC_UNROLL];
+    int32_t ix[SC_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SC_UNROLL; ++u) {
+      const int64_t k = k0 + (int64_t)u * SC_NT;
+      if (k < c) { zv[u] = zz[k]; po[u] = p[k]; ix[u] = J[k]; }
+    }
+#pragma unroll
+    for (int u = 0; u < SC_UNROLL; ++u) {
+      const int64_t k = k0 + (int64_t)u * SC_NT;
+      if (k < c) {
+        const T pn = zv[u] + (T)beta * po[u];
+        p[k] = pn;
+        phat[ix[u]] = pn;
+      }
+    }
   }
   if (threadIdx.x == 0) {
     ctrl->cg_alpha[1] = alpha;
@@ -951,6 +1021,12 @@ sc_row_finish(int64_t n, const T *__restrict__ u, T *__restrict__ x,
   const double alpha = ctrl->cg_alpha[1];
   const int64_t j = (int64_t)blockIdx.x * SC_NT + threadIdx.x;
   if (j < n && alpha != 0.0) x[j] += (T)alpha * u[j];
+}
+
+static unsigned sc_init_blocks(int64_t cap) {
+  int64_t b = (cap + SC_NT - 1) / SC_NT;
+  if (b > 256) b = 256;
+  return (unsigned)(b < 1 ? 1 : b);
 }
 
 template <typename T>
@@ -975,11 +1051,11 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
                            int64_t cap, const T *g, T *z, SparseCg<T> &w,
                            int max_steps, double tol, Ctrl *ctrl,
                            int respect_done, hipStream_t st) {
-  hipLaunchKernelGGL(sc_init<T>, dim3(1), dim3(SC_NT), 0, st, U, count_dev, g,
-                     (const double *)nullptr, w.res, (T *)nullptr, w.p, w.phat,
-                     ctrl, 0, respect_done);
-  const unsigned nbw = seg_blocks<T>(csr.rows, csr.group);
-  unsigned nbn = seg_blocks<T>(cap, csc.group);
+  hipLaunchKernelGGL(sc_init<T>, dim3(sc_init_blocks(cap)), dim3(SC_NT), 0, st,
+                     U, count_dev, g, (const double *)nullptr, w.res,
+                     (T *)nullptr, w.p, w.phat, w.part, ctrl, 0, respect_done);
+  const unsigned nbw = std::min<unsigned>(seg_blocks<T>(csr.rows, csr.group), SC_MAXB);
+  unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csc.group), SC_MAXB);
   if (nbn < 64) nbn = 64;
   for (int s = 0; s < max_steps; ++s) {
     RG_SWITCH_G(csr.group, hipLaunchKernelGGL((sc_wide_col<T, GG>), dim3(nbw),
@@ -1002,11 +1078,12 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                            int64_t cap, const T *r, const double *rho, T *x,
                            SparseCg<T> &w, int max_steps, double tol,
                            Ctrl *ctrl, int respect_done, hipStream_t st) {
-  hipLaunchKernelGGL(sc_init<T>, dim3(1), dim3(SC_NT), 0, st, J, count_dev, r,
-                     rho, w.res, w.v, w.p, w.phat, ctrl, 1, respect_done);
+  hipLaunchKernelGGL(sc_init<T>, dim3(sc_init_blocks(cap)), dim3(SC_NT), 0, st,
+                     J, count_dev, r, rho, w.res, w.v, w.p, w.phat, w.part,
+                     ctrl, 1, respect_done);
   // w.v doubles as the Jacobi-scaled residual buffer zz during steps
   const unsigned nbw = seg_blocks<T>(csc.rows, csc.group);
-  const unsigned nbn = seg_blocks<T>(cap, csr.group);
+  const unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csr.group), SC_MAXB);
   for (int s = 0; s < max_steps; ++s) {
     RG_SWITCH_G(csc.group, hipLaunchKernelGGL((sc_wide_row<T, GG>), dim3(nbw),
                                               dim3(SC_NT), 0, st, csc, w.phat,

@@ -106,6 +106,8 @@ struct Engine {
   double *part = nullptr;     // row-residual partials
   double floor = 0.0;         // relative weight floor of the block draws
   int32_t *seltmp = nullptr;  // per-system draws before packing (batch)
+  double *segmax = nullptr;   // per-system largest weight (batch)
+  int64_t seg_dmax[2] = {0, 0};  // largest system dimension per phase
   int64_t *selcnt = nullptr;  // per-system draw counts (batch)
   int nseg = 0;               // systems (0: a single system)
   SegInfo *seg = nullptr;
@@ -347,6 +349,13 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   if (h->nseg) {
     e.seltmp = P.alloc<int32_t>(std::max(e.kc, e.kr) + 64);
     e.selcnt = P.alloc<int64_t>(h->nseg + 1);
+    e.segmax = P.alloc<double>(h->nseg + 1);
+    for (const SegInfo &g : h->hseg) {
+      const int64_t dc = transpose ? g.nrow : g.ncol;
+      const int64_t dr = transpose ? g.ncol : g.nrow;
+      e.seg_dmax[0] = std::max(e.seg_dmax[0], dc);
+      e.seg_dmax[1] = std::max(e.seg_dmax[1], dr);
+    }
     e.nseg = h->nseg;
     e.seg = transpose ? h->seg_t : h->seg;
   }
@@ -425,8 +434,9 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     launch_segdot<T>(e.csc, EPI_COLRES, a, c, 1, st);
   }
   if (ns)
-    launch_select_seg<T>(e.eps_z, e.seg, ns, 0, e.floor, p.seed, o.key1, 0,
-                         e.sel.keys, e.seltmp, e.selcnt, e.U, c, 1, st);
+    launch_select_seg<T>(e.eps_z, e.seg, ns, 0, e.seg_dmax[0], e.floor, p.seed,
+                         o.key1, 0, e.sel.keys, e.segmax, e.seltmp, e.selcnt,
+                         e.U, c, 1, st);
   else
     launch_select<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0,
                      e.sel, e.U, c, 1, st);
@@ -471,8 +481,9 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     }
   }
   if (ns)
-    launch_select_seg<T>(e.eps_x, e.seg, ns, 1, e.floor, p.seed, o.key1, 1,
-                         e.sel.keys, e.seltmp, e.selcnt, e.J, c, 1, st);
+    launch_select_seg<T>(e.eps_x, e.seg, ns, 1, e.seg_dmax[1], e.floor, p.seed,
+                         o.key1, 1, e.sel.keys, e.segmax, e.seltmp, e.selcnt,
+                         e.J, c, 1, st);
   else
     launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1,
                      e.sel, e.J, c, 1, st);

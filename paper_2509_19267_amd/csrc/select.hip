@@ -133,229 +133,257 @@ __device__ __forceinline__ int64_t compact_chunk(const uint64_t *keys,
 
 // ------------------------------------------------ one-workgroup selection
 // One workgroup of 1024 threads draws the block from d weights.  keys:
-// scratch of d entries; writes out[0..count) (local indices), returns count
-// (the same value in every thread); raises *numeric on a bad weight.
+// scratch of d entries (written once, then read by the radix levels);
+// writes out[0..count) (local indices), returns count (the same value in
+// every thread); raises *numeric on a bad weight.  Radix levels of 11, 11,
+// 11, 11, 11, 9 bits with LDS histograms until the bucket holding rank k has
+// at most WG_CAND keys; those are gathered into LDS (any order) and ranked
+// by counting, giving the k-th pair (key, index); an ordered ballot/scan
+// compaction writes the block.  More than WG_CAND equal keys: the tie index
+// comes from an ordered scan.
+constexpr int WG_NT = 1024;
+constexpr int WG_CAND = WG_NT;
+constexpr int WG_UNROLL = 8;
+
+__device__ __forceinline__ int wg_shift(int lev) { return lev < 5 ? 53 - 11 * lev : 0; }
+__device__ __forceinline__ int wg_width(int lev) { return lev < 5 ? 11 : 9; }
+
+// exclusive prefix of v over the workgroup (thread order); *tot = sum
+__device__ __forceinline__ int64_t wg_scan(int64_t v, int64_t *sh, int64_t *tot) {
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  int64_t inc = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int64_t u = __shfl_up(inc, o, WAVE);
+    if (lane >= o) inc += u;
+  }
+  __syncthreads();
+  if (lane == WAVE - 1) sh[wv] = inc;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < WG_NT / WAVE; ++i) {
+    if (i < wv) before += sh[i];
+    all += sh[i];
+  }
+  *tot = all;
+  return before + inc - v;
+}
+
+// From keys (d of them, SENT for zero weights), the count of positive keys
+// and the LDS histogram of their top 11 bits: find the threshold pair and
+// write the ordered block to out; returns its size (same in every thread).
+__device__ int64_t resolve_compact(const uint64_t *__restrict__ keys,
+                                   int64_t d, int64_t k, int64_t pos,
+                                   unsigned *hist, int32_t *__restrict__ out) {
+  constexpr int NT = WG_NT;
+  __shared__ int64_t sh64[NT / WAVE];
+  __shared__ uint64_t s_ck[WG_CAND];
+  __shared__ int32_t s_ci[WG_CAND];
+  __shared__ unsigned s_nc;
+  __shared__ int64_t s_b, s_acc, s_cb, s_tidx;
+  __shared__ uint64_t s_tkey;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  uint64_t lo, tkey;
+  int64_t tidx;
+  if (pos <= k) {
+    lo = SENT; tkey = SENT; tidx = -1;
+  } else {
+    uint64_t prefix = 0;
+    int64_t krem = k;
+    int lev = 0;
+    while (true) {
+      const int sh = wg_shift(lev), wd = wg_width(lev);
+      const int nb = 1 << wd;
+      if (wv == 0) {
+        const int per = nb / WAVE;
+        int64_t ls = 0;
+        for (int i = 0; i < per; ++i) ls += hist[lane * per + i];
+        int64_t inc = ls;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+          const int64_t u = __shfl_up(inc, o, WAVE);
+          if (lane >= o) inc += u;
+        }
+        const int64_t exc = inc - ls;
+        if (exc < krem && krem <= inc) {
+          int64_t acc = exc;
+          int b = lane * per;
+          for (;; ++b) {
+            if (acc + (int64_t)hist[b] >= krem) break;
+            acc += hist[b];
+          }
+          s_b = b;
+          s_acc = acc;
+          s_cb = hist[b];
+        }
+      }
+      if (tid == 0) s_nc = 0u;
+      __syncthreads();
+      prefix = (prefix << wd) | (uint64_t)s_b;
+      krem -= s_acc;
+      const int64_t cb = s_cb;
+      __syncthreads();
+      if (cb == krem) {
+        lo = (prefix + 1ull) << sh;
+        tkey = SENT; tidx = -1;
+        break;
+      }
+      if (cb <= WG_CAND) {
+        // gather the bucket into LDS (any order) and rank by counting
+        for (int64_t j0 = tid; j0 < d; j0 += WG_UNROLL * NT) {
+          uint64_t kv[WG_UNROLL];
+#pragma unroll
+          for (int u = 0; u < WG_UNROLL; ++u) {
+            const int64_t j = j0 + (int64_t)u * NT;
+            kv[u] = j < d ? keys[j] : SENT;
+          }
+#pragma unroll
+          for (int u = 0; u < WG_UNROLL; ++u)
+            if (kv[u] != SENT && (kv[u] >> sh) == prefix) {
+              const unsigned slot = atomicAdd(&s_nc, 1u);
+              s_ck[slot] = kv[u];
+              s_ci[slot] = (int32_t)(j0 + (int64_t)u * NT);
+            }
+        }
+        __syncthreads();
+        const int nc = (int)cb;
+        if (tid < nc) {
+          const uint64_t a = s_ck[tid];
+          const int32_t ai = s_ci[tid];
+          int64_t rank = 0;
+          for (int u = 0; u < nc; ++u) {
+            const uint64_t b = s_ck[u];
+            rank += (b < a) || (b == a && s_ci[u] < ai);
+          }
+          if (rank == krem - 1) { s_tkey = a; s_tidx = ai; }
+        }
+        __syncthreads();
+        tkey = s_tkey;
+        tidx = s_tidx;
+        lo = tkey;
+        break;
+      }
+      if (sh == 0) {
+        // more than WG_CAND equal keys: the krem-th of them in index order
+        tkey = prefix;
+        if (tid == 0) s_tidx = -1;
+        int64_t seen = 0;
+        for (int64_t base = 0; base < d && seen < krem; base += NT) {
+          const int64_t j = base + tid;
+          const int64_t f = (j < d && keys[j] == tkey) ? 1 : 0;
+          int64_t tot;
+          const int64_t r = seen + wg_scan(f, sh64, &tot);
+          if (f && r == krem - 1) s_tidx = j;
+          seen += tot;
+        }
+        __syncthreads();
+        tidx = s_tidx;
+        lo = tkey;
+        break;
+      }
+      // histogram of the next digit inside the bucket
+      const int nsh = wg_shift(lev + 1), nwd = wg_width(lev + 1);
+      for (int i = tid; i < (1 << nwd); i += NT) hist[i] = 0u;
+      __syncthreads();
+      for (int64_t j0 = tid; j0 < d; j0 += WG_UNROLL * NT) {
+        uint64_t kv[WG_UNROLL];
+#pragma unroll
+        for (int u = 0; u < WG_UNROLL; ++u) {
+          const int64_t j = j0 + (int64_t)u * NT;
+          kv[u] = j < d ? keys[j] : SENT;
+        }
+#pragma unroll
+        for (int u = 0; u < WG_UNROLL; ++u)
+          if (kv[u] != SENT && (kv[u] >> sh) == prefix)
+            atomicAdd(&hist[(kv[u] >> nsh) & ((1u << nwd) - 1u)], 1u);
+      }
+      __syncthreads();
+      ++lev;
+    }
+  }
+  // ordered compaction, four consecutive indices per thread per pass
+  int64_t off = 0;
+  for (int64_t base = 0; base < d; base += 4 * NT) {
+    const int64_t j0 = base + 4 * (int64_t)tid;
+    bool f[4];
+    int64_t c = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = j0 + q;
+      f[q] = j < d && take(keys[j], j, lo, tkey, tidx);
+      c += f[q];
+    }
+    int64_t tot;
+    int64_t r = off + wg_scan(c, sh64, &tot);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (f[q]) out[r++] = (int32_t)(j0 + q);
+    off += tot;
+  }
+  return off;
+}
+
 template <typename T>
 __device__ int64_t select_wg(const T *__restrict__ eps, int64_t d, int64_t k,
                              double floor, uint64_t seed, uint64_t key1,
                              uint64_t it, uint32_t phase, uint32_t sys,
                              uint64_t *__restrict__ keys,
                              int32_t *__restrict__ out, int *numeric) {
-  constexpr int NT = 1024;
-  __shared__ unsigned hist[256];
+  constexpr int NT = WG_NT;
+  __shared__ unsigned hist[2048];
   __shared__ int64_t sh64[NT / WAVE];
-  __shared__ int wtot[NT / WAVE];
-  __shared__ uint64_t s_prefix;
-  __shared__ int64_t s_krem, s_tidx;
-  __shared__ int s_done;
   __shared__ double shmax[NT / WAVE];
-  constexpr int SS = 2048;        // samples
-  constexpr int SW = 64;          // bracket half-width in sample ranks
-  constexpr int SCAND = 8192;     // largest bracket sorted in LDS
-  __shared__ uint64_t s_samp_key[SCAND];
-  __shared__ int32_t s_cand_idx[SCAND];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  // 1. largest finite weight
+  // (the passes over d issue WG_UNROLL independent loads per thread at a
+  // time: one workgroup has no other latency hiding)
   double mx = 0.0;
-  for (int64_t j = threadIdx.x; j < d; j += NT) {
-    const double e = (double)eps[j];
-    mx = e > mx ? e : mx;
+  for (int64_t j0 = tid; j0 < d; j0 += WG_UNROLL * NT) {
+    double e[WG_UNROLL];
+#pragma unroll
+    for (int u = 0; u < WG_UNROLL; ++u) {
+      const int64_t j = j0 + (int64_t)u * NT;
+      e[u] = j < d ? (double)eps[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < WG_UNROLL; ++u)
+      if (e[u] <= 1.7976931348623157e308) mx = e[u] > mx ? e[u] : mx;
   }
   mx = wave_max(mx);
-  if ((threadIdx.x & (WAVE - 1)) == 0) shmax[threadIdx.x / WAVE] = mx;
+  if (lane == 0) shmax[wv] = mx;
+  for (int i = tid; i < 2048; i += NT) hist[i] = 0u;
   __syncthreads();
   mx = 0.0;
   for (int i = 0; i < NT / WAVE; ++i) mx = shmax[i] > mx ? shmax[i] : mx;
   const double cut = floor > 0.0 ? floor * mx : 0.0;
+  // 2. keys and the top-digit histogram
   int bad = 0;
   int64_t pos = 0;
-  for (int64_t g = threadIdx.x; g * 4 < d; g += NT) {
+  for (int64_t g = tid; g * 4 < d; g += NT) {
+    double ev[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t j = g * 4 + q;
+      ev[q] = j < d ? (double)eps[j] : 0.0;
+    }
     const P4 r = philox4x64_10((uint64_t)g, it, phase, sys, seed, key1);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t j = g * 4 + q;
       if (j < d) {
-        const uint64_t kk = make_key((double)eps[j], r.v[q], cut, &bad);
+        const uint64_t kk = make_key(ev[q], r.v[q], cut, &bad);
         keys[j] = kk;
-        pos += (kk != SENT);
+        if (kk != SENT) {
+          ++pos;
+          atomicAdd(&hist[kk >> 53], 1u);
+        }
       }
     }
   }
   if (bad) atomicOr(numeric, 1);
-  pos = block_sum_i64<NT>(pos, sh64);
-  __syncthreads();   // keys visible to the whole workgroup
-
-  uint64_t lo, tkey;
-  int64_t tidx;
-  bool resolved = false;
-  if (pos <= k) {
-    lo = SENT; tkey = SENT; tidx = -1;
-    resolved = true;
-  } else {
-    // Sample select: sort SS keys taken at fixed positions, bracket the rank
-    // k by sample ranks +-SW, count the keys below and inside the bracket,
-    // gather the bracket in index order and sort it.  Any miss falls back
-    // to the radix select below (same result, slower).
-    uint64_t *sk = s_samp_key;
-    const int64_t p_est = (k * SS) / d;
-    for (int i = threadIdx.x; i < SS; i += NT)
-      sk[i] = keys[((int64_t)i * d) / SS];
-    __syncthreads();
-    for (int size = 2; size <= SS; size <<= 1)
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int i = threadIdx.x; i < SS; i += NT) {
-          const int q = i ^ stride;
-          if (q > i) {
-            const uint64_t a = sk[i], b = sk[q];
-            if ((a > b) == ((i & size) == 0)) { sk[i] = b; sk[q] = a; }
-          }
-        }
-        __syncthreads();
-      }
-    const int64_t il = p_est - SW, ih = p_est + SW;
-    const uint64_t wlo = il <= 0 ? 0ull : sk[il];
-    const uint64_t whi = ih >= SS ? SENT - 1 : sk[ih];
-    __syncthreads();
-    int64_t clt = 0, cwin = 0;
-    for (int64_t j = threadIdx.x; j < d; j += NT) {
-      const uint64_t kk = keys[j];
-      if (kk == SENT) continue;
-      clt += kk < wlo;
-      cwin += (kk >= wlo && kk <= whi);
-    }
-    clt = block_sum_i64<NT>(clt, sh64);
-    cwin = block_sum_i64<NT>(cwin, sh64);
-    if (clt < k && k <= clt + cwin && cwin <= SCAND) {
-      // gather the bracket in index order (ballot compaction)
-      uint64_t *ck = s_samp_key;
-      int32_t *ci = s_cand_idx;
-      int64_t off = 0;
-      for (int64_t base = 0; base < d; base += NT) {
-        const int64_t j = base + threadIdx.x;
-        const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-        bool f = false;
-        uint64_t kk = 0;
-        if (j < d) {
-          kk = keys[j];
-          f = kk != SENT && kk >= wlo && kk <= whi;
-        }
-        const uint64_t mask = __ballot(f);
-        __syncthreads();
-        if (lane == 0) wtot[wv] = __popcll(mask);
-        __syncthreads();
-        int wb = 0, tot = 0;
-        for (int i = 0; i < NT / WAVE; ++i) {
-          if (i < wv) wb += wtot[i];
-          tot += wtot[i];
-        }
-        if (f) {
-          const int64_t slot = off + wb + __popcll(mask & ((1ull << lane) - 1ull));
-          ck[slot] = kk;
-          ci[slot] = (int32_t)j;
-        }
-        off += tot;
-      }
-      int np2 = 1;
-      while (np2 < cwin) np2 <<= 1;
-      for (int64_t i = cwin + threadIdx.x; i < np2; i += NT) {
-        ck[i] = SENT;
-        ci[i] = INT32_MAX;
-      }
-      __syncthreads();
-      for (int size = 2; size <= np2; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          for (int i = threadIdx.x; i < np2; i += NT) {
-            const int q = i ^ stride;
-            if (q > i) {
-              const uint64_t a = ck[i], b = ck[q];
-              const int32_t ai = ci[i], bi = ci[q];
-              const bool gt = (a > b) || (a == b && ai > bi);
-              if (gt == ((i & size) == 0)) {
-                ck[i] = b; ck[q] = a; ci[i] = bi; ci[q] = ai;
-              }
-            }
-          }
-          __syncthreads();
-        }
-      tkey = ck[k - clt - 1];
-      tidx = ci[k - clt - 1];
-      lo = tkey;
-      resolved = true;
-      __syncthreads();
-    }
-  }
-  if (!resolved) {
-    // MSB-first radix select of the k-th smallest key, 8 bits per pass.
-    if (threadIdx.x == 0) { s_prefix = 0; s_krem = k; s_done = 0; }
-    int shift = 64;
-    __syncthreads();
-    uint64_t bound_lo = 0;
-    bool resolved_bucket = false;
-    for (int pass = 0; pass < 8; ++pass) {
-      const int nshift = shift - 8;
-      for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
-      __syncthreads();
-      const uint64_t pre = s_prefix;
-      for (int64_t j = threadIdx.x; j < d; j += NT) {
-        const uint64_t kk = keys[j];
-        if (kk == SENT) continue;
-        if (shift < 64 && (kk >> shift) != pre) continue;
-        atomicAdd(&hist[(kk >> nshift) & 255u], 1u);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int64_t kr = s_krem, acc = 0;
-        int b = 0;
-        for (; b < 256; ++b) {
-          if (acc + (int64_t)hist[b] >= kr) break;
-          acc += hist[b];
-        }
-        s_prefix = (pre << 8) | (uint64_t)b;
-        s_krem = kr - acc;
-        s_done = ((int64_t)hist[b] == kr - acc) ? 1 : 0;
-      }
-      __syncthreads();
-      shift = nshift;
-      if (s_done) {
-        resolved_bucket = true;
-        bound_lo = (shift == 0) ? s_prefix + 1 : ((s_prefix + 1) << shift);
-        break;
-      }
-    }
-    if (resolved_bucket && !(shift == 0 && s_prefix == SENT)) {
-      lo = bound_lo; tkey = SENT; tidx = -1;
-    } else {
-      // all 64 bits resolved: take the first krem indices with key == prefix
-      tkey = s_prefix;
-      lo = tkey;
-      const int64_t krem = s_krem;
-      int64_t seen = 0;
-      if (threadIdx.x == 0) s_tidx = -1;
-      __syncthreads();
-      for (int64_t base = 0; base < d && seen < krem; base += NT) {
-        const int64_t j = base + threadIdx.x;
-        const bool f = (j < d) && keys[j] == tkey;
-        const uint64_t mask = __ballot(f);
-        const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-        __syncthreads();
-        if (lane == 0) wtot[wv] = __popcll(mask);
-        __syncthreads();
-        int64_t wb = 0, tot = 0;
-        for (int i = 0; i < NT / WAVE; ++i) {
-          if (i < wv) wb += wtot[i];
-          tot += wtot[i];
-        }
-        const int64_t rank = seen + wb + __popcll(mask & ((1ull << lane) - 1ull));
-        if (f && rank == krem - 1) s_tidx = j;
-        seen += tot;
-        __syncthreads();
-      }
-      tidx = s_tidx;
-    }
-  }
-  // ordered compaction
-  int64_t off = 0;
-  for (int64_t base = 0; base < d; base += NT)
-    off += compact_chunk<NT>(keys, base, d, lo, tkey, tidx, out, off, wtot);
-  return off;
+  pos = block_sum_i64<NT>(pos, sh64);   // (also orders keys/hist writes)
+  return resolve_compact(keys, d, k, pos, hist, out);
 }
 
 template <typename T>
@@ -371,29 +399,113 @@ sel_small(const T *__restrict__ eps, int64_t d, int64_t k, double floor,
   if (threadIdx.x == 0) ctrl->sel_count[ph] = cnt;
 }
 
-// Per-system draws of a batch: workgroup s draws from the weights of system
-// s (eps[off_s .. off_s + d_s)) with its own block size, iteration counter
-// and generator stream (system id in counter word 3); a finished system
-// draws nothing.  Local indices go to tmp[koff_s ..]; counts to cnt[s].
+// Per-system draws of a batch: each system draws from its own weights
+// (eps[off_s .. off_s + d_s)) with its own block size, iteration counter and
+// generator stream (system id in counter word 3); a finished system draws
+// nothing.  Three launches: the largest weight of every system (one
+// workgroup each), the keys of all systems (many workgroups per system),
+// and the threshold search and ordered compaction (one workgroup each).
+// Local indices go to tmp[koff_s ..]; counts to cnt[s].
 template <typename T>
-__global__ void __launch_bounds__(1024)
-sel_seg(const T *__restrict__ eps, const SegInfo *__restrict__ seg, int ph,
-        double floor, uint64_t seed, uint64_t key1, uint32_t phase,
-        uint64_t *__restrict__ keys, int32_t *__restrict__ tmp,
-        int64_t *__restrict__ cnt, Ctrl *ctrl, int respect_done) {
+__global__ void __launch_bounds__(256)
+sel_seg_max(const T *__restrict__ eps, const SegInfo *__restrict__ seg, int ph,
+            double *__restrict__ segmax, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const SegInfo &g = seg[blockIdx.x];
+  if (g.done) return;
+  __shared__ double sh[256 / WAVE];
+  const int64_t off = ph == 0 ? g.col_off : g.row_off;
+  const int64_t d = ph == 0 ? g.ncol : g.nrow;
+  double mx = 0.0;
+  for (int64_t j0 = threadIdx.x; j0 < d; j0 += WG_UNROLL * 256) {
+    double e[WG_UNROLL];
+#pragma unroll
+    for (int u = 0; u < WG_UNROLL; ++u) {
+      const int64_t j = j0 + (int64_t)u * 256;
+      e[u] = j < d ? (double)eps[off + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < WG_UNROLL; ++u)
+      if (e[u] <= 1.7976931348623157e308) mx = e[u] > mx ? e[u] : mx;
+  }
+  mx = wave_max(mx);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 256 / WAVE; ++i) mx = sh[i] > mx ? sh[i] : mx;
+    segmax[blockIdx.x] = mx;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+sel_seg_keys(const T *__restrict__ eps, const SegInfo *__restrict__ seg,
+             int ph, double floor, uint64_t seed, uint64_t key1,
+             uint32_t phase, const double *__restrict__ segmax,
+             uint64_t *__restrict__ keys, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int sidx = blockIdx.y;
+  const SegInfo &g = seg[sidx];
+  if (g.done) return;
+  const int64_t off = ph == 0 ? g.col_off : g.row_off;
+  const int64_t d = ph == 0 ? g.ncol : g.nrow;
+  const int64_t gl = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gl * 4 >= d) return;
+  const double mx = segmax[sidx];
+  const double cut = floor > 0.0 ? floor * mx : 0.0;
+  double ev[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = gl * 4 + q;
+    ev[q] = j < d ? (double)eps[off + j] : 0.0;
+  }
+  const P4 r = philox4x64_10((uint64_t)gl, (uint64_t)g.it, phase,
+                             (uint32_t)sidx, seed, key1);
+  int bad = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = gl * 4 + q;
+    if (j < d) keys[off + j] = make_key(ev[q], r.v[q], cut, &bad);
+  }
+  if (bad) atomicOr(&ctrl->numeric, 1);
+}
+
+__global__ void __launch_bounds__(WG_NT)
+sel_seg_resolve(const SegInfo *__restrict__ seg, int ph,
+                const uint64_t *__restrict__ keys, int32_t *__restrict__ tmp,
+                int64_t *__restrict__ cnt, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   const SegInfo &g = seg[blockIdx.x];
   if (g.done) {
     if (threadIdx.x == 0) cnt[blockIdx.x] = 0;
     return;
   }
+  __shared__ unsigned hist[2048];
+  __shared__ int64_t sh64[WG_NT / WAVE];
   const int64_t off = ph == 0 ? g.col_off : g.row_off;
   const int64_t d = ph == 0 ? g.ncol : g.nrow;
   const int64_t k = ph == 0 ? g.kc : g.kr;
   const int64_t ko = ph == 0 ? g.kc_off : g.kr_off;
-  const int64_t c = select_wg<T>(eps + off, d, k, floor, seed, key1,
-                                 (uint64_t)g.it, phase, (uint32_t)blockIdx.x,
-                                 keys + off, tmp + ko, &ctrl->numeric);
+  const uint64_t *kk = keys + off;
+  for (int i = threadIdx.x; i < 2048; i += WG_NT) hist[i] = 0u;
+  __syncthreads();
+  int64_t pos = 0;
+  for (int64_t j0 = threadIdx.x; j0 < d; j0 += WG_UNROLL * WG_NT) {
+    uint64_t kv[WG_UNROLL];
+#pragma unroll
+    for (int u = 0; u < WG_UNROLL; ++u) {
+      const int64_t j = j0 + (int64_t)u * WG_NT;
+      kv[u] = j < d ? kk[j] : SENT;
+    }
+#pragma unroll
+    for (int u = 0; u < WG_UNROLL; ++u)
+      if (kv[u] != SENT) {
+        ++pos;
+        atomicAdd(&hist[kv[u] >> 53], 1u);
+      }
+  }
+  pos = block_sum_i64<WG_NT>(pos, sh64);
+  const int64_t c = resolve_compact(kk, d, k, pos, hist, tmp + ko);
   if (threadIdx.x == 0) cnt[blockIdx.x] = c;
 }
 
@@ -1176,25 +1288,31 @@ int64_t select_scratch_blocks(int64_t d) {
 
 template <typename T>
 void launch_select_seg(const T *eps, const SegInfo *seg, int nseg, int ph,
-                       double floor, uint64_t seed, uint64_t key1,
-                       uint32_t phase, uint64_t *keys, int32_t *tmp,
-                       int64_t *cnt, int32_t *out, Ctrl *ctrl,
-                       int respect_done, hipStream_t st) {
-  hipLaunchKernelGGL(sel_seg<T>, dim3(nseg), dim3(1024), 0, st, eps, seg, ph,
-                     floor, seed, key1, phase, keys, tmp, cnt, ctrl,
-                     respect_done);
+                       int64_t dmax, double floor, uint64_t seed,
+                       uint64_t key1, uint32_t phase, uint64_t *keys,
+                       double *segmax, int32_t *tmp, int64_t *cnt,
+                       int32_t *out, Ctrl *ctrl, int respect_done,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(sel_seg_max<T>, dim3(nseg), dim3(256), 0, st, eps, seg,
+                     ph, segmax, ctrl, respect_done);
+  const unsigned gx = (unsigned)((dmax + 4 * 256 - 1) / (4 * 256));
+  hipLaunchKernelGGL(sel_seg_keys<T>, dim3(gx > 0 ? gx : 1, nseg), dim3(256),
+                     0, st, eps, seg, ph, floor, seed, key1, phase, segmax,
+                     keys, ctrl, respect_done);
+  hipLaunchKernelGGL(sel_seg_resolve, dim3(nseg), dim3(WG_NT), 0, st, seg, ph,
+                     keys, tmp, cnt, ctrl, respect_done);
   hipLaunchKernelGGL(sel_seg_pack, dim3(nseg), dim3(256), 0, st, seg, nseg, ph,
                      tmp, cnt, out, ctrl, respect_done);
 }
 template void launch_select_seg<double>(const double *, const SegInfo *, int,
-                                        int, double, uint64_t, uint64_t,
-                                        uint32_t, uint64_t *, int32_t *,
-                                        int64_t *, int32_t *, Ctrl *, int,
-                                        hipStream_t);
+                                        int, int64_t, double, uint64_t,
+                                        uint64_t, uint32_t, uint64_t *,
+                                        double *, int32_t *, int64_t *,
+                                        int32_t *, Ctrl *, int, hipStream_t);
 template void launch_select_seg<float>(const float *, const SegInfo *, int,
-                                       int, double, uint64_t, uint64_t,
-                                       uint32_t, uint64_t *, int32_t *,
-                                       int64_t *, int32_t *, Ctrl *, int,
-                                       hipStream_t);
+                                       int, int64_t, double, uint64_t,
+                                       uint64_t, uint32_t, uint64_t *,
+                                       double *, int32_t *, int64_t *,
+                                       int32_t *, Ctrl *, int, hipStream_t);
 
 }  // namespace rg
