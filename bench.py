@@ -241,7 +241,8 @@ def main():
         handles = {}
         del a, b, xs
         torch.cuda.empty_cache()
-        extras = {"spmv": spmv_powerlaw(), "batched": batched_laplacian()}
+        extras = {"spmv": spmv_powerlaw(), "batched": batched_laplacian(),
+                  "gdbek_vs_rgdbek": gdbek_vs_rgdbek()}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -386,6 +387,51 @@ def batched_laplacian(count=16, itol=0.1, imax=16, tol=1e-8):
     out["speedup_batched_fp64_vs_one_by_one"] = round(tot * 1e3 / out["fp64_batched_ms"], 3)
     out["speedup_batched_mixed_vs_one_by_one"] = round(tot * 1e3 / out["mixed_f32_batched_ms"], 3)
     log(f"one by one fp64: {1e3 * tot:.1f} ms")
+    return out
+
+
+def gdbek_vs_rgdbek(shapes=((8000, 500), (8000, 1000), (500, 8000),
+                             (1000, 8000)), seeds=3, eta=0.5, tol=1e-6):
+    """The comparison of Section 3 (Tables 1 and 2) on the same kernels:
+    GDBEK's greedy sets vs RGDBEK's randomized draws, threshold / fraction
+    eta = 0.5, stop at ||Ax - b||^2 <= tol ||b||^2, on sparse random matrices
+    with 1% density (N(0,1) values, planted x*) -- synthetic stand-ins for
+    the paper's sprandn matrices.  Mean iterations and time over `seeds`
+    matrices per shape; the paper's mean iterations are quoted as context."""
+    import torch
+    import paper_2509_19267_amd as rg
+    import workloads
+    with open(os.path.join(ROOT, "tests", "golden", "paper_iteration_counts.json")) as f:
+        gold = json.load(f)
+    out = []
+    for m, n in shapes:
+        row = {"m": m, "n": n}
+        for method in ["greedy", "random"]:
+            its, ts = [], []
+            for seed in range(seeds):
+                p = workloads.sparse_uniform(m, n, density=0.01, seed=seed)
+                rp, ci, v = workloads.to_csr_arrays(p.a)
+                csr = (torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(),
+                       torch.as_tensor(v).cuda())
+                s = rg.Solver(csr=csr, shape=(m, n), eta=eta, select=method,
+                              stop="rse", tol=tol, max_iter=400_000, seed=seed)
+                b = torch.as_tensor(p.b).cuda()
+                s.solve(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = s.solve(b)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                its.append(info["iterations"])
+                s.close()
+            name = "gdbek" if method == "greedy" else "rgdbek"
+            row[f"{name}_iterations"] = float(np.mean(its))
+            row[f"{name}_ms"] = round(1e3 * float(np.mean(ts)), 2)
+        key = ("tall_8000_rows", str(n)) if m == 8000 else ("fat_8000_columns", str(m))
+        row["paper_rgdbek_iterations"] = gold[key[0]].get(key[1])
+        row["paper_gdbek_iterations"] = gold["gdbek_" + key[0]].get(key[1])
+        log(f"gdbek vs rgdbek {m}x{n}: {row}")
+        out.append(row)
     return out
 
 

@@ -115,7 +115,12 @@ typedef struct {
   int32_t tile_rows;     /* rows per workgroup tile of the dense residual
                             pass (rounded up to 16); 0 = sized so one grid
                             round fills the device                          */
-  int32_t reserved;      /* must be 0                                       */
+  int32_t select_mode;   /* RGDBEK_SELECT_*: 0 = Algorithm 1's randomized
+                            draws; 1 = GDBEK's greedy sets (Section 2):
+                            indices with weight >= eta * max weight, eta the
+                            threshold, k_col/k_row the capacity (0 = the
+                            dimension; a larger set keeps its lowest
+                            indices).  Single systems only.                 */
 } rgdbek_params;
 
 /* Dense block solvers: AUTO picks Cholesky for blocks up to 256 and
@@ -124,6 +129,8 @@ enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
 /* Flags: GRAPH captures the iteration loop into HIP graphs (default on via
  * rgdbek_params_default); GRAM_AAT precomputes A A^T for dense row blocks. */
 enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2 };
+/* Block rule (rgdbek_params.select_mode). */
+enum { RGDBEK_SELECT_RANDOM = 0, RGDBEK_SELECT_GREEDY = 1 };
 
 typedef struct {
   int64_t iterations;        /* RGDBEK iterations run (inner, summed)       */
@@ -237,6 +244,19 @@ rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
                             uint64_t it,
                             uint32_t phase, uint32_t sys, int32_t *out_idx,
                             int64_t *out_count, void *stream);
+
+/* GDBEK's greedy set (Section 2) on a weight vector: the indices j with
+ * eps[j] > 0 and eps[j] >= eta * max(eps) (the product and comparison in
+ * FP64), in ascending order, at most cap of them (the lowest indices when
+ * more pass); every weight zero gives the empty set.
+ *  eps      device, d FP64 weights (finite, >= 0; NUMERIC otherwise);
+ *  eta      threshold in (0, 1];  cap >= 0;
+ *  out_idx  device, cap int32 (may be NULL when cap == 0);
+ *  out_count host, receives the set size (after the cap);
+ *  stream   hipStream_t (NULL = default); synchronises it before returning. */
+rgdbek_status rgdbek_select_threshold(const double *eps, int64_t d, double eta,
+                                      int64_t cap, int32_t *out_idx,
+                                      int64_t *out_count, void *stream);
 
 /* One residual pass without a solve: ax = A x (m entries) and atz = A^T z
  * (n entries) -- the two products every iteration forms (the column residual

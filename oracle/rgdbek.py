@@ -45,7 +45,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from .select import select, block_size, FLOOR_FP64
+from .select import select, select_threshold, block_size, FLOOR_FP64
 from .blockls import column_projection, row_projection
 
 
@@ -88,12 +88,15 @@ def row_weights(b, z_next, q, rho):
 def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
            stop="none", tol=0.0, x_ref=None, sys=0, key1=0, it0=0,
            x0=None, z0=None, col_offset=None, record=False,
-           floor=FLOOR_FP64):
+           floor=FLOOR_FP64, greedy=None):
     """Run Algorithm 1.  Returns (x, z, Info).
 
     a: dense (m, n) ndarray or scipy sparse matrix; b: (m,) FP64.
     Block sizes come from k_col/k_row, or from eta through ``block_size``.
-    x0/z0/it0 resume a run (x_0 = 0 and z_0 = b by default)."""
+    x0/z0/it0 resume a run (x_0 = 0 and z_0 = b by default).
+    greedy: None for Algorithm 1's randomized draws, or a threshold in
+    (0, 1] for GDBEK's greedy sets {eps_j >= greedy * max eps} (Section 2),
+    with the same update rules and the same order of the two phases."""
     if sp.issparse(a):
         a = sp.csr_matrix(a, dtype=np.float64)
         a_csc = a.tocsc()
@@ -102,9 +105,9 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
         a_csc = a
     m, n = a.shape
     b = np.asarray(b, dtype=np.float64)
-    if k_col is None:
+    if k_col is None and greedy is None:
         k_col = block_size(eta, n)
-    if k_row is None:
+    if k_row is None and greedy is None:
         k_row = block_size(eta, m)
     rho = _sq_norms(a, 1)
     kappa = _sq_norms(a, 0)
@@ -127,7 +130,10 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
         it = it0 + k
         # column phase
         eps_z, g = column_weights(a, z, kappa, col_offset)
-        u = select(eps_z, k_col, seed, it, 0, sys, key1, floor)
+        if greedy is None:
+            u = select(eps_z, k_col, seed, it, 0, sys, key1, floor)
+        else:
+            u = select_threshold(eps_z, greedy)
         z_prev = z
         if u.size:
             z, y, nr_c = column_projection(a_csc[:, u], z)
@@ -146,7 +152,10 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
             if info.metric <= tol:
                 info.converged = True
                 break
-        j = select(eps_x, k_row, seed, it, 1, sys, key1, floor)
+        if greedy is None:
+            j = select(eps_x, k_row, seed, it, 1, sys, key1, floor)
+        else:
+            j = select_threshold(eps_x, greedy)
         x_prev = x
         if j.size:
             d, nr_r = row_projection(a[j, :], r[j])

@@ -6,7 +6,9 @@ include/rgdbek.h); this package only marshals arguments to it.
 """
 from ._binding import RgdbekError, LIB_PATH, load  # noqa: F401
 from .solver import (Solver, BatchSolver, MultiRhsSolver,  # noqa: F401
-                     block_diagonal, select, solve, RGDBEKFunction)
+                     block_diagonal, select, select_threshold, solve,
+                     RGDBEKFunction)
 
-__all__ = ["Solver", "BatchSolver", "MultiRhsSolver", "block_diagonal", "select", "solve", "RGDBEKFunction", "RgdbekError",
+__all__ = ["Solver", "BatchSolver", "MultiRhsSolver", "block_diagonal", "select",
+           "select_threshold", "solve", "RGDBEKFunction", "RgdbekError",
            "LIB_PATH", "load"]

@@ -19,6 +19,7 @@ STOP_NONE, STOP_ERR_REF, STOP_RSE, STOP_RES_EXT = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED_F32, PREC_MIXED_BF16 = 0, 1, 2
 SOLVER_AUTO, SOLVER_CHOL, SOLVER_CG = 0, 1, 2
 FLAG_GRAPH, FLAG_GRAM_AAT = 1, 2
+SELECT_RANDOM, SELECT_GREEDY = 0, 1
 
 STOP_NAMES = {"none": STOP_NONE, "err_ref": STOP_ERR_REF, "rse": STOP_RSE,
               "res_ext": STOP_RES_EXT}
@@ -41,7 +42,7 @@ class Params(ctypes.Structure):
                 ("inner_max", ctypes.c_int32), ("graph_iters", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("solver", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("weight_floor", ctypes.c_double),
-                ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("select_mode", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -73,6 +74,10 @@ SIGNATURES = {
                                      ctypes.c_uint64, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32, _vp,
                                      ctypes.POINTER(ctypes.c_int64), _vp]),
+    "rgdbek_select_threshold": (ctypes.c_int, [_vp, ctypes.c_int64,
+                                               ctypes.c_double, ctypes.c_int64,
+                                               _vp, ctypes.POINTER(ctypes.c_int64),
+                                               _vp]),
     "rgdbek_apply": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]),
     "rgdbek_create_batched": (ctypes.c_int, [ctypes.POINTER(Matrix),
                                              ctypes.c_int64,

@@ -34,8 +34,17 @@ struct SelectScratch {
   uint64_t *ckey = nullptr;   // 4096 candidate keys
   int64_t *cidx = nullptr;    // 4096 candidate indices
   int32_t *blk = nullptr;     // per-chunk counts
+  double *gmax = nullptr;     // per-chunk maxima (greedy sets)
 };
 int64_t select_scratch_blocks(int64_t d);
+int64_t select_greedy_blocks(int64_t d);
+
+// GDBEK's greedy set {j : eps_j >= eta * max eps, eps_j > 0} (Section 2),
+// ascending, at most cap indices; count to Ctrl::sel_count[ph].
+template <typename T>
+void launch_select_greedy(const T *eps, int64_t d, double eta, int64_t cap,
+                          int ph, SelectScratch &s, int32_t *out, Ctrl *ctrl,
+                          int respect_done, hipStream_t st);
 
 // eps: d weights (T promoted to FP64 before the key division); weights not
 // above floor * max(eps) count as zero.  ph selects the Ctrl slot (0 columns,

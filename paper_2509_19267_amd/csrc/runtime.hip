@@ -344,6 +344,7 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   e.sel.ckey = P.alloc<uint64_t>(4096);
   e.sel.cidx = P.alloc<int64_t>(4096);
   e.sel.blk = P.alloc<int32_t>(select_scratch_blocks(dmax) + 64);
+  e.sel.gmax = P.alloc<double>(select_greedy_blocks(dmax) + 64);
   e.red.part = P.alloc<double>(1024);
   e.red.cap = 1024;
   if (h->nseg) {
@@ -437,6 +438,8 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     launch_select_seg<T>(e.eps_z, e.seg, ns, 0, e.seg_dmax[0], e.floor, p.seed,
                          o.key1, 0, e.sel.keys, e.segmax, e.seltmp, e.selcnt,
                          e.U, c, 1, st);
+  else if (p.select_mode == RGDBEK_SELECT_GREEDY)
+    launch_select_greedy<T>(e.eps_z, e.n, p.eta, e.kc, 0, e.sel, e.U, c, 1, st);
   else
     launch_select<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0,
                      e.sel, e.U, c, 1, st);
@@ -484,6 +487,8 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     launch_select_seg<T>(e.eps_x, e.seg, ns, 1, e.seg_dmax[1], e.floor, p.seed,
                          o.key1, 1, e.sel.keys, e.segmax, e.seltmp, e.selcnt,
                          e.J, c, 1, st);
+  else if (p.select_mode == RGDBEK_SELECT_GREEDY)
+    launch_select_greedy<T>(e.eps_x, e.m, p.eta, e.kr, 1, e.sel, e.J, c, 1, st);
   else
     launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1,
                      e.sel, e.J, c, 1, st);
@@ -875,8 +880,9 @@ void validate_params(const rgdbek_params *p, int64_t m, int64_t n,
     int64_t k = (int64_t)std::floor(p->eta * (double)d + 0.5);
     return std::min<int64_t>(d, std::max<int64_t>(1, k));
   };
-  *kc = p->k_col > 0 ? p->k_col : from_eta(n);
-  *kr = p->k_row > 0 ? p->k_row : from_eta(m);
+  const bool greedy = p->select_mode == RGDBEK_SELECT_GREEDY;
+  *kc = p->k_col > 0 ? p->k_col : (greedy ? n : from_eta(n));
+  *kr = p->k_row > 0 ? p->k_row : (greedy ? m : from_eta(m));
   if (p->k_col < 0 || p->k_row < 0)
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "k_col/k_row must be >= 0"};
   if (*kc > n || *kr > m)
@@ -900,9 +906,14 @@ void validate_params(const rgdbek_params *p, int64_t m, int64_t n,
   if (p->inner_max < 0 || p->inner_max > 4096 || p->graph_iters < 0 ||
       p->graph_iters > 1024)
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "inner_max/graph_iters out of range"};
-  if (p->tile_rows < 0 || p->tile_rows > (1 << 20) || p->reserved != 0)
+  if (p->tile_rows < 0 || p->tile_rows > (1 << 20))
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "tile_rows must lie in [0, 2^20]"};
+  if (p->select_mode != RGDBEK_SELECT_RANDOM &&
+      p->select_mode != RGDBEK_SELECT_GREEDY)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "unknown select_mode"};
+  if (p->select_mode == RGDBEK_SELECT_GREEDY && !(p->eta > 0.0))
     throw ApiError{RGDBEK_ERR_INVALID_ARG,
-                   "tile_rows must lie in [0, 2^20] and reserved must be 0"};
+                   "the greedy threshold eta must lie in (0, 1]"};
 }
 
 // Compute units of the current device (sizes the dense pass grid).
@@ -1282,6 +1293,8 @@ rgdbek_status rgdbek_create_batched(const rgdbek_matrix *A, int64_t nsys,
   rgdbek_status st = guarded(nullptr, [&]() {
     int64_t kc, kr;
     validate_params(&q, h->m, h->n, &kc, &kr);
+    if (q.select_mode != RGDBEK_SELECT_RANDOM)
+      throw ApiError{RGDBEK_ERR_UNSUPPORTED, "greedy sets: single systems only"};
     h->kc = kc_tot;
     h->kr = kr_tot;
     if (!A->row_ptr || (!A->col_idx && A->nnz > 0) || !A->values || A->nnz < 0 ||
@@ -1378,6 +1391,8 @@ rgdbek_status rgdbek_create_multirhs(const rgdbek_matrix *A, int64_t nrhs,
   rgdbek_status st = guarded(nullptr, [&]() {
     int64_t k1, k2;
     validate_params(&q, A->m, A->n, &k1, &k2);
+    if (q.select_mode != RGDBEK_SELECT_RANDOM)
+      throw ApiError{RGDBEK_ERR_UNSUPPORTED, "greedy sets: single systems only"};
     if (h->user_st) {
       h->st = h->user_st;
     } else {
@@ -1610,6 +1625,39 @@ rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
     *out_count = hc.sel_count[0];
     if (hc.sync_fail)
       throw ApiError{RGDBEK_ERR_DEVICE, "a grid-barrier wait timed out"};
+    if (hc.numeric)
+      throw ApiError{RGDBEK_ERR_NUMERIC, "weights must be finite and >= 0"};
+    return RGDBEK_OK;
+  });
+  P.release();
+  return s;
+}
+
+rgdbek_status rgdbek_select_threshold(const double *eps, int64_t d, double eta,
+                                      int64_t cap, int32_t *out_idx,
+                                      int64_t *out_count, void *stream) {
+  if (!eps || !out_count || d < 0 || cap < 0 || (cap > 0 && !out_idx) ||
+      !(eta > 0.0) || eta > 1.0) {
+    set_err(nullptr, "invalid arguments to rgdbek_select_threshold");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  Pool P;
+  P.st = st;
+  rgdbek_status s = guarded(nullptr, [&]() {
+    *out_count = 0;
+    if (d == 0) return RGDBEK_OK;
+    SelectScratch sc;
+    sc.blk = P.alloc<int32_t>(select_greedy_blocks(d) + 64);
+    sc.gmax = P.alloc<double>(select_greedy_blocks(d) + 64);
+    int32_t *o = out_idx ? out_idx : P.alloc<int32_t>(1);
+    Ctrl *c = P.alloc<Ctrl>(1);
+    launch_select_greedy<double>(eps, d, eta, cap, 0, sc, o, c, 0, st);
+    Ctrl hc;
+    HIPCHK(hipMemcpyAsync(&hc, c, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    *out_count = hc.sel_count[0];
     if (hc.numeric)
       throw ApiError{RGDBEK_ERR_NUMERIC, "weights must be finite and >= 0"};
     return RGDBEK_OK;

@@ -1225,6 +1225,147 @@ int64_t select_persist_max(int ncu) {
 // smallest d that takes the persistent form (below: one workgroup)
 constexpr int64_t SP_MIN_D = 4096;
 
+// ------------------------------------------------ greedy (GDBEK) sets
+// GDBEK's threshold sets (Section 2): {j : eps_j >= eta * max eps, eps_j > 0}
+// in ascending order, at most `cap` of them (the lowest indices when more
+// pass).  Three launches, no atomics: per-chunk maxima; per-chunk counts
+// (every block re-reduces the maxima in the same order); ordered writes from
+// per-chunk offsets.  The comparison is one FP64 product and compare, as in
+// the oracle, so the set is bit-exact.
+constexpr int GR_NT = 256;
+constexpr int GR_PT = 16;                       // weights per thread
+constexpr int64_t GR_CH = (int64_t)GR_NT * GR_PT;
+
+template <typename T>
+__global__ void __launch_bounds__(GR_NT)
+gr_max(const T *__restrict__ eps, int64_t d, double *__restrict__ pmax,
+       Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[GR_NT / WAVE];
+  const int64_t base = (int64_t)blockIdx.x * GR_CH;
+  double mx = 0.0;
+#pragma unroll
+  for (int q = 0; q < GR_PT; ++q) {
+    const int64_t j = base + (int64_t)q * GR_NT + threadIdx.x;
+    if (j < d) {
+      const double e = (double)eps[j];
+      if (e <= 1.7976931348623157e308) mx = e > mx ? e : mx;
+    }
+  }
+  mx = wave_max(mx);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < GR_NT / WAVE; ++i) mx = sh[i] > mx ? sh[i] : mx;
+    pmax[blockIdx.x] = mx;
+  }
+}
+
+__device__ __forceinline__ double gr_threshold(const double *pmax, int nb,
+                                               double eta, double *sh) {
+  double gm = 0.0;
+  for (int b = threadIdx.x; b < nb; b += GR_NT) gm = pmax[b] > gm ? pmax[b] : gm;
+  gm = wave_max(gm);
+  __syncthreads();
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = gm;
+  __syncthreads();
+  gm = 0.0;
+  for (int i = 0; i < GR_NT / WAVE; ++i) gm = sh[i] > gm ? sh[i] : gm;
+  return gm > 0.0 ? eta * gm : -1.0;    // -1: every weight is zero
+}
+
+__device__ __forceinline__ bool gr_take(double e, double thr) {
+  return thr >= 0.0 && e > 0.0 && e >= thr;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(GR_NT)
+gr_count(const T *__restrict__ eps, int64_t d, double eta,
+         const double *__restrict__ pmax, int32_t *__restrict__ blk,
+         Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[GR_NT / WAVE];
+  __shared__ int64_t sh64[GR_NT / WAVE];
+  const double thr = gr_threshold(pmax, (int)gridDim.x, eta, sh);
+  const int64_t base = (int64_t)blockIdx.x * GR_CH;
+  int64_t c = 0;
+  int bad = 0;
+#pragma unroll
+  for (int q = 0; q < GR_PT; ++q) {
+    const int64_t j = base + (int64_t)q * GR_NT + threadIdx.x;
+    if (j < d) {
+      const double e = (double)eps[j];
+      if (!(e >= 0.0) || e > 1.7976931348623157e308) bad = 1;
+      c += gr_take(e, thr);
+    }
+  }
+  if (bad) atomicOr(&ctrl->numeric, 1);
+  c = block_sum_i64<GR_NT>(c, sh64);
+  if (threadIdx.x == 0) blk[blockIdx.x] = (int32_t)c;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(GR_NT)
+gr_write(const T *__restrict__ eps, int64_t d, double eta, int64_t cap,
+         const double *__restrict__ pmax, const int32_t *__restrict__ blk,
+         int32_t *__restrict__ out, Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[GR_NT / WAVE];
+  __shared__ int64_t sh64[GR_NT / WAVE];
+  __shared__ int wtot[GR_NT / WAVE];
+  const double thr = gr_threshold(pmax, (int)gridDim.x, eta, sh);
+  int64_t before = 0, total = 0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += GR_NT) {
+    total += blk[b];
+    if (b < (int)blockIdx.x) before += blk[b];
+  }
+  before = block_sum_i64<GR_NT>(before, sh64);
+  total = block_sum_i64<GR_NT>(total, sh64);
+  const int64_t base = (int64_t)blockIdx.x * GR_CH;
+  int64_t off = before;
+  for (int q = 0; q < GR_PT; ++q) {
+    const int64_t j = base + (int64_t)q * GR_NT + threadIdx.x;
+    const bool f = j < d && gr_take((double)eps[j], thr);
+    const uint64_t mask = __ballot(f);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) wtot[wv] = __popcll(mask);
+    __syncthreads();
+    int wb = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < GR_NT / WAVE; ++i) {
+      if (i < wv) wb += wtot[i];
+      tot += wtot[i];
+    }
+    const int64_t r = off + wb + __popcll(mask & ((1ull << lane) - 1ull));
+    if (f && r < cap) out[r] = (int32_t)j;
+    off += tot;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    ctrl->sel_count[ph] = total < cap ? total : cap;
+}
+
+template <typename T>
+void launch_select_greedy(const T *eps, int64_t d, double eta, int64_t cap,
+                          int ph, SelectScratch &s, int32_t *out, Ctrl *ctrl,
+                          int respect_done, hipStream_t st) {
+  const int nb = (int)((d + GR_CH - 1) / GR_CH);
+  const unsigned g = (unsigned)(nb > 0 ? nb : 1);
+  hipLaunchKernelGGL(gr_max<T>, dim3(g), dim3(GR_NT), 0, st, eps, d, s.gmax,
+                     ctrl, respect_done);
+  hipLaunchKernelGGL(gr_count<T>, dim3(g), dim3(GR_NT), 0, st, eps, d, eta,
+                     s.gmax, s.blk, ctrl, respect_done);
+  hipLaunchKernelGGL(gr_write<T>, dim3(g), dim3(GR_NT), 0, st, eps, d, eta,
+                     cap, s.gmax, s.blk, out, ctrl, ph, respect_done);
+}
+template void launch_select_greedy<double>(const double *, int64_t, double,
+                                           int64_t, int, SelectScratch &,
+                                           int32_t *, Ctrl *, int, hipStream_t);
+template void launch_select_greedy<float>(const float *, int64_t, double,
+                                          int64_t, int, SelectScratch &,
+                                          int32_t *, Ctrl *, int, hipStream_t);
+int64_t select_greedy_blocks(int64_t d) { return (d + GR_CH - 1) / GR_CH; }
+
 // ------------------------------------------------ launcher
 template <typename T>
 void launch_select(const T *eps, int64_t d, int64_t k, double floor,

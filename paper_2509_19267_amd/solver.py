@@ -39,7 +39,7 @@ class Solver:
                  k_row=0, tol=1e-8, stop="err_ref", max_iter=10000, seed=0,
                  precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
                  solver=B.SOLVER_AUTO, graph=True, gram_aat=False,
-                 weight_floor=0.0, tile_rows=0, stream=None):
+                 weight_floor=0.0, tile_rows=0, select="random", stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -78,6 +78,7 @@ class Solver:
         p.solver = int(solver)
         p.weight_floor = float(weight_floor)
         p.tile_rows = int(tile_rows)
+        p.select_mode = {"random": B.SELECT_RANDOM, "greedy": B.SELECT_GREEDY}[select]
         p.flags = (B.FLAG_GRAPH if graph else 0) | (B.FLAG_GRAM_AAT if gram_aat else 0)
         self.m, self.n = int(m), int(n)
         self.params = p
@@ -179,7 +180,7 @@ class BatchSolver(Solver):
     def __init__(self, csr, row_off, col_off, *, eta=0.1, k_col=0, k_row=0,
                  tol=1e-8, stop="err_ref", max_iter=10000, seed=0,
                  precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
-                 graph=True, weight_floor=0.0, stream=None):
+                 graph=True, weight_floor=0.0, select="random", stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -206,6 +207,7 @@ class BatchSolver(Solver):
         p.inner_max, p.inner_tol, p.graph_iters = inner_max, inner_tol, graph_iters
         p.flags = B.FLAG_GRAPH if graph else 0
         p.weight_floor = float(weight_floor)
+        p.select_mode = {"random": B.SELECT_RANDOM, "greedy": B.SELECT_GREEDY}[select]
         self.m, self.n, self.params, self.stream = m, n, p, stream
         st = lib.rgdbek_create_batched(ctypes.byref(mat), self.nsys, ro, co,
                                        ctypes.byref(p), _stream(stream),
@@ -299,6 +301,22 @@ def select(eps, k, seed=0, it=0, phase=0, sys=0, key1=0, floor=1e-20,
                            int(key1), int(it),
                            int(phase), int(sys), _ptr(out), ctypes.byref(cnt),
                            _stream(stream))
+    B.check(st, None)
+    return out[:cnt.value]
+
+
+def select_threshold(eps, eta, cap=None, stream=None):
+    """GDBEK's greedy set on given weights (device FP64 tensor): ascending
+    int32 indices j with eps_j > 0 and eps_j >= eta * max(eps), at most cap
+    of them (default: all)."""
+    lib = B.load()
+    _need_cuda(eps, "eps", torch.float64)
+    d = eps.numel()
+    cap = d if cap is None else int(cap)
+    out = torch.empty(max(1, cap), dtype=torch.int32, device=eps.device)
+    cnt = ctypes.c_int64(0)
+    st = lib.rgdbek_select_threshold(_ptr(eps), d, float(eta), cap, _ptr(out),
+                                     ctypes.byref(cnt), _stream(stream))
     B.check(st, None)
     return out[:cnt.value]
 

@@ -576,3 +576,75 @@ def test_multirhs_gradient_layer(rg):
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - v.grad[e].item()) <= 1e-6 * max(1.0, abs(fd))
     s.close()
+
+
+# ------------------------------------------------------------ GDBEK sets
+def threshold_cases():
+    rng = np.random.default_rng(40)
+    yield "random", rng.random(1000) ** 3, 0.5, None
+    e = rng.random(9000)
+    e[rng.random(9000) < 0.7] = 0.0
+    e[::17] = 0.25 * e.max()            # ties exactly at the threshold
+    yield "ties_at_threshold", e, 0.25, None
+    yield "all_zero", np.zeros(300), 0.5, None
+    yield "eta_one", rng.random(5000), 1.0, None
+    big = rng.random(300_000) ** 8
+    yield "multi_block", big, 0.01, None
+    yield "capped", rng.random(20_000), 0.1, 1000
+
+
+@pytest.mark.parametrize("case", list(threshold_cases()), ids=lambda c: c[0])
+def test_select_threshold_bit_exact(rg, case):
+    from oracle.select import select_threshold as othr
+    name, eps, eta, cap = case
+    got = rg.select_threshold(dev(eps), eta, cap).cpu().numpy().astype(np.int64)
+    want = othr(eps, eta)
+    if cap is not None:
+        want = want[:cap]
+    assert np.array_equal(got, want), name
+
+
+@pytest.mark.parametrize("kind", ["dense_c1", "dense_ls", "sparse"])
+def test_gdbek_trajectory(rg, kind):
+    # GDBEK's greedy sets (Section 2) on the same kernels: iterates equal
+    # the oracle's with the same threshold
+    if kind == "dense_c1":
+        p = workloads.dense_consistent(500, 250, seed=0)
+        s = rg.Solver(dev(p.a), eta=0.5, select="greedy", stop="none",
+                      max_iter=4, inner_max=500)
+    elif kind == "dense_ls":
+        p = workloads.dense_least_squares(1200, 300, seed=41)
+        s = rg.Solver(dev(p.a), eta=0.3, select="greedy", stop="none",
+                      max_iter=4, inner_max=500)
+    else:
+        p = workloads.sparse_uniform(3000, 1500, density=0.01, seed=42)
+        s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, eta=0.5,
+                      select="greedy", stop="none", max_iter=4, inner_max=500)
+    x, _ = s.solve(dev(p.b))
+    z = s.get_z().cpu().numpy()
+    s.close()
+    xo, zo, _ = rgdbek(p.a, p.b, greedy=0.5 if kind != "dense_ls" else 0.3,
+                       max_iter=4)
+    print(f"gdbek {kind}: rel_x {rel(x.cpu().numpy(), xo):.2e} rel_z {rel(z, zo):.2e}",
+          flush=True)
+    assert rel(x.cpu().numpy(), xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
+
+
+def test_gdbek_solution_and_batch_rejected(rg):
+    p = workloads.dense_consistent(500, 250, seed=0)
+    s = rg.Solver(dev(p.a), eta=0.5, select="greedy", stop="err_ref",
+                  tol=1e-10, max_iter=2000, inner_max=500)
+    x, info = s.solve(dev(p.b), x_ref=dev(p.x_star))
+    s.close()
+    xo, _, io = rgdbek(p.a, p.b, greedy=0.5, max_iter=2000, stop="err_ref",
+                       tol=1e-10, x_ref=p.x_star)
+    print("gdbek solve", info, io.iterations, flush=True)
+    assert info["converged"] == 1
+    assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
+    assert abs(info["iterations"] - io.iterations) <= 1
+    ps = workloads.laplacian_batch(count=2, n_min=50, n_max=80, seed=24)
+    csr, ro, co = batch_tensors(ps)
+    with pytest.raises(rg.RgdbekError) as ei:
+        rg.BatchSolver(csr, ro, co, eta=0.5, select="greedy")
+    assert ei.value.status == 6
