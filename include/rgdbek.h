@@ -120,7 +120,10 @@ typedef struct {
                             indices with weight >= eta * max weight, eta the
                             threshold, k_col/k_row the capacity (0 = the
                             dimension; a larger set keeps its lowest
-                            indices).  Single systems only.                 */
+                            indices); 2 = blocks of size k_col/k_row from
+                            the law of Lemma 2.1 (see
+                            rgdbek_select_block_law).  Modes 1 and 2:
+                            single systems only.                            */
 } rgdbek_params;
 
 /* Dense block solvers: AUTO picks Cholesky for blocks up to 256 and
@@ -130,7 +133,8 @@ enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
  * rgdbek_params_default); GRAM_AAT precomputes A A^T for dense row blocks. */
 enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2 };
 /* Block rule (rgdbek_params.select_mode). */
-enum { RGDBEK_SELECT_RANDOM = 0, RGDBEK_SELECT_GREEDY = 1 };
+enum { RGDBEK_SELECT_RANDOM = 0, RGDBEK_SELECT_GREEDY = 1,
+       RGDBEK_SELECT_BLOCK_LAW = 2 };
 
 typedef struct {
   int64_t iterations;        /* RGDBEK iterations run (inner, summed)       */
@@ -244,6 +248,20 @@ rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
                             uint64_t it,
                             uint32_t phase, uint32_t sys, int32_t *out_idx,
                             int64_t *out_count, void *stream);
+
+/* A block of size s from the law of Lemma 2.1 (Section 2): P(B) proportional
+ * to the sum of eps over B among all s-subsets.  Drawn as the one-index draw
+ * of rgdbek_select (k = 1, same arguments) followed by the s-1 smallest
+ * exponential keys -ln(u'_j) over the other indices, u'_j from the Philox
+ * stream of phase + 2; ascending indices; every weight zero (after the
+ * floor) gives the empty block; s >= d gives every index.  Arguments as for
+ * rgdbek_select (out_idx holds min(s, d) int32). */
+rgdbek_status rgdbek_select_block_law(const double *eps, int64_t d, int64_t s,
+                                      double floor, uint64_t seed,
+                                      uint64_t key1, uint64_t it,
+                                      uint32_t phase, uint32_t sys,
+                                      int32_t *out_idx, int64_t *out_count,
+                                      void *stream);
 
 /* GDBEK's greedy set (Section 2) on a weight vector: the indices j with
  * eps[j] > 0 and eps[j] >= eta * max(eps) (the product and comparison in

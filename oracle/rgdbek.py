@@ -45,7 +45,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from .select import select, select_threshold, block_size, FLOOR_FP64
+from .select import (select, select_threshold, select_block_law, block_size,
+                     FLOOR_FP64)
 from .blockls import column_projection, row_projection
 
 
@@ -88,7 +89,7 @@ def row_weights(b, z_next, q, rho):
 def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
            stop="none", tol=0.0, x_ref=None, sys=0, key1=0, it0=0,
            x0=None, z0=None, col_offset=None, record=False,
-           floor=FLOOR_FP64, greedy=None):
+           floor=FLOOR_FP64, greedy=None, block_law=False):
     """Run Algorithm 1.  Returns (x, z, Info).
 
     a: dense (m, n) ndarray or scipy sparse matrix; b: (m,) FP64.
@@ -96,7 +97,9 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
     x0/z0/it0 resume a run (x_0 = 0 and z_0 = b by default).
     greedy: None for Algorithm 1's randomized draws, or a threshold in
     (0, 1] for GDBEK's greedy sets {eps_j >= greedy * max eps} (Section 2),
-    with the same update rules and the same order of the two phases."""
+    with the same update rules and the same order of the two phases.
+    block_law: draw the blocks from the law of Lemma 2.1 instead
+    (``select_block_law``, block sizes k_col / k_row)."""
     if sp.issparse(a):
         a = sp.csr_matrix(a, dtype=np.float64)
         a_csc = a.tocsc()
@@ -130,10 +133,12 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
         it = it0 + k
         # column phase
         eps_z, g = column_weights(a, z, kappa, col_offset)
-        if greedy is None:
-            u = select(eps_z, k_col, seed, it, 0, sys, key1, floor)
-        else:
+        if greedy is not None:
             u = select_threshold(eps_z, greedy)
+        elif block_law:
+            u = select_block_law(eps_z, k_col, seed, it, 0, sys, key1, floor)
+        else:
+            u = select(eps_z, k_col, seed, it, 0, sys, key1, floor)
         z_prev = z
         if u.size:
             z, y, nr_c = column_projection(a_csc[:, u], z)
@@ -152,10 +157,12 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
             if info.metric <= tol:
                 info.converged = True
                 break
-        if greedy is None:
-            j = select(eps_x, k_row, seed, it, 1, sys, key1, floor)
-        else:
+        if greedy is not None:
             j = select_threshold(eps_x, greedy)
+        elif block_law:
+            j = select_block_law(eps_x, k_row, seed, it, 1, sys, key1, floor)
+        else:
+            j = select(eps_x, k_row, seed, it, 1, sys, key1, floor)
         x_prev = x
         if j.size:
             d, nr_r = row_projection(a[j, :], r[j])

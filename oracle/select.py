@@ -92,3 +92,31 @@ def select_threshold(eps, eta):
     if mx <= 0:
         return np.zeros(0, dtype=np.int64)
     return np.flatnonzero(eps >= eta * mx).astype(np.int64)
+
+
+def select_block_law(eps, s, seed, it, phase, sys=0, key1=0, floor=FLOOR_FP64):
+    """A block of size s from the law of Lemma 2.1 (Section 2):
+    P(B) proportional to sum_{j in B} w_j^2 over all s-subsets, with the
+    weights w_j^2 = eps_j.  Since every index lies in C(d-1, s-1) blocks,
+    this law is: one index j* drawn with probability eps_j / sum eps, then
+    a uniform (s-1)-subset of the other d-1 indices.
+
+    j* is the one-index draw of ``select`` (k = 1, same generator
+    coordinates and weight floor); the subset takes the s-1 smallest keys
+    -ln(u'_j) over j != j* (ties by index), u'_j from the Philox stream of
+    phase + 2.  Every weight zero (after the floor): the empty block, as
+    for the other rules.  Ascending indices."""
+    eps = np.asarray(eps, dtype=np.float64)
+    d = eps.size
+    first = select(eps, 1, seed, it, phase, sys, key1, floor)
+    if first.size == 0 or s <= 0:
+        return np.zeros(0, dtype=np.int64)
+    j0 = int(first[0])
+    if s >= d:
+        return np.arange(d, dtype=np.int64)
+    idx = np.delete(np.arange(d, dtype=np.int64), j0)
+    u = words_to_unit(index_words(idx, seed, it, phase + 2, sys, key1))
+    keys = -ln_own(u)
+    order = np.lexsort((idx, keys))
+    chosen = idx[order[:s - 1]]
+    return np.sort(np.concatenate([chosen, [j0]])).astype(np.int64)

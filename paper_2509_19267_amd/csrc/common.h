@@ -32,6 +32,7 @@ struct Ctrl {
   int64_t sel_tidx[2];    // threshold index (ties broken by index)
   int64_t sel_cand[2];    // candidates gathered for the final sort
   uint64_t sel_maxbits[2]; // bits of the largest weight (non-negative)
+  int64_t bl_first[2];    // block law: the weighted index (-1: none)
   // inner solver state (one per phase)
   double cg_rz[2], cg_rz0[2], cg_alpha[2], cg_beta[2];
   int32_t cg_done[2], cg_steps[2];

@@ -39,6 +39,15 @@ struct SelectScratch {
 int64_t select_scratch_blocks(int64_t d);
 int64_t select_greedy_blocks(int64_t d);
 
+// Block from the law of Lemma 2.1 (Section 2), size s (see select.hip); w:
+// d doubles of scratch, tmp: s ints of scratch.
+template <typename T>
+void launch_select_block_law(const T *eps, int64_t d, int64_t s, double floor,
+                             uint64_t seed, uint64_t key1, uint32_t phase,
+                             uint32_t sys, int ph, SelectScratch &sc,
+                             double *w, int32_t *tmp, int32_t *out,
+                             Ctrl *ctrl, int respect_done, hipStream_t st);
+
 // GDBEK's greedy set {j : eps_j >= eta * max eps, eps_j > 0} (Section 2),
 // ascending, at most cap indices; count to Ctrl::sel_count[ph].
 template <typename T>

@@ -107,6 +107,8 @@ struct Engine {
   double floor = 0.0;         // relative weight floor of the block draws
   int32_t *seltmp = nullptr;  // per-system draws before packing (batch)
   double *segmax = nullptr;   // per-system largest weight (batch)
+  double *blw = nullptr;      // block law: unit weights of the subset draw
+  int32_t *bltmp = nullptr;   // block law: the subset before the merge
   int64_t seg_dmax[2] = {0, 0};  // largest system dimension per phase
   int64_t *selcnt = nullptr;  // per-system draw counts (batch)
   int nseg = 0;               // systems (0: a single system)
@@ -345,6 +347,10 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   e.sel.cidx = P.alloc<int64_t>(4096);
   e.sel.blk = P.alloc<int32_t>(select_scratch_blocks(dmax) + 64);
   e.sel.gmax = P.alloc<double>(select_greedy_blocks(dmax) + 64);
+  if (h->p.select_mode == RGDBEK_SELECT_BLOCK_LAW) {
+    e.blw = P.alloc<double>(dmax + 64);
+    e.bltmp = P.alloc<int32_t>(std::max(e.kc, e.kr) + 64);
+  }
   e.red.part = P.alloc<double>(1024);
   e.red.cap = 1024;
   if (h->nseg) {
@@ -440,6 +446,9 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
                          e.U, c, 1, st);
   else if (p.select_mode == RGDBEK_SELECT_GREEDY)
     launch_select_greedy<T>(e.eps_z, e.n, p.eta, e.kc, 0, e.sel, e.U, c, 1, st);
+  else if (p.select_mode == RGDBEK_SELECT_BLOCK_LAW)
+    launch_select_block_law<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0,
+                               0, 0, e.sel, e.blw, e.bltmp, e.U, c, 1, st);
   else
     launch_select<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0,
                      e.sel, e.U, c, 1, st);
@@ -489,6 +498,9 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
                          e.J, c, 1, st);
   else if (p.select_mode == RGDBEK_SELECT_GREEDY)
     launch_select_greedy<T>(e.eps_x, e.m, p.eta, e.kr, 1, e.sel, e.J, c, 1, st);
+  else if (p.select_mode == RGDBEK_SELECT_BLOCK_LAW)
+    launch_select_block_law<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1,
+                               0, 1, e.sel, e.blw, e.bltmp, e.J, c, 1, st);
   else
     launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1,
                      e.sel, e.J, c, 1, st);
@@ -909,7 +921,8 @@ void validate_params(const rgdbek_params *p, int64_t m, int64_t n,
   if (p->tile_rows < 0 || p->tile_rows > (1 << 20))
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "tile_rows must lie in [0, 2^20]"};
   if (p->select_mode != RGDBEK_SELECT_RANDOM &&
-      p->select_mode != RGDBEK_SELECT_GREEDY)
+      p->select_mode != RGDBEK_SELECT_GREEDY &&
+      p->select_mode != RGDBEK_SELECT_BLOCK_LAW)
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "unknown select_mode"};
   if (p->select_mode == RGDBEK_SELECT_GREEDY && !(p->eta > 0.0))
     throw ApiError{RGDBEK_ERR_INVALID_ARG,
@@ -1294,7 +1307,8 @@ rgdbek_status rgdbek_create_batched(const rgdbek_matrix *A, int64_t nsys,
     int64_t kc, kr;
     validate_params(&q, h->m, h->n, &kc, &kr);
     if (q.select_mode != RGDBEK_SELECT_RANDOM)
-      throw ApiError{RGDBEK_ERR_UNSUPPORTED, "greedy sets: single systems only"};
+      throw ApiError{RGDBEK_ERR_UNSUPPORTED,
+                     "greedy and block-law rules: single systems only"};
     h->kc = kc_tot;
     h->kr = kr_tot;
     if (!A->row_ptr || (!A->col_idx && A->nnz > 0) || !A->values || A->nnz < 0 ||
@@ -1392,7 +1406,8 @@ rgdbek_status rgdbek_create_multirhs(const rgdbek_matrix *A, int64_t nrhs,
     int64_t k1, k2;
     validate_params(&q, A->m, A->n, &k1, &k2);
     if (q.select_mode != RGDBEK_SELECT_RANDOM)
-      throw ApiError{RGDBEK_ERR_UNSUPPORTED, "greedy sets: single systems only"};
+      throw ApiError{RGDBEK_ERR_UNSUPPORTED,
+                     "greedy and block-law rules: single systems only"};
     if (h->user_st) {
       h->st = h->user_st;
     } else {
@@ -1631,6 +1646,50 @@ rgdbek_status rgdbek_select(const double *eps, int64_t d, int64_t k,
   });
   P.release();
   return s;
+}
+
+rgdbek_status rgdbek_select_block_law(const double *eps, int64_t d, int64_t s,
+                                      double floor, uint64_t seed,
+                                      uint64_t key1, uint64_t it,
+                                      uint32_t phase, uint32_t sys,
+                                      int32_t *out_idx, int64_t *out_count,
+                                      void *stream) {
+  if (!eps || !out_idx || !out_count || d <= 0 || s <= 0 || d > INT32_MAX) {
+    set_err(nullptr, "invalid arguments to rgdbek_select_block_law");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (s > d) s = d;
+  hipStream_t st = (hipStream_t)stream;
+  Pool P;
+  P.st = st;
+  rgdbek_status r = guarded(nullptr, [&]() {
+    SelectScratch sc;
+    sc.pers = P.alloc<SelPersist>(1);
+    sc.ncu = device_cus();
+    sc.keys = P.alloc<uint64_t>(d + 64, false);
+    sc.hist = P.alloc<unsigned>(2048);
+    sc.ckey = P.alloc<uint64_t>(4096);
+    sc.cidx = P.alloc<int64_t>(4096);
+    sc.blk = P.alloc<int32_t>(select_scratch_blocks(d) + 64);
+    double *w = P.alloc<double>(d + 64);
+    int32_t *tmp = P.alloc<int32_t>(s + 64);
+    Ctrl *c = P.alloc<Ctrl>(1);
+    launch_fill_ctrl_it(c, (int64_t)it, st);
+    launch_select_block_law<double>(eps, d, s, floor, seed, key1, phase, sys, 0,
+                                    sc, w, tmp, out_idx, c, 0, st);
+    Ctrl hc;
+    HIPCHK(hipMemcpyAsync(&hc, c, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    *out_count = hc.sel_count[0];
+    if (hc.sync_fail)
+      throw ApiError{RGDBEK_ERR_DEVICE, "a grid-barrier wait timed out"};
+    if (hc.numeric)
+      throw ApiError{RGDBEK_ERR_NUMERIC, "weights must be finite and >= 0"};
+    return RGDBEK_OK;
+  });
+  P.release();
+  return r;
 }
 
 rgdbek_status rgdbek_select_threshold(const double *eps, int64_t d, double eta,

@@ -1225,6 +1225,80 @@ int64_t select_persist_max(int ncu) {
 // smallest d that takes the persistent form (below: one workgroup)
 constexpr int64_t SP_MIN_D = 4096;
 
+// ------------------------------------------------ Lemma 2.1 block law
+// P(B) proportional to sum_{j in B} eps_j over the s-subsets: the one-index
+// draw j* of launch_select (k = 1, same coordinates), then a uniform
+// (s-1)-subset of the other indices -- launch_select with k = s-1 on unit
+// weights (zero at j*), generator phase + 2 -- merged into one ascending
+// list.  Every weight zero: the empty block.
+__global__ void __launch_bounds__(256)
+bl_weights(int64_t d, const int32_t *__restrict__ first,
+           double *__restrict__ w, Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t js = ctrl->sel_count[ph] > 0 ? (int64_t)first[0] : -1;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < d;
+       j += (int64_t)gridDim.x * 256)
+    w[j] = (js < 0 || j == js) ? 0.0 : 1.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->bl_first[ph] = js;
+}
+
+__global__ void __launch_bounds__(1024)
+bl_merge(const int32_t *__restrict__ tmp, int32_t *__restrict__ out,
+         int with_subset, Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t js = ctrl->bl_first[ph];
+  const int64_t c2 = with_subset ? ctrl->sel_count[ph] : 0;
+  __syncthreads();
+  if (js < 0) {
+    if (threadIdx.x == 0) ctrl->sel_count[ph] = 0;
+    return;
+  }
+  int64_t below = 0;
+  for (int64_t a = threadIdx.x; a < c2; a += 1024) {
+    const int32_t v = tmp[a];
+    out[a + (v > js ? 1 : 0)] = v;
+    below += v < js;
+  }
+  __shared__ int64_t sh64[1024 / WAVE];
+  below = block_sum_i64<1024>(below, sh64);
+  if (threadIdx.x == 0) {
+    out[below] = (int32_t)js;
+    ctrl->sel_count[ph] = c2 + 1;
+  }
+}
+
+template <typename T>
+void launch_select_block_law(const T *eps, int64_t d, int64_t s, double floor,
+                             uint64_t seed, uint64_t key1, uint32_t phase,
+                             uint32_t sys, int ph, SelectScratch &sc,
+                             double *w, int32_t *tmp, int32_t *out,
+                             Ctrl *ctrl, int respect_done, hipStream_t st) {
+  launch_select<T>(eps, d, 1, floor, seed, key1, phase, sys, ph, sc, out, ctrl,
+                   respect_done, st);
+  unsigned g = (unsigned)((d + 255) / 256);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(bl_weights, dim3(g > 0 ? g : 1), dim3(256), 0, st, d, out,
+                     w, ctrl, ph, respect_done);
+  const int with_subset = s > 1 ? 1 : 0;
+  if (with_subset)
+    launch_select<double>(w, d, s - 1, 0.0, seed, key1, phase + 2, sys, ph, sc,
+                          tmp, ctrl, respect_done, st);
+  hipLaunchKernelGGL(bl_merge, dim3(1), dim3(1024), 0, st, tmp, out,
+                     with_subset, ctrl, ph, respect_done);
+}
+template void launch_select_block_law<double>(const double *, int64_t, int64_t,
+                                              double, uint64_t, uint64_t,
+                                              uint32_t, uint32_t, int,
+                                              SelectScratch &, double *,
+                                              int32_t *, int32_t *, Ctrl *,
+                                              int, hipStream_t);
+template void launch_select_block_law<float>(const float *, int64_t, int64_t,
+                                             double, uint64_t, uint64_t,
+                                             uint32_t, uint32_t, int,
+                                             SelectScratch &, double *,
+                                             int32_t *, int32_t *, Ctrl *,
+                                             int, hipStream_t);
+
 // ------------------------------------------------ greedy (GDBEK) sets
 // GDBEK's threshold sets (Section 2): {j : eps_j >= eta * max eps, eps_j > 0}
 // in ascending order, at most `cap` of them (the lowest indices when more

@@ -648,3 +648,43 @@ def test_gdbek_solution_and_batch_rejected(rg):
     with pytest.raises(rg.RgdbekError) as ei:
         rg.BatchSolver(csr, ro, co, eta=0.5, select="greedy")
     assert ei.value.status == 6
+
+
+# ------------------------------------------------------------ Lemma 2.1 law
+def block_law_cases():
+    rng = np.random.default_rng(50)
+    yield "random", rng.random(1000) ** 3, 100
+    yield "s1", rng.random(777), 1
+    yield "all_zero", np.zeros(500), 10
+    yield "s_ge_d", rng.random(50) + 0.1, 80
+    one = np.zeros(3000)
+    one[1234] = 2.0
+    yield "one_positive", one, 40
+    yield "persistent", rng.random(70_000) ** 2, 5000
+
+
+@pytest.mark.parametrize("case", list(block_law_cases()), ids=lambda c: c[0])
+def test_select_block_law_bit_exact(rg, case):
+    from oracle.select import select_block_law as obl
+    name, eps, s = case
+    for (seed, it, phase, sys, key1) in [(0, 0, 0, 0, 0), (99, 5, 1, 2, 1)]:
+        got = rg.select_block_law(dev(eps), s, seed=seed, it=it, phase=phase,
+                                  sys=sys, key1=key1).cpu().numpy()
+        want = obl(eps, s, seed, it, phase, sys, key1)
+        assert np.array_equal(got.astype(np.int64), want), name
+
+
+def test_block_law_trajectory(rg):
+    # RGDBEK iterations with the blocks drawn from the law of Lemma 2.1
+    p = workloads.dense_least_squares(2000, 500, seed=51)
+    s = rg.Solver(dev(p.a), k_col=100, k_row=200, select="block_law",
+                  stop="none", max_iter=4, inner_max=300)
+    x, _ = s.solve(dev(p.b))
+    z = s.get_z().cpu().numpy()
+    s.close()
+    xo, zo, _ = rgdbek(p.a, p.b, k_col=100, k_row=200, max_iter=4,
+                       block_law=True)
+    print(f"block law: rel_x {rel(x.cpu().numpy(), xo):.2e} rel_z {rel(z, zo):.2e}",
+          flush=True)
+    assert rel(x.cpu().numpy(), xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
