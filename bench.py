@@ -242,7 +242,7 @@ def main():
         del a, b, xs
         torch.cuda.empty_cache()
         extras = {"spmv": spmv_powerlaw(), "batched": batched_laplacian(),
-                  "gdbek_vs_rgdbek": gdbek_vs_rgdbek()}
+                  "gdbek_vs_rgdbek": gdbek_vs_rgdbek(), "fem": fem_table8()}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -432,6 +432,48 @@ def gdbek_vs_rgdbek(shapes=((8000, 500), (8000, 1000), (500, 8000),
         row["paper_gdbek_iterations"] = gold["gdbek_" + key[0]].get(key[1])
         log(f"gdbek vs rgdbek {m}x{n}: {row}")
         out.append(row)
+    return out
+
+
+def fem_table8(max_iter=10000, eta=0.5, tol=1e-6):
+    """Section 6's finite-element systems at the paper's settings (eta = 0.5,
+    stop at ||Ax - b||^2 <= tol ||b||^2 or after max_iter iterations):
+    Poisson on 25 x 25 nodes, Helmholtz k = 25 on 50 x 50 nodes, P1
+    triangles.  Reports iterations, time, the RSE reached and the relative
+    nodal L2 error against the exact solution, beside Table 8's figures."""
+    import torch
+    import paper_2509_19267_amd as rg
+    import workloads
+    with open(os.path.join(ROOT, "tests", "golden", "paper_fem_table8.json")) as f:
+        gold = json.load(f)
+    out = {}
+    for name, (npts, k, mode) in (("poisson", (25, 0.0, 1)),
+                                  ("helmholtz", (50, 25.0, 4))):
+        A, b, u, _ = workloads.fem_p1_unit_square(npts, k, mode)
+        rp, ci, v = workloads.to_csr_arrays(A)
+        csr = (torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(),
+               torch.as_tensor(v).cuda())
+        s = rg.Solver(csr=csr, shape=A.shape, eta=eta, stop="rse", tol=tol,
+                      max_iter=max_iter)
+        bt = torch.as_tensor(b).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = s.solve(bt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s.close()
+        xh = x.cpu().numpy()
+        row = {"n": int(A.shape[0]), "nnz": int(A.nnz),
+               "iterations": info["iterations"],
+               "converged": bool(info["converged"]),
+               "ms": round(1e3 * el, 1),
+               "us_per_iteration": round(1e6 * el / max(info["iterations"], 1), 1),
+               "rse": float(np.linalg.norm(b - A @ xh) ** 2 / np.linalg.norm(b) ** 2),
+               "rel_l2": float(np.linalg.norm(xh - u) / np.linalg.norm(u)),
+               "paper_rse": gold[name]["rse"],
+               "paper_rel_l2": gold[name]["rel_l2"]}
+        log(f"fem {name}: {row}")
+        out[name] = row
     return out
 
 

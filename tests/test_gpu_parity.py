@@ -688,3 +688,20 @@ def test_block_law_trajectory(rg):
           flush=True)
     assert rel(x.cpu().numpy(), xo) <= TRAJ_TOL
     assert rel(z, zo) <= TRAJ_TOL
+
+
+# ------------------------------------------------- finite-element systems
+@pytest.mark.parametrize("npts,k,mode", [(25, 0.0, 1), (50, 25.0, 4)],
+                         ids=["poisson", "helmholtz"])
+def test_fem_trajectory(rg, npts, k, mode):
+    # Section 6's FEM systems at eta = 0.5 (313 / 1250 of 625 / 2500
+    # columns and rows): symmetric, boundary identity rows, and right-hand
+    # sides that vanish on the boundary (zero weights that are never drawn)
+    A, b, u, xy = workloads.fem_p1_unit_square(npts, k, mode)
+    p = SimpleNamespace(a=A, b=b)
+    kc = kr = int(np.floor(0.5 * A.shape[0] + 0.5))
+    x, z, info, xo, zo = run_both(rg, p, kc, kr, 4, sparse=True,
+                                  inner_max=2000)
+    print(f"fem npts={npts} k={k} rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+    assert rel(x, xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL

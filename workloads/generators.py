@@ -249,3 +249,55 @@ def laplacian_batch(count=256, n_min=2000, n_max=200000, extra=0.2,
         out.append(Problem(f"laplacian_{s}", a, a @ x, x,
                            meta=dict(nx=nx, ny=ny, shift=shift)))
     return out
+
+
+def fem_p1_unit_square(npts, k=0.0, mode=1):
+    """P1 finite elements on the unit square (Section 6, finite element
+    method): an npts x npts uniform grid of nodes, Delaunay-triangulated
+    (2 (npts-1)^2 elements), for -Laplace(u) - k^2 u = f with u = 0 on the
+    boundary and the exact solution u = sin(mode pi x) sin(mode pi y).
+    Every grid cell has four cocircular corners, so which diagonal splits
+    it is the triangulator's choice; scipy's Qhull is used, as its choice
+    reproduces the condition number the paper reports for Helmholtz.
+    Assembled: stiffness K and consistent mass M; A = K - k^2 M;
+    b = M f_I (f interpolated at the nodes); boundary nodes get identity
+    rows, and their columns are removed from the other rows (u = 0 there).
+    Returns (A csr, b, u_exact at the nodes, coordinates)."""
+    from scipy.spatial import Delaunay
+    xs = np.linspace(0.0, 1.0, npts)
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    tris = Delaunay(xy).simplices
+    rows, cols, kv, mv = [], [], [], []
+    for t in tris:
+        p = xy[t]
+        mat = np.array([[1.0, p[0, 0], p[0, 1]], [1.0, p[1, 0], p[1, 1]],
+                        [1.0, p[2, 0], p[2, 1]]])
+        area = 0.5 * abs(np.linalg.det(mat))
+        grads = np.linalg.inv(mat)[1:, :]          # d(phi_i)/dx, d/dy
+        ke = area * grads.T @ grads
+        me = area / 12.0 * (np.ones((3, 3)) + np.eye(3))
+        for a_ in range(3):
+            for b2 in range(3):
+                rows.append(t[a_]); cols.append(t[b2])
+                kv.append(ke[a_, b2]); mv.append(me[a_, b2])
+    N = npts * npts
+    K = sp.csr_matrix((kv, (rows, cols)), shape=(N, N))
+    M = sp.csr_matrix((mv, (rows, cols)), shape=(N, N))
+    w = mode * np.pi
+    u = np.sin(w * xy[:, 0]) * np.sin(w * xy[:, 1])
+    f = (2.0 * w * w - k * k) * u
+    A = (K - (k * k) * M).tolil()
+    b = M @ f
+    bnd = np.where((xy[:, 0] == 0) | (xy[:, 0] == 1) | (xy[:, 1] == 0) |
+                   (xy[:, 1] == 1))[0]
+    A[:, bnd] = 0.0
+    A[bnd, :] = 0.0
+    for i in bnd:
+        A[i, i] = 1.0
+    b[bnd] = 0.0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    A.data[np.abs(A.data) < 1e-14 * np.abs(A.data).max()] = 0.0
+    A.eliminate_zeros()
+    return A, b, u, xy
