@@ -45,8 +45,8 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from .select import (select, select_threshold, select_block_law, block_size,
-                     FLOOR_FP64)
+from .select import (select, select_threshold, select_block_law, select_iid,
+                     block_size, FLOOR_FP64)
 from .blockls import column_projection, row_projection
 
 
@@ -89,7 +89,7 @@ def row_weights(b, z_next, q, rho):
 def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
            stop="none", tol=0.0, x_ref=None, sys=0, key1=0, it0=0,
            x0=None, z0=None, col_offset=None, record=False,
-           floor=FLOOR_FP64, greedy=None, block_law=False):
+           floor=FLOOR_FP64, greedy=None, block_law=False, iid=False):
     """Run Algorithm 1.  Returns (x, z, Info).
 
     a: dense (m, n) ndarray or scipy sparse matrix; b: (m,) FP64.
@@ -99,7 +99,9 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
     (0, 1] for GDBEK's greedy sets {eps_j >= greedy * max eps} (Section 2),
     with the same update rules and the same order of the two phases.
     block_law: draw the blocks from the law of Lemma 2.1 instead
-    (``select_block_law``, block sizes k_col / k_row)."""
+    (``select_block_law``, block sizes k_col / k_row).
+    iid: draw k_col / k_row indices with replacement and keep the distinct
+    ones (``select_iid``)."""
     if sp.issparse(a):
         a = sp.csr_matrix(a, dtype=np.float64)
         a_csc = a.tocsc()
@@ -137,6 +139,8 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
             u = select_threshold(eps_z, greedy)
         elif block_law:
             u = select_block_law(eps_z, k_col, seed, it, 0, sys, key1, floor)
+        elif iid:
+            u = select_iid(eps_z, k_col, seed, it, 0, sys, key1, floor)
         else:
             u = select(eps_z, k_col, seed, it, 0, sys, key1, floor)
         z_prev = z
@@ -161,6 +165,8 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
             j = select_threshold(eps_x, greedy)
         elif block_law:
             j = select_block_law(eps_x, k_row, seed, it, 1, sys, key1, floor)
+        elif iid:
+            j = select_iid(eps_x, k_row, seed, it, 1, sys, key1, floor)
         else:
             j = select(eps_x, k_row, seed, it, 1, sys, key1, floor)
         x_prev = x

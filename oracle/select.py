@@ -120,3 +120,49 @@ def select_block_law(eps, s, seed, it, phase, sys=0, key1=0, floor=FLOOR_FP64):
     order = np.lexsort((idx, keys))
     chosen = idx[order[:s - 1]]
     return np.sort(np.concatenate([chosen, [j0]])).astype(np.int64)
+
+
+def iid_shift(d):
+    """sh = 63 - ceil(log2 d): integer weights up to 2^sh sum below 2^63."""
+    return 63 - (int(d) - 1).bit_length()
+
+
+def iid_weights(eps, floor=FLOOR_FP64):
+    """Integer weights w_j = floor(eps_j / max eps * 2^sh), zero where
+    eps_j <= floor * max eps; (w, sh).  The quotient is one correctly
+    rounded FP64 division, the scaling by 2^sh is exact."""
+    eps = np.asarray(eps, dtype=np.float64)
+    d = eps.size
+    sh = iid_shift(max(d, 1))
+    mx = eps.max() if d else 0.0
+    if not mx > 0:
+        return np.zeros(d, dtype=np.uint64), sh
+    q = np.floor((eps / mx) * (2.0 ** sh))
+    q[~(eps > floor * mx)] = 0.0
+    return q.astype(np.uint64), sh
+
+
+def select_iid(eps, k, seed, it, phase, sys=0, key1=0, floor=FLOOR_FP64):
+    """k independent draws with replacement from P(j) = eps_j / sum eps
+    (Section 2, Algorithm 1), the distinct indices kept, ascending.
+
+    The probabilities are the integer weights of ``iid_weights`` over their
+    total W (relative resolution 2^-sh of the largest weight).  Draw t takes
+    the Philox word u_t of index t in the stream of phase + 4, r_t =
+    floor(u_t W / 2^64), and the index j whose cumulative-weight interval
+    [P_(j-1), P_j) holds r_t (exact integer arithmetic, so any summation
+    order gives the same P).  Every weight zero: the empty block."""
+    eps = np.asarray(eps, dtype=np.float64)
+    if not np.all(np.isfinite(eps)) or np.any(eps < 0):
+        raise NumericError("selection weights must be finite and >= 0")
+    if eps.size == 0 or k <= 0:
+        return np.zeros(0, dtype=np.int64)
+    w, _ = iid_weights(eps, floor)
+    P = np.cumsum(w, dtype=np.uint64)
+    W = int(P[-1])
+    if W == 0:
+        return np.zeros(0, dtype=np.int64)
+    u = index_words(np.arange(k, dtype=np.int64), seed, it, phase + 4, sys, key1)
+    r = np.array([(int(v) * W) >> 64 for v in u], dtype=np.uint64)
+    j = np.searchsorted(P, r, side="right")
+    return np.unique(j).astype(np.int64)
