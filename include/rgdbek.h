@@ -122,8 +122,10 @@ typedef struct {
                             dimension; a larger set keeps its lowest
                             indices); 2 = blocks of size k_col/k_row from
                             the law of Lemma 2.1 (see
-                            rgdbek_select_block_law).  Modes 1 and 2:
-                            single systems only.                            */
+                            rgdbek_select_block_law); 3 = k_col/k_row draws
+                            with replacement, distinct indices kept (see
+                            rgdbek_select_iid; at most 16M rows/columns).
+                            Modes 1-3: single systems only.                 */
 } rgdbek_params;
 
 /* Dense block solvers: AUTO picks Cholesky for blocks up to 256 and
@@ -134,7 +136,7 @@ enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
 enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2 };
 /* Block rule (rgdbek_params.select_mode). */
 enum { RGDBEK_SELECT_RANDOM = 0, RGDBEK_SELECT_GREEDY = 1,
-       RGDBEK_SELECT_BLOCK_LAW = 2 };
+       RGDBEK_SELECT_BLOCK_LAW = 2, RGDBEK_SELECT_IID = 3 };
 
 typedef struct {
   int64_t iterations;        /* RGDBEK iterations run (inner, summed)       */
@@ -262,6 +264,26 @@ rgdbek_status rgdbek_select_block_law(const double *eps, int64_t d, int64_t s,
                                       uint32_t phase, uint32_t sys,
                                       int32_t *out_idx, int64_t *out_count,
                                       void *stream);
+
+/* A block drawn with replacement (Section 2 probabilities, Algorithm 1's
+ * "select k indices using P" read as k independent draws): the distinct
+ * indices of k draws from P(j) = eps_j / sum eps, ascending.  The
+ * probabilities are integer weights w_j = floor(eps_j / max(eps) * 2^sh),
+ * sh = 63 - ceil(log2 d), zero where eps_j <= floor * max(eps); draw t maps
+ * the Philox word u_t of index t (stream phase + 4, otherwise the
+ * coordinates of rgdbek_select) to r_t = floor(u_t W / 2^64), W = sum w, and
+ * takes the j whose cumulative interval [w_0+..+w_(j-1), w_0+..+w_j) holds
+ * r_t.  All integer after the weights: bit-exact.  Every weight zero gives
+ * the empty block.
+ *  eps: device, d FP64 (d <= 16M);  k >= 1 draws;
+ *  out_idx: device, room for min(k, d) int32;  out_count: host.
+ * NUMERIC if a weight is NaN, negative or infinite; INVALID_ARG for d or
+ * k out of range.  Synchronises the stream before returning. */
+rgdbek_status rgdbek_select_iid(const double *eps, int64_t d, int64_t k,
+                                double floor, uint64_t seed, uint64_t key1,
+                                uint64_t it, uint32_t phase, uint32_t sys,
+                                int32_t *out_idx, int64_t *out_count,
+                                void *stream);
 
 /* GDBEK's greedy set (Section 2) on a weight vector: the indices j with
  * eps[j] > 0 and eps[j] >= eta * max(eps) (the product and comparison in

@@ -19,7 +19,7 @@ STOP_NONE, STOP_ERR_REF, STOP_RSE, STOP_RES_EXT = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED_F32, PREC_MIXED_BF16 = 0, 1, 2
 SOLVER_AUTO, SOLVER_CHOL, SOLVER_CG = 0, 1, 2
 FLAG_GRAPH, FLAG_GRAM_AAT = 1, 2
-SELECT_RANDOM, SELECT_GREEDY, SELECT_BLOCK_LAW = 0, 1, 2
+SELECT_RANDOM, SELECT_GREEDY, SELECT_BLOCK_LAW, SELECT_IID = 0, 1, 2, 3
 
 STOP_NAMES = {"none": STOP_NONE, "err_ref": STOP_ERR_REF, "rse": STOP_RSE,
               "res_ext": STOP_RES_EXT}
@@ -75,6 +75,13 @@ SIGNATURES = {
                                      ctypes.c_uint32, ctypes.c_uint32, _vp,
                                      ctypes.POINTER(ctypes.c_int64), _vp]),
     "rgdbek_select_block_law": (ctypes.c_int, [_vp, ctypes.c_int64,
+                                               ctypes.c_int64, ctypes.c_double,
+                                               ctypes.c_uint64, ctypes.c_uint64,
+                                               ctypes.c_uint64, ctypes.c_uint32,
+                                               ctypes.c_uint32, _vp,
+                                               ctypes.POINTER(ctypes.c_int64),
+                                               _vp]),
+    "rgdbek_select_iid": (ctypes.c_int, [_vp, ctypes.c_int64,
                                                ctypes.c_int64, ctypes.c_double,
                                                ctypes.c_uint64, ctypes.c_uint64,
                                                ctypes.c_uint64, ctypes.c_uint32,

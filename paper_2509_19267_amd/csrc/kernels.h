@@ -41,6 +41,20 @@ int64_t select_greedy_blocks(int64_t d);
 
 // Block from the law of Lemma 2.1 (Section 2), size s (see select.hip); w:
 // d doubles of scratch, tmp: s ints of scratch.
+// Draws with replacement (select.hip): integer cumulative weights, flags.
+struct IidScratch {
+  uint64_t *ploc = nullptr;   // in-chunk inclusive weight sums (d)
+  uint64_t *ctot = nullptr;   // chunk totals
+  int32_t *flags = nullptr;   // one per index, zero between calls
+};
+int64_t select_iid_chunks(int64_t d);
+int64_t select_iid_max_d();
+template <typename T>
+void launch_select_iid(const T *eps, int64_t d, int64_t k, double floor,
+                       uint64_t seed, uint64_t key1, uint32_t phase,
+                       uint32_t sys, int ph, SelectScratch &s, IidScratch &w,
+                       int32_t *out, Ctrl *ctrl, int respect_done,
+                       hipStream_t st);
 template <typename T>
 void launch_select_block_law(const T *eps, int64_t d, int64_t s, double floor,
                              uint64_t seed, uint64_t key1, uint32_t phase,

@@ -109,6 +109,7 @@ struct Engine {
   double *segmax = nullptr;   // per-system largest weight (batch)
   double *blw = nullptr;      // block law: unit weights of the subset draw
   int32_t *bltmp = nullptr;   // block law: the subset before the merge
+  IidScratch iid;             // draws with replacement
   int64_t seg_dmax[2] = {0, 0};  // largest system dimension per phase
   int64_t *selcnt = nullptr;  // per-system draw counts (batch)
   int nseg = 0;               // systems (0: a single system)
@@ -351,6 +352,14 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     e.blw = P.alloc<double>(dmax + 64);
     e.bltmp = P.alloc<int32_t>(std::max(e.kc, e.kr) + 64);
   }
+  if (h->p.select_mode == RGDBEK_SELECT_IID) {
+    if (dmax > select_iid_max_d())
+      throw ApiError{RGDBEK_ERR_UNSUPPORTED,
+                     "draws with replacement take at most 16M rows/columns"};
+    e.iid.ploc = P.alloc<uint64_t>(dmax + 64);
+    e.iid.ctot = P.alloc<uint64_t>(select_iid_chunks(dmax) + 64);
+    e.iid.flags = P.alloc<int32_t>(dmax + 64);
+  }
   e.red.part = P.alloc<double>(1024);
   e.red.cap = 1024;
   if (h->nseg) {
@@ -449,6 +458,9 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
   else if (p.select_mode == RGDBEK_SELECT_BLOCK_LAW)
     launch_select_block_law<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0,
                                0, 0, e.sel, e.blw, e.bltmp, e.U, c, 1, st);
+  else if (p.select_mode == RGDBEK_SELECT_IID)
+    launch_select_iid<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0,
+                         e.sel, e.iid, e.U, c, 1, st);
   else
     launch_select<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0,
                      e.sel, e.U, c, 1, st);
@@ -501,6 +513,9 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
   else if (p.select_mode == RGDBEK_SELECT_BLOCK_LAW)
     launch_select_block_law<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1,
                                0, 1, e.sel, e.blw, e.bltmp, e.J, c, 1, st);
+  else if (p.select_mode == RGDBEK_SELECT_IID)
+    launch_select_iid<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1,
+                         e.sel, e.iid, e.J, c, 1, st);
   else
     launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1,
                      e.sel, e.J, c, 1, st);
@@ -922,7 +937,8 @@ void validate_params(const rgdbek_params *p, int64_t m, int64_t n,
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "tile_rows must lie in [0, 2^20]"};
   if (p->select_mode != RGDBEK_SELECT_RANDOM &&
       p->select_mode != RGDBEK_SELECT_GREEDY &&
-      p->select_mode != RGDBEK_SELECT_BLOCK_LAW)
+      p->select_mode != RGDBEK_SELECT_BLOCK_LAW &&
+      p->select_mode != RGDBEK_SELECT_IID)
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "unknown select_mode"};
   if (p->select_mode == RGDBEK_SELECT_GREEDY && !(p->eta > 0.0))
     throw ApiError{RGDBEK_ERR_INVALID_ARG,
@@ -1684,6 +1700,44 @@ rgdbek_status rgdbek_select_block_law(const double *eps, int64_t d, int64_t s,
     *out_count = hc.sel_count[0];
     if (hc.sync_fail)
       throw ApiError{RGDBEK_ERR_DEVICE, "a grid-barrier wait timed out"};
+    if (hc.numeric)
+      throw ApiError{RGDBEK_ERR_NUMERIC, "weights must be finite and >= 0"};
+    return RGDBEK_OK;
+  });
+  P.release();
+  return r;
+}
+
+rgdbek_status rgdbek_select_iid(const double *eps, int64_t d, int64_t k,
+                                double floor, uint64_t seed, uint64_t key1,
+                                uint64_t it, uint32_t phase, uint32_t sys,
+                                int32_t *out_idx, int64_t *out_count,
+                                void *stream) {
+  if (!eps || !out_idx || !out_count || d <= 0 || k <= 0 ||
+      d > select_iid_max_d()) {
+    set_err(nullptr, "invalid arguments to rgdbek_select_iid");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  Pool P;
+  P.st = st;
+  rgdbek_status r = guarded(nullptr, [&]() {
+    SelectScratch sc;
+    sc.blk = P.alloc<int32_t>(select_iid_chunks(d) + 64);
+    sc.gmax = P.alloc<double>(select_iid_chunks(d) + 64);
+    IidScratch w;
+    w.ploc = P.alloc<uint64_t>(d + 64);
+    w.ctot = P.alloc<uint64_t>(select_iid_chunks(d) + 64);
+    w.flags = P.alloc<int32_t>(d + 64);
+    Ctrl *c = P.alloc<Ctrl>(1);
+    launch_fill_ctrl_it(c, (int64_t)it, st);
+    launch_select_iid<double>(eps, d, k, floor, seed, key1, phase, sys, 0, sc,
+                              w, out_idx, c, 0, st);
+    Ctrl hc;
+    HIPCHK(hipMemcpyAsync(&hc, c, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    *out_count = hc.sel_count[0];
     if (hc.numeric)
       throw ApiError{RGDBEK_ERR_NUMERIC, "weights must be finite and >= 0"};
     return RGDBEK_OK;

@@ -24,6 +24,8 @@
 //  large d (multi-workgroup): keys + histogram of bits 62..52 -> scan ->
 //    histogram of bits 51..41 -> scan -> gather the few candidates left ->
 //    one-workgroup bitonic sort -> per-chunk counts -> ordered compaction.
+#include <cmath>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -1439,6 +1441,229 @@ template void launch_select_greedy<float>(const float *, int64_t, double,
                                           int64_t, int, SelectScratch &,
                                           int32_t *, Ctrl *, int, hipStream_t);
 int64_t select_greedy_blocks(int64_t d) { return (d + GR_CH - 1) / GR_CH; }
+
+// ------------------------------------------------ draws with replacement
+// k independent draws from P(j) = eps_j / sum eps, the distinct indices kept
+// in ascending order.  Integer weights w_j = floor(eps_j / max eps * 2^sh)
+// (one FP64 division, an exact scaling and an exact floor), zero at or below
+// floor * max eps, with sh = 63 - ceil(log2 d): the total W stays below
+// 2^63 and every cumulative sum is exact in any order.  Draw t takes the
+// Philox word u_t of index t in the stream of phase + 4, r_t =
+// floor(u_t W / 2^64), and the index j with P_(j-1) <= r_t < P_j.  Five
+// launches, no float atomics: chunk maxima (gr_max); integer weights with
+// in-chunk inclusive sums and chunk totals; the draws (the chunk by a binary
+// search over the chunk prefix held in LDS, then a binary search inside the
+// chunk) set one flag per drawn index; per-chunk flag counts; ordered
+// writes that also clear the flags for the next call.
+constexpr int ID_NT = GR_NT;
+constexpr int ID_PT = GR_PT;                    // consecutive weights per thread
+constexpr int64_t ID_CH = GR_CH;                // chunk = gr_max's chunk
+constexpr int ID_MAXCH = 4096;                  // chunks: d <= 16M
+constexpr int ID_DRAW_NT = 256;
+
+__device__ __forceinline__ double id_gmax(const double *pmax, int nb,
+                                          double *sh) {
+  double gm = 0.0;
+  for (int b = threadIdx.x; b < nb; b += ID_NT) gm = pmax[b] > gm ? pmax[b] : gm;
+  gm = wave_max(gm);
+  __syncthreads();
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = gm;
+  __syncthreads();
+  gm = 0.0;
+  for (int i = 0; i < ID_NT / WAVE; ++i) gm = sh[i] > gm ? sh[i] : gm;
+  return gm;
+}
+
+// exclusive scan of one uint64 per thread over the block; *tot = the sum
+__device__ __forceinline__ uint64_t id_scan(uint64_t v, uint64_t *sh,
+                                            uint64_t *tot) {
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  uint64_t inc = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const uint64_t u = __shfl_up(inc, o, WAVE);
+    if (lane >= o) inc += u;
+  }
+  __syncthreads();
+  if (lane == WAVE - 1) sh[wv] = inc;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+  for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
+    if (i < wv) before += sh[i];
+    all += sh[i];
+  }
+  *tot = all;
+  return before + inc - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(ID_NT)
+id_weights(const T *__restrict__ eps, int64_t d, double flr, double scale,
+           const double *__restrict__ pmax, uint64_t *__restrict__ ploc,
+           uint64_t *__restrict__ ctot, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ double sh[ID_NT / WAVE];
+  __shared__ uint64_t shu[ID_NT / WAVE];
+  const double gm = id_gmax(pmax, (int)gridDim.x, sh);
+  const double cut = flr * gm;
+  const int64_t j0 = (int64_t)blockIdx.x * ID_CH + (int64_t)threadIdx.x * ID_PT;
+  uint64_t w[ID_PT];
+  uint64_t acc = 0;
+  int bad = 0;
+#pragma unroll
+  for (int q = 0; q < ID_PT; ++q) {
+    const int64_t j = j0 + q;
+    uint64_t v = 0;
+    if (j < d) {
+      const double e = (double)eps[j];
+      if (!(e >= 0.0) || e > 1.7976931348623157e308) bad = 1;
+      else if (gm > 0.0 && e > cut) v = (uint64_t)__builtin_floor((e / gm) * scale);
+    }
+    acc += v;
+    w[q] = acc;                                  // in-thread inclusive sums
+  }
+  if (bad) atomicOr(&ctrl->numeric, 1);
+  uint64_t tot;
+  const uint64_t before = id_scan(acc, shu, &tot);
+#pragma unroll
+  for (int q = 0; q < ID_PT; ++q)
+    if (j0 + q < d) ploc[j0 + q] = before + w[q];
+  if (threadIdx.x == 0) ctot[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(ID_DRAW_NT)
+id_draw(int64_t k, int64_t d, int nb, uint64_t seed, uint64_t key1,
+        uint32_t phase, uint32_t sys, const uint64_t *__restrict__ ploc,
+        const uint64_t *__restrict__ ctot, int32_t *__restrict__ flags,
+        Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ uint64_t cp[ID_MAXCH];
+  __shared__ uint64_t shu[ID_DRAW_NT / WAVE];
+  // inclusive prefix of the chunk totals: consecutive runs per thread
+  const int per = (nb + ID_DRAW_NT - 1) / ID_DRAW_NT;
+  const int b0 = threadIdx.x * per;
+  uint64_t run = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) run += ctot[b0 + i];
+  uint64_t all;
+  uint64_t pre = id_scan(run, shu, &all);
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) { pre += ctot[b0 + i]; cp[b0 + i] = pre; }
+  __syncthreads();
+  const uint64_t W = all;
+  if (W == 0) return;
+  const uint64_t it = (uint64_t)ctrl->it;
+  for (int64_t t = (int64_t)blockIdx.x * ID_DRAW_NT + threadIdx.x; t < k;
+       t += (int64_t)gridDim.x * ID_DRAW_NT) {
+    const P4 rw = philox4x64_10((uint64_t)(t >> 2), it, phase, sys, seed, key1);
+    const uint64_t r = __umul64hi(rw.v[t & 3], W);     // r < W
+    int lo = 0, hi = nb - 1;                         // first chunk with cp > r
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cp[mid] > r) hi = mid; else lo = mid + 1;
+    }
+    const uint64_t r2 = r - (lo ? cp[lo - 1] : 0ull);
+    int64_t a = (int64_t)lo * ID_CH;
+    int64_t b = a + ID_CH < d ? a + ID_CH - 1 : d - 1;  // ploc[b] = chunk total > r2
+    while (a < b) {
+      const int64_t mid = (a + b) >> 1;
+      if (ploc[mid] > r2) b = mid; else a = mid + 1;
+    }
+    flags[a] = 1;
+  }
+}
+
+__global__ void __launch_bounds__(ID_NT)
+id_count(const int32_t *__restrict__ flags, int64_t d,
+         int32_t *__restrict__ blk, Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ int64_t sh64[ID_NT / WAVE];
+  const int64_t base = (int64_t)blockIdx.x * ID_CH;
+  int64_t c = 0;
+#pragma unroll
+  for (int q = 0; q < ID_PT; ++q) {
+    const int64_t j = base + (int64_t)q * ID_NT + threadIdx.x;
+    if (j < d) c += flags[j] != 0;
+  }
+  c = block_sum_i64<ID_NT>(c, sh64);
+  if (threadIdx.x == 0) blk[blockIdx.x] = (int32_t)c;
+}
+
+__global__ void __launch_bounds__(ID_NT)
+id_write(int32_t *__restrict__ flags, int64_t d,
+         const int32_t *__restrict__ blk, int32_t *__restrict__ out,
+         Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ int64_t sh64[ID_NT / WAVE];
+  __shared__ int wtot[ID_NT / WAVE];
+  int64_t before = 0, total = 0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += ID_NT) {
+    total += blk[b];
+    if (b < (int)blockIdx.x) before += blk[b];
+  }
+  before = block_sum_i64<ID_NT>(before, sh64);
+  total = block_sum_i64<ID_NT>(total, sh64);
+  const int64_t base = (int64_t)blockIdx.x * ID_CH;
+  int64_t off = before;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  for (int q = 0; q < ID_PT; ++q) {
+    const int64_t j = base + (int64_t)q * ID_NT + threadIdx.x;
+    const bool f = j < d && flags[j] != 0;
+    const uint64_t mask = __ballot(f);
+    __syncthreads();
+    if (lane == 0) wtot[wv] = __popcll(mask);
+    __syncthreads();
+    int wb = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < ID_NT / WAVE; ++i) {
+      if (i < wv) wb += wtot[i];
+      tot += wtot[i];
+    }
+    if (f) {
+      out[off + wb + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)j;
+      flags[j] = 0;
+    }
+    off += tot;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->sel_count[ph] = total;
+}
+
+int64_t select_iid_chunks(int64_t d) { return (d + ID_CH - 1) / ID_CH; }
+int64_t select_iid_max_d() { return (int64_t)ID_MAXCH * ID_CH; }
+
+template <typename T>
+void launch_select_iid(const T *eps, int64_t d, int64_t k, double floor,
+                       uint64_t seed, uint64_t key1, uint32_t phase,
+                       uint32_t sys, int ph, SelectScratch &s, IidScratch &w,
+                       int32_t *out, Ctrl *ctrl, int respect_done,
+                       hipStream_t st) {
+  const int nb = (int)select_iid_chunks(d);
+  int sh = 63;
+  while (sh > 0 && (((int64_t)1) << (63 - sh)) < d) --sh;   // 63 - ceil(log2 d)
+  const double scale = std::ldexp(1.0, sh);
+  hipLaunchKernelGGL(gr_max<T>, dim3(nb), dim3(GR_NT), 0, st, eps, d, s.gmax,
+                     ctrl, respect_done);
+  hipLaunchKernelGGL(id_weights<T>, dim3(nb), dim3(ID_NT), 0, st, eps, d,
+                     floor, scale, s.gmax, w.ploc, w.ctot, ctrl, respect_done);
+  int64_t g = (k + ID_DRAW_NT - 1) / ID_DRAW_NT;
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(id_draw, dim3((unsigned)(g > 0 ? g : 1)), dim3(ID_DRAW_NT),
+                     0, st, k > 0 ? k : 0, d, nb, seed, key1, phase + 4u, sys,
+                     w.ploc, w.ctot, w.flags, ctrl, respect_done);
+  hipLaunchKernelGGL(id_count, dim3(nb), dim3(ID_NT), 0, st, w.flags, d, s.blk,
+                     ctrl, respect_done);
+  hipLaunchKernelGGL(id_write, dim3(nb), dim3(ID_NT), 0, st, w.flags, d, s.blk,
+                     out, ctrl, ph, respect_done);
+}
+template void launch_select_iid<double>(const double *, int64_t, int64_t,
+                                        double, uint64_t, uint64_t, uint32_t,
+                                        uint32_t, int, SelectScratch &,
+                                        IidScratch &, int32_t *, Ctrl *, int,
+                                        hipStream_t);
+template void launch_select_iid<float>(const float *, int64_t, int64_t, double,
+                                       uint64_t, uint64_t, uint32_t, uint32_t,
+                                       int, SelectScratch &, IidScratch &,
+                                       int32_t *, Ctrl *, int, hipStream_t);
 
 // ------------------------------------------------ launcher
 template <typename T>

@@ -79,7 +79,8 @@ class Solver:
         p.weight_floor = float(weight_floor)
         p.tile_rows = int(tile_rows)
         p.select_mode = {"random": B.SELECT_RANDOM, "greedy": B.SELECT_GREEDY,
-                         "block_law": B.SELECT_BLOCK_LAW}[select]
+                         "block_law": B.SELECT_BLOCK_LAW,
+                         "iid": B.SELECT_IID}[select]
         p.flags = (B.FLAG_GRAPH if graph else 0) | (B.FLAG_GRAM_AAT if gram_aat else 0)
         self.m, self.n = int(m), int(n)
         self.params = p
@@ -209,7 +210,8 @@ class BatchSolver(Solver):
         p.flags = B.FLAG_GRAPH if graph else 0
         p.weight_floor = float(weight_floor)
         p.select_mode = {"random": B.SELECT_RANDOM, "greedy": B.SELECT_GREEDY,
-                         "block_law": B.SELECT_BLOCK_LAW}[select]
+                         "block_law": B.SELECT_BLOCK_LAW,
+                         "iid": B.SELECT_IID}[select]
         self.m, self.n, self.params, self.stream = m, n, p, stream
         st = lib.rgdbek_create_batched(ctypes.byref(mat), self.nsys, ro, co,
                                        ctypes.byref(p), _stream(stream),
@@ -322,6 +324,24 @@ def select_block_law(eps, s, seed=0, it=0, phase=0, sys=0, key1=0,
                                      int(seed), int(key1), int(it), int(phase),
                                      int(sys), _ptr(out), ctypes.byref(cnt),
                                      _stream(stream))
+    B.check(st, None)
+    return out[:cnt.value]
+
+
+def select_iid(eps, k, seed=0, it=0, phase=0, sys=0, key1=0, floor=1e-20,
+               stream=None):
+    """Distinct indices of k draws with replacement from P(j) = eps_j /
+    sum eps on given weights (device FP64 tensor): ascending int32 indices,
+    as the solver draws them in the "iid" mode."""
+    lib = B.load()
+    _need_cuda(eps, "eps", torch.float64)
+    d = eps.numel()
+    out = torch.empty(max(1, min(int(k), d)), dtype=torch.int32,
+                      device=eps.device)
+    cnt = ctypes.c_int64(0)
+    st = lib.rgdbek_select_iid(_ptr(eps), d, int(k), float(floor), int(seed),
+                               int(key1), int(it), int(phase), int(sys),
+                               _ptr(out), ctypes.byref(cnt), _stream(stream))
     B.check(st, None)
     return out[:cnt.value]
 

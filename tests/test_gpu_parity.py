@@ -705,3 +705,86 @@ def test_fem_trajectory(rg, npts, k, mode):
     print(f"fem npts={npts} k={k} rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
     assert rel(x, xo) <= TRAJ_TOL
     assert rel(z, zo) <= TRAJ_TOL
+
+
+# ------------------------------------------------- draws with replacement
+def iid_cases():
+    rng = np.random.default_rng(60)
+    yield "random", rng.random(1000) ** 4, 500
+    e = rng.random(5000)
+    e[rng.random(5000) < 0.7] = 0.0
+    yield "zero_heavy", e, 3000
+    yield "ties", np.repeat([0.5, 1.0, 2.0], [300, 300, 400]), 700
+    yield "k1", rng.random(777), 1
+    yield "k_gt_d", rng.random(300) + 0.1, 2000
+    yield "one_weight", np.eye(1, 97, 13).ravel(), 5
+    yield "all_zero", np.zeros(400), 30
+    yield "denormal", np.full(200, 5e-324), 17
+    yield "chunk_edge", rng.random(4097), 4097
+    yield "multi_chunk", rng.random(300_000) ** 3, 100_000
+    big = rng.random(1_000_000)
+    big[rng.random(1_000_000) < 0.5] = 0.0
+    yield "rows_1e6", big, 250_000
+
+
+@pytest.mark.parametrize("case", list(iid_cases()), ids=lambda c: c[0])
+def test_select_iid_bit_exact(rg, case):
+    from oracle.select import select_iid as oiid
+    name, eps, k = case
+    print(f"iid case {name} d={eps.size} k={k}", flush=True)
+    for (seed, it, phase, sys, key1, floor) in [(0, 0, 0, 0, 0, 1e-20),
+                                                (77, 9, 1, 3, 1, 0.0)]:
+        got = rg.select_iid(dev(eps), k, seed=seed, it=it, phase=phase,
+                            sys=sys, key1=key1, floor=floor).cpu().numpy()
+        want = oiid(eps, k, seed, it, phase, sys, key1, floor)
+        assert np.array_equal(got.astype(np.int64), want), name
+
+
+def test_iid_trajectories(rg):
+    # dense least squares and sparse uniform, blocks drawn with replacement
+    p = workloads.dense_least_squares(2000, 500, seed=61)
+    s = rg.Solver(dev(p.a), k_col=120, k_row=300, select="iid", stop="none",
+                  max_iter=4, inner_max=300)
+    x, _ = s.solve(dev(p.b))
+    z = s.get_z().cpu().numpy()
+    s.close()
+    xo, zo, _ = rgdbek(p.a, p.b, k_col=120, k_row=300, max_iter=4, iid=True)
+    print(f"iid dense: rel_x {rel(x.cpu().numpy(), xo):.2e} rel_z {rel(z, zo):.2e}", flush=True)
+    assert rel(x.cpu().numpy(), xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
+    p = workloads.sparse_uniform(3000, 1500, density=0.01, seed=62)
+    s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, k_col=150, k_row=300,
+                  select="iid", stop="none", max_iter=4, inner_max=300)
+    x, _ = s.solve(dev(p.b))
+    z = s.get_z().cpu().numpy()
+    s.close()
+    xo, zo, _ = rgdbek(p.a, p.b, k_col=150, k_row=300, max_iter=4, iid=True)
+    print(f"iid sparse: rel_x {rel(x.cpu().numpy(), xo):.2e} rel_z {rel(z, zo):.2e}", flush=True)
+    assert rel(x.cpu().numpy(), xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
+
+
+def test_iid_table_iteration_counts(rg):
+    # Tables 1 and 2 (sparse 1% random, eta = 0.5, RSE <= 1e-6): with draws
+    # with replacement the GPU solver needs the paper's iteration counts
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "paper_iteration_counts.json")) as f:
+        gold = json.load(f)
+    for m, n, ref in ((8000, 500, gold["tall_8000_rows"]["500"]),
+                      (8000, 1000, gold["tall_8000_rows"]["1000"]),
+                      (500, 8000, gold["fat_8000_columns"]["500"]),
+                      (1000, 8000, gold["fat_8000_columns"]["1000"])):
+        its = []
+        for seed in range(3):
+            p = workloads.sparse_uniform(m, n, density=0.01, seed=seed)
+            s = rg.Solver(csr=csr_tensors(p.a), shape=(m, n), eta=0.5,
+                          select="iid", stop="rse", tol=1e-6, max_iter=1000,
+                          seed=seed)
+            _, info = s.solve(dev(p.b))
+            s.close()
+            assert info["converged"] == 1
+            its.append(info["iterations"])
+        print(f"iid {m}x{n}: {its} paper {ref}", flush=True)
+        assert abs(np.mean(its) - ref) <= 0.1 * ref
