@@ -393,7 +393,8 @@ def batched_laplacian(count=16, itol=0.1, imax=16, tol=1e-8):
 def gdbek_vs_rgdbek(shapes=((8000, 500), (8000, 1000), (500, 8000),
                              (1000, 8000)), seeds=3, eta=0.5, tol=1e-6):
     """The comparison of Section 3 (Tables 1 and 2) on the same kernels:
-    GDBEK's greedy sets vs RGDBEK's randomized draws, threshold / fraction
+    GDBEK's greedy sets vs RGDBEK's randomized draws (without replacement,
+    and with replacement keeping the distinct indices), threshold / fraction
     eta = 0.5, stop at ||Ax - b||^2 <= tol ||b||^2, on sparse random matrices
     with 1% density (N(0,1) values, planted x*) -- synthetic stand-ins for
     the paper's sprandn matrices.  Mean iterations and time over `seeds`
@@ -406,7 +407,7 @@ def gdbek_vs_rgdbek(shapes=((8000, 500), (8000, 1000), (500, 8000),
     out = []
     for m, n in shapes:
         row = {"m": m, "n": n}
-        for method in ["greedy", "random"]:
+        for method in ["greedy", "random", "iid"]:
             its, ts = [], []
             for seed in range(seeds):
                 p = workloads.sparse_uniform(m, n, density=0.01, seed=seed)
@@ -424,7 +425,8 @@ def gdbek_vs_rgdbek(shapes=((8000, 500), (8000, 1000), (500, 8000),
                 ts.append(time.perf_counter() - t0)
                 its.append(info["iterations"])
                 s.close()
-            name = "gdbek" if method == "greedy" else "rgdbek"
+            name = {"greedy": "gdbek", "random": "rgdbek",
+                    "iid": "rgdbek_with_replacement"}[method]
             row[f"{name}_iterations"] = float(np.mean(its))
             row[f"{name}_ms"] = round(1e3 * float(np.mean(ts)), 2)
         key = ("tall_8000_rows", str(n)) if m == 8000 else ("fat_8000_columns", str(m))
