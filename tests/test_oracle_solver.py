@@ -346,8 +346,8 @@ def test_greedy_all_zero_weights_skip():
 def test_table2_gdbek_iterations_loose():
     # GDBEK (threshold 0.5) on 8000x500 sprandn-like matrices: the paper's
     # Table 2 reports 35.1 iterations on average to RSE <= 1e-6; our
-    # synthetic stand-in must land within a factor of 1.5 of it, and above
-    # RGDBEK's count on the same matrices (the table's ordering)
+    # synthetic stand-in must land within 15% of it, and above RGDBEK's
+    # count on the same matrices (the table's ordering)
     with open(os.path.join(GOLDEN, "paper_iteration_counts.json")) as f:
         gold = json.load(f)
     ref = gold["gdbek_tall_8000_rows"]["500"]
@@ -361,5 +361,5 @@ def test_table2_gdbek_iterations_loose():
         x, z, info = rgdbek(p.a, p.b, eta=0.5, max_iter=200, stop="rse",
                             tol=1e-6, seed=seed)
         its_r.append(info.iterations)
-    assert ref / 1.5 <= np.mean(its_g) <= 1.5 * ref
+    assert abs(np.mean(its_g) - ref) <= 0.15 * ref, its_g
     assert np.mean(its_g) > np.mean(its_r)
