@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the sparse pass and batched-form measurements")
+    ap.add_argument("--probe-sparse", action="store_true",
+                    help="counter-run program: copy calibration, then the "
+                    "sparse residual passes on the power-law matrix")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: a 1 GiB device copy (calibration) "
                          "and fused-pass launches only, no solves")
@@ -88,6 +91,42 @@ def probe(args):
     print(json.dumps({"probe": "done", "m": m, "n": n}))
 
 
+def probe_sparse():
+    """Short program for hardware-counter runs of the sparse path: the 1 GiB
+    device copy (calibration), then three CSR + CSC residual pass pairs
+    (rgdbek_apply) per precision on the 1,000,000 x 500,000 power-law
+    matrix."""
+    import torch
+    import paper_2509_19267_amd as rg
+    import workloads
+    dev = torch.device("cuda", 0)
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    log("copy: 1 GiB read + 1 GiB write per launch")
+    p = workloads.sparse_powerlaw(1_000_000, 500_000, mean_len=10,
+                                  max_len=2000, seed=0)
+    m, n = p.a.shape
+    rp, ci, v = workloads.to_csr_arrays(p.a)
+    csr = (torch.as_tensor(rp).to(dev), torch.as_tensor(ci).to(dev),
+           torch.as_tensor(v).to(dev))
+    s = rg.Solver(csr=csr, shape=(m, n), eta=0.1, precision="mixed_f32")
+    for prec, dt in [("f64", torch.float64), ("f32", torch.float32)]:
+        x = torch.randn(n, dtype=dt, device=dev)
+        z = torch.randn(m, dtype=dt, device=dev)
+        ax = torch.empty(m, dtype=dt, device=dev)
+        atz = torch.empty(n, dtype=dt, device=dev)
+        for _ in range(3):
+            s.apply(x, z, ax, atz, precision=prec)
+        torch.cuda.synchronize()
+        log(f"sparse pass pair {prec}: 3 launches")
+    s.close()
+    print(json.dumps({"probe": "done", "m": m, "n": n, "nnz": int(p.a.nnz)}))
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dense_fused_pass_20000x5000_hbm.md")
 
 
@@ -124,6 +163,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a HIP device"
     if args.probe:
         probe(args)
+        return
+    if args.probe_sparse:
+        probe_sparse()
         return
     dev = torch.device("cuda", 0)
     t0 = time.time()
