@@ -43,7 +43,7 @@ typedef enum {
   RGDBEK_ERR_NOT_CONVERGED = 3, /* max_iter reached before the stop test    */
   RGDBEK_ERR_OUT_OF_MEMORY = 4, /* a device allocation failed               */
   RGDBEK_ERR_DEVICE = 5,        /* a HIP call failed (message has details)  */
-  RGDBEK_ERR_UNSUPPORTED = 6    /* valid request this build does not serve  */
+  RGDBEK_ERR_UNSUPPORTED = 6    /* valid request the library does not serve */
 } rgdbek_status;
 
 /* Matrix storage (rgdbek_matrix.layout). */

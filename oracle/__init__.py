@@ -16,7 +16,7 @@ Modules
   blockls  the two pseudoinverse block projections (the GDBEK update rule
            that RGDBEK reuses, Section 1 / Section 2).
   rgdbek   Algorithm 1 iterated step by step, plus the stopping tests, the
-           extended-residual refinement driver and the adjoint/gradient
+           extended-residual refinement loop and the adjoint/gradient
            formulas.
   refsol   closed-form references (pseudoinverse solution and optimal
            residual, Theorem 2.3 notation).
