@@ -140,12 +140,15 @@ __device__ __forceinline__ int64_t compact_chunk(const uint64_t *keys,
 // every thread); raises *numeric on a bad weight.  Radix levels of 11, 11,
 // 11, 11, 11, 9 bits with LDS histograms until the bucket holding rank k has
 // at most WG_CAND keys; those are gathered into LDS (any order) and ranked
-// by counting, giving the k-th pair (key, index); an ordered ballot/scan
-// compaction writes the block.  More than WG_CAND equal keys: the tie index
-// comes from an ordered scan.
+// by counting (O(WG_CAND^2) LDS reads, so the bucket is refined further
+// rather than ranked large), giving the k-th pair (key, index); an ordered
+// ballot/scan compaction writes the block.  More than WG_CAND equal keys:
+// the tie index comes from an ordered scan.  Up to WG_LDS_KEYS keys are
+// kept in LDS instead of the global scratch.
 constexpr int WG_NT = 1024;
-constexpr int WG_CAND = WG_NT;
+constexpr int WG_CAND = 256;
 constexpr int WG_UNROLL = 8;
+constexpr int WG_LDS_KEYS = 8192;
 
 __device__ __forceinline__ int wg_shift(int lev) { return lev < 5 ? 53 - 11 * lev : 0; }
 __device__ __forceinline__ int wg_width(int lev) { return lev < 5 ? 11 : 9; }
@@ -175,7 +178,7 @@ __device__ __forceinline__ int64_t wg_scan(int64_t v, int64_t *sh, int64_t *tot)
 // From keys (d of them, SENT for zero weights), the count of positive keys
 // and the LDS histogram of their top 11 bits: find the threshold pair and
 // write the ordered block to out; returns its size (same in every thread).
-__device__ int64_t resolve_compact(const uint64_t *__restrict__ keys,
+__device__ __forceinline__ int64_t resolve_compact(const uint64_t *__restrict__ keys,
                                    int64_t d, int64_t k, int64_t pos,
                                    unsigned *hist, int32_t *__restrict__ out) {
   constexpr int NT = WG_NT;
@@ -327,7 +330,7 @@ __device__ int64_t resolve_compact(const uint64_t *__restrict__ keys,
 }
 
 template <typename T>
-__device__ int64_t select_wg(const T *__restrict__ eps, int64_t d, int64_t k,
+__device__ __forceinline__ int64_t select_wg(const T *__restrict__ eps, int64_t d, int64_t k,
                              double floor, uint64_t seed, uint64_t key1,
                              uint64_t it, uint32_t phase, uint32_t sys,
                              uint64_t *__restrict__ keys,
@@ -336,6 +339,8 @@ __device__ int64_t select_wg(const T *__restrict__ eps, int64_t d, int64_t k,
   __shared__ unsigned hist[2048];
   __shared__ int64_t sh64[NT / WAVE];
   __shared__ double shmax[NT / WAVE];
+  __shared__ uint64_t s_keys[WG_LDS_KEYS];
+  if (d <= WG_LDS_KEYS) keys = s_keys;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   // 1. largest finite weight
   // (the passes over d issue WG_UNROLL independent loads per thread at a
@@ -489,6 +494,8 @@ sel_seg_resolve(const SegInfo *__restrict__ seg, int ph,
   const int64_t k = ph == 0 ? g.kc : g.kr;
   const int64_t ko = ph == 0 ? g.kc_off : g.kr_off;
   const uint64_t *kk = keys + off;
+  __shared__ uint64_t s_keys[WG_LDS_KEYS];
+  const bool lds = d <= WG_LDS_KEYS;     // later passes read the LDS copy
   for (int i = threadIdx.x; i < 2048; i += WG_NT) hist[i] = 0u;
   __syncthreads();
   int64_t pos = 0;
@@ -500,14 +507,18 @@ sel_seg_resolve(const SegInfo *__restrict__ seg, int ph,
       kv[u] = j < d ? kk[j] : SENT;
     }
 #pragma unroll
-    for (int u = 0; u < WG_UNROLL; ++u)
+    for (int u = 0; u < WG_UNROLL; ++u) {
+      const int64_t j = j0 + (int64_t)u * WG_NT;
+      if (lds && j < d) s_keys[j] = kv[u];
       if (kv[u] != SENT) {
         ++pos;
         atomicAdd(&hist[kv[u] >> 53], 1u);
       }
+    }
   }
-  pos = block_sum_i64<WG_NT>(pos, sh64);
-  const int64_t c = resolve_compact(kk, d, k, pos, hist, tmp + ko);
+  pos = block_sum_i64<WG_NT>(pos, sh64);   // (also orders the LDS copy)
+  const int64_t c = resolve_compact(lds ? s_keys : kk, d, k, pos, hist,
+                                    tmp + ko);
   if (threadIdx.x == 0) cnt[blockIdx.x] = c;
 }
 
@@ -1556,7 +1567,9 @@ id_draw(int64_t k, int64_t d, int nb, uint64_t seed, uint64_t key1,
   for (int64_t t = (int64_t)blockIdx.x * ID_DRAW_NT + threadIdx.x; t < k;
        t += (int64_t)gridDim.x * ID_DRAW_NT) {
     const P4 rw = philox4x64_10((uint64_t)(t >> 2), it, phase, sys, seed, key1);
-    const uint64_t r = __umul64hi(rw.v[t & 3], W);     // r < W
+    const int q = (int)(t & 3);                        // no dynamic index
+    const uint64_t u = q == 0 ? rw.v[0] : q == 1 ? rw.v[1] : q == 2 ? rw.v[2] : rw.v[3];
+    const uint64_t r = __umul64hi(u, W);               // r < W
     int lo = 0, hi = nb - 1;                         // first chunk with cp > r
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;

@@ -57,6 +57,9 @@ def sel_cases():
     yield "k_eq_d", rng.random(333) + 0.1, 333
     yield "k_gt_pos", np.where(rng.random(400) < 0.05, 1.0, 0.0), 50
     yield "denormal", np.full(200, 5e-324), 17
+    # 1000 equal (infinite) keys: more equal keys than the one-workgroup
+    # ranking holds, resolved by the ordered scan
+    yield "equal_keys", np.full(1000, 5e-324), 300
     yield "one_weight", np.eye(1, 97, 13).ravel(), 5
     yield "small_max", rng.random(65536), 6553
     yield "large_min", rng.random(65537), 6554
