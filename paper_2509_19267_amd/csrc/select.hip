@@ -1235,8 +1235,9 @@ int64_t select_persist_max(int ncu) {
   const int64_t lim = ncu < SP_MAXG ? ncu : SP_MAXG;
   return ncu > 0 ? lim * 16 * SP_NT : 0;
 }
-// smallest d that takes the persistent form (below: one workgroup)
-constexpr int64_t SP_MIN_D = 4096;
+// smallest d that takes the persistent form (below: one workgroup, keys in
+// LDS)
+constexpr int64_t SP_MIN_D = WG_LDS_KEYS + 1;
 
 // ------------------------------------------------ Lemma 2.1 block law
 // P(B) proportional to sum_{j in B} eps_j over the s-subsets: the one-index
