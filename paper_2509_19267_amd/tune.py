@@ -4,10 +4,11 @@ RGDBEK's block fraction trades per-iteration cost against iteration count
 (the remark on eta in Section 2), and the inner tolerance of the block
 projections trades inner steps against outer progress.  The tuner times
 real solves to the target tolerance on the problem at hand over a grid of
-(k_col, k_row), then over the inner tolerance and step cap, then over the
-row-tile height of the dense residual pass, for each arithmetic form, and
-keeps the fastest converging choice.  Results are cached per
-(layout, m, n, form) in tuned.json next to this file.
+(k_col, k_row), then over the inner tolerance and step cap, and keeps the
+fastest converging choice; the row-tile height of the dense residual pass
+is then picked by timing that pass alone (its effect on a whole solve is
+within run-to-run noise), and the choice is checked to converge.  Results
+are cached per (layout, m, n, form) in tuned.json next to this file.
 """
 import json
 import os
@@ -64,6 +65,41 @@ def _time_solve(a, b, x_ref, choice, *, stream, tol, precision, reps):
     return min(ts), ok, its
 
 
+def _time_pass(a, tile_rows, precision, stream, reps=30, rounds=3):
+    """Mean time of one fused residual pass (rgdbek_apply) with the given
+    row tile, best of `rounds` rounds of `reps` launches, timed with events
+    on the handle's stream."""
+    import torch
+    from .solver import Solver
+    m, n = a.shape
+    prec = "f32" if precision == "mixed_f32" else "f64"
+    dt = torch.float32 if prec == "f32" else torch.float64
+    s = Solver(a, k_col=8, k_row=8, precision="mixed_f32", stream=stream,
+               tile_rows=tile_rows)
+    try:
+        xv = torch.randn(n, dtype=dt, device=a.device)
+        zv = torch.randn(m, dtype=dt, device=a.device)
+        ax = torch.empty(m, dtype=dt, device=a.device)
+        atz = torch.empty(n, dtype=dt, device=a.device)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        for _ in range(3):
+            s.apply(xv, zv, ax, atz, precision=prec)
+        best = float("inf")
+        for _ in range(rounds):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                s.apply(xv, zv, ax, atz, precision=prec)
+            e1.record(st)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / reps)
+    finally:
+        s.close()
+    return best
+
+
 def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
                precision="fp64", reps=2):
     """Sweep the block sizes, the inner tolerance and step cap, and the row
@@ -100,7 +136,14 @@ def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
             if ch != base:
                 best = run(ch, best)
     base = best[1]
-    for tr in [32, 64, 128, 256]:
-        best = run(dict(base, tile_rows=tr), best)
-    store("dense", m, n, precision, best[1])
-    return best[1]
+    times = {}
+    for tr in [0, 64, 128, 160, 224, 256, 320, 400]:
+        times[tr] = _time_pass(a, tr, precision, stream)
+        log(f"tune {precision} fused pass tile_rows={tr}: "
+            f"{1e3 * times[tr]:.1f} us")
+    tr = min(times, key=times.get)
+    chosen = run(dict(base, tile_rows=tr), None)
+    if chosen is None:
+        chosen = best
+    store("dense", m, n, precision, chosen[1])
+    return chosen[1]
