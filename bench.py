@@ -284,7 +284,8 @@ def main():
         del a, b, xs
         torch.cuda.empty_cache()
         extras = {"spmv": spmv_powerlaw(), "batched": batched_laplacian(),
-                  "gdbek_vs_rgdbek": gdbek_vs_rgdbek(), "fem": fem_table8()}
+                  "gdbek_vs_rgdbek": gdbek_vs_rgdbek(), "fem": fem_table8(),
+                  "differentiable": differentiable_dense(args.m, args.n)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -476,6 +477,66 @@ def gdbek_vs_rgdbek(shapes=((8000, 500), (8000, 1000), (500, 8000),
         row["paper_gdbek_iterations"] = gold["gdbek_" + key[0]].get(key[1])
         log(f"gdbek vs rgdbek {m}x{n}: {row}")
         out.append(row)
+    return out
+
+
+def differentiable_dense(m, n, tol=1e-10):
+    """The differentiable form on the dense least-squares workload, FP64,
+    block settings as tuned for the FP64 form, RES_EXT stop at tol (no
+    reference solution inside a layer): time of the forward solve alone vs
+    forward + backward (adjoint solve on A^T, second solve lam = A^+ w,
+    gradient on A's m*n pattern), with the adjoint residual
+    ||A^T w - dL/dx|| / ||dL/dx|| of the returned dL/db = w."""
+    import torch
+    import paper_2509_19267_amd as rg
+    import workloads
+    from paper_2509_19267_amd import tune
+    prob = workloads.dense_least_squares(m, n, seed=0)
+    ch = tune.lookup("dense", m, n, "fp64") or {}
+    dev = torch.device("cuda", 0)
+    a = torch.as_tensor(prob.a).to(dev)
+    b = torch.as_tensor(prob.b).to(dev)
+    st = torch.cuda.Stream()
+    s = rg.Solver(a, k_col=ch.get("k_col", 0), k_row=ch.get("k_row", 0),
+                  gram_aat=ch.get("gram_aat", False),
+                  inner_tol=ch.get("inner_tol", 0.0),
+                  inner_max=ch.get("inner_max", 0),
+                  tile_rows=ch.get("tile_rows", 0), stop="res_ext", tol=tol,
+                  max_iter=20000, stream=st)
+    c = torch.randn(n, dtype=torch.float64, device=dev)
+    values = a.reshape(-1).detach().requires_grad_(True)
+
+    def fwd():
+        x, info = s.solve(b)
+        torch.cuda.synchronize()
+        return info
+
+    def fwd_bwd():
+        bt = b.clone().requires_grad_(True)
+        x = rg.solve(s, values, bt, least_squares=True)
+        (x * c).sum().backward()
+        torch.cuda.synchronize()
+        return bt.grad
+
+    fwd()
+    fwd_bwd()
+    values.grad = None
+    t0 = time.perf_counter()
+    info = fwd()
+    t_f = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    w = fwd_bwd()
+    t_fb = time.perf_counter() - t0
+    adj = float(torch.linalg.norm(a.t() @ w - c) / torch.linalg.norm(c))
+    out = {"workload": f"dense_least_squares_{m}x{n}", "stop": "res_ext",
+           "tol": tol, "forward_iterations": info["iterations"],
+           "forward_ms": round(1e3 * t_f, 2),
+           "forward_backward_ms": round(1e3 * t_fb, 2),
+           "backward_over_forward": round((t_fb - t_f) / t_f, 3),
+           "adjoint_residual": adj,
+           "grad_A_finite": bool(torch.isfinite(values.grad).all())}
+    s.close()
+    log(f"differentiable: {out}")
     return out
 
 

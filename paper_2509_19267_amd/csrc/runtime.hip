@@ -188,6 +188,11 @@ void set_err(rgdbek_ctx *h, const std::string &m) {
 }
 
 // ------------------------------------------------------------ engine set-up
+// the forward engine of precision T (the adjoint engine shares its Grams)
+template <typename T> Engine<T> &forward_engine(rgdbek_ctx *h);
+template <> Engine<double> &forward_engine<double>(rgdbek_ctx *h) { return h->e64; }
+template <> Engine<float> &forward_engine<float>(rgdbek_ctx *h) { return h->e32; }
+
 template <typename T>
 void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   Pool &P = h->pool;
@@ -225,18 +230,33 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     e.dw.qpart = P.alloc<T>((int64_t)nch * e.m);
     e.dw.gpart = P.alloc<T>((int64_t)nrg * ld);
     // Gram of all columns (A^T A) when the column blocks are large enough to
-    // be worth a gather; rows: A A^T only on request.
-    const bool gram_cols = e.kc > 64 && e.n <= 8192;
-    if (gram_cols) {
-      T *F = P.alloc<T>(e.n * e.n, false);
-      launch_gram_full<T>(cm, ldc, e.n, e.m, F, h->st);
-      e.ata = F;
+    // be worth a gather; rows: A A^T only on request.  The adjoint engine
+    // (A^T) takes the forward engine's Grams with the roles swapped: its
+    // columns are the rows of A.
+    const T *ata = nullptr, *aat = nullptr;
+    if (transpose) {
+      const Engine<T> &f = forward_engine<T>(h);
+      ata = f.aat;
+      aat = f.ata;
     }
-    const bool gram_rows = (h->p.flags & RGDBEK_FLAG_GRAM_AAT) && e.m <= 32768;
+    const bool gram_cols = e.kc > 64 && (ata || e.n <= 8192);
+    if (gram_cols) {
+      if (!ata) {
+        T *F = P.alloc<T>(e.n * e.n, false);
+        launch_gram_full<T>(cm, ldc, e.n, e.m, F, h->st);
+        ata = F;
+      }
+      e.ata = ata;
+    }
+    const bool gram_rows =
+        aat || ((h->p.flags & RGDBEK_FLAG_GRAM_AAT) && e.m <= 32768);
     if (gram_rows) {
-      T *F = P.alloc<T>(e.m * e.m, false);
-      launch_gram_full<T>(rm, ld, e.m, e.n, F, h->st);
-      e.aat = F;
+      if (!aat) {
+        T *F = P.alloc<T>(e.m * e.m, false);
+        launch_gram_full<T>(rm, ld, e.m, e.n, F, h->st);
+        aat = F;
+      }
+      e.aat = aat;
     }
     e.GU = P.alloc<T>(e.kc * e.kc);
     e.GJ = P.alloc<T>(e.kr * e.kr);
