@@ -132,8 +132,13 @@ typedef struct {
  * preconditioned conjugate gradients on the Gram matrix above that. */
 enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
 /* Flags: GRAPH captures the iteration loop into HIP graphs (default on via
- * rgdbek_params_default); GRAM_AAT precomputes A A^T for dense row blocks. */
-enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2 };
+ * rgdbek_params_default); GRAM_AAT precomputes A A^T for dense row blocks;
+ * CG_SPLIT makes the sparse block projections finish every CG step with
+ * separate many-workgroup launches whatever the block size (by default only
+ * blocks of more than 16384 indices do; smaller ones finish in the last
+ * workgroup of the step).  The arithmetic is the same either way. */
+enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2,
+       RGDBEK_FLAG_CG_SPLIT = 4 };
 /* Block rule (rgdbek_params.select_mode). */
 enum { RGDBEK_SELECT_RANDOM = 0, RGDBEK_SELECT_GREEDY = 1,
        RGDBEK_SELECT_BLOCK_LAW = 2, RGDBEK_SELECT_IID = 3 };

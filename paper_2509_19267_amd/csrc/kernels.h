@@ -333,6 +333,9 @@ struct SparseCg {
   T *wide = nullptr;    // wide product (m for columns, n for rows)
   T *p = nullptr, *res = nullptr, *v = nullptr;  // narrow (cap)
   double *part = nullptr;
+  int32_t *pos = nullptr;   // block position of each index, -1 outside
+  double *plong = nullptr;  // one partial per long segment
+  int split = 0;            // many-workgroup step finish at any block size
 };
 template <typename T>
 void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,

@@ -711,12 +711,16 @@ void launch_list_resid(const T *Arm, int64_t ld, int64_t len,
 //         res -= alpha v, zz = res/rho, beta, p = zz + beta p
 constexpr int SC_NT = 256;
 constexpr unsigned SC_MAXB = 512;   // blocks of a launch that ends in a ticket
+// Larger blocks update the CG vectors with separate many-workgroup launches
+// (sc_cupd, sc_rupd1/2) instead of a walk by the last workgroup.
+constexpr int64_t SC_SERIAL_MAX = 16384;
 constexpr int SC_UNROLL = 8;        // loads in flight in one-block list walks
 
 template <typename T, int G>
 __global__ void __launch_bounds__(SC_NT)
 sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
-            double *__restrict__ part, Ctrl *ctrl, int respect_done) {
+            double *__restrict__ part, const double *__restrict__ plong,
+            int64_t nlong, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   if (ld_agent(&ctrl->cg_done[0])) return;
   __shared__ double sh[SC_NT / WAVE];
@@ -730,14 +734,17 @@ sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
     const int64_t slot = slot0 + threadIdx.x / G;
     int64_t s = 0, br = 0, co = 0;
     T acc = 0;
-    if (slot < A.rows) {
+    bool mine = slot < A.rows;
+    if (mine) {
       vrow(A, slot, s, br, co);
       const T *ph = phat + co;
       const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
-      for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * ph[A.idx[e]];
+      if (nlong && e1 - e0 > A.long_limit) mine = false;   // sc_long_wide
+      else
+        for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * ph[A.idx[e]];
     }
     acc = group_sum<G>(acc);
-    if (slot < A.rows && lg == 0) {
+    if (mine && lg == 0) {
       q[s] = acc;
       qq += (double)acc * (double)acc;
     }
@@ -745,9 +752,11 @@ sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
   qq = block_sum<SC_NT>(qq, sh);
   if (threadIdx.x == 0) st_agent(&part[blockIdx.x], qq);
   if (!last_block(&ctrl->ticket[3])) return;
-  double tot = 0.0;
+  double tot = 0.0, tl = 0.0;
   for (int b = threadIdx.x; b < (int)gridDim.x; b += SC_NT) tot += ld_agent(&part[b]);
+  for (int64_t i = threadIdx.x; i < nlong; i += SC_NT) tl += plong[i];
   tot = block_sum<SC_NT>(tot, sh);
+  tot += block_sum<SC_NT>(tl, sh);
   if (threadIdx.x == 0) {
     const double gam = ctrl->cg_rz[0];
     ctrl->cg_alpha[0] = tot > 0.0 ? gam / tot : 0.0;
@@ -763,7 +772,8 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
               const int64_t *__restrict__ cnt, const T *__restrict__ q,
               T *__restrict__ z, int64_t m, T *__restrict__ sres,
               T *__restrict__ p, T *__restrict__ phat,
-              double *__restrict__ part, double tol, Ctrl *ctrl,
+              double *__restrict__ part, const double *__restrict__ plong,
+              int64_t nlong, double tol, int par, Ctrl *ctrl,
               int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   if (ld_agent(&ctrl->cg_done[0])) return;
@@ -783,15 +793,18 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
        a0 += (int64_t)gridDim.x * SPB) {
     const int64_t a = a0 + threadIdx.x / G;
     T acc = 0;
-    if (a < c) {
+    bool mine = a < c;
+    if (mine) {
       int64_t bc, ro;
       gsplit(At, (int64_t)U[a], bc, ro);
       const T *qv = q + ro;
       const int64_t e0 = At.ptr[bc], e1 = At.ptr[bc + 1];
-      for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * qv[At.idx[e]];
+      if (nlong && e1 - e0 > At.long_limit) mine = false;   // sc_long_narrow
+      else
+        for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * qv[At.idx[e]];
     }
     acc = group_sum<G>(acc);
-    if (a < c && lg == 0) {
+    if (mine && lg == 0) {
       const T sv = sres[a] - (T)alpha * acc;
       sres[a] = sv;
       ss += (double)sv * (double)sv;
@@ -800,13 +813,15 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
   ss = block_sum<SC_NT>(ss, sh);
   if (threadIdx.x == 0) st_agent(&part[blockIdx.x], ss);
   if (!last_block(&ctrl->ticket[4])) return;
-  double tot = 0.0;
+  double tot = 0.0, tl = 0.0;
   for (int b = threadIdx.x; b < (int)gridDim.x; b += SC_NT) tot += ld_agent(&part[b]);
+  for (int64_t i = threadIdx.x; i < nlong; i += SC_NT) tl += plong[i];
   tot = block_sum<SC_NT>(tot, sh);
+  tot += block_sum<SC_NT>(tl, sh);
   const double gam = ctrl->cg_rz[0];
   const double beta = gam > 0.0 ? tot / gam : 0.0;
   // one block walks the whole list: keep SC_UNROLL loads in flight
-  for (int64_t k0 = threadIdx.x; k0 < c; k0 += SC_UNROLL * SC_NT) {
+  for (int64_t k0 = threadIdx.x; !par && k0 < c; k0 += SC_UNROLL * SC_NT) {
     T sv[SC_UNROLL], po[SC_UNROLL];
     int32_t ix[SC_UNROLL];
 #pragma unroll
@@ -825,6 +840,7 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
     }
   }
   if (threadIdx.x == 0) {
+    ctrl->cg_beta[0] = beta;
     ctrl->cg_rz[0] = tot;
     ctrl->cg_steps[0] += 1;
     if (tot <= tol * tol * ctrl->cg_rz0[0]) ctrl->cg_done[0] = 1;
@@ -836,8 +852,8 @@ __global__ void __launch_bounds__(SC_NT)
 sc_init(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
         const T *__restrict__ rhs_src, const double *__restrict__ jac,
         T *__restrict__ sres, T *__restrict__ zz_or_null, T *__restrict__ p,
-        T *__restrict__ phat, double *__restrict__ part, Ctrl *ctrl, int ph,
-        int respect_done) {
+        T *__restrict__ phat, int32_t *__restrict__ pos,
+        double *__restrict__ part, Ctrl *ctrl, int ph, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   __shared__ double sh[SC_NT / WAVE];
   const int64_t c = *cnt;
@@ -845,6 +861,7 @@ sc_init(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
   for (int64_t a = (int64_t)blockIdx.x * SC_NT + threadIdx.x; a < c;
        a += (int64_t)gridDim.x * SC_NT) {
     const int64_t l = list[a];
+    if (pos) pos[l] = (int32_t)a;
     const T h = rhs_src[l];
     sres[a] = h;
     T zz = h;
@@ -885,12 +902,165 @@ sc_init(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
 template <typename T>
 __global__ void __launch_bounds__(SC_NT)
 sc_clear(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
-         int64_t cap, T *__restrict__ phat, Ctrl *ctrl, int respect_done) {
+         int64_t cap, T *__restrict__ phat, int32_t *__restrict__ pos,
+         Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   const int64_t c = *cnt;
   for (int64_t a = (int64_t)blockIdx.x * SC_NT + threadIdx.x; a < c;
-       a += (int64_t)gridDim.x * SC_NT)
+       a += (int64_t)gridDim.x * SC_NT) {
     phat[list[a]] = (T)0;
+    if (pos) pos[list[a]] = -1;
+  }
+}
+
+// Many-workgroup finish of a CG step for large blocks (SC_SERIAL_MAX).  Each
+// runs only when the narrow kernel of the same step completed (the step
+// counter equals step + 1), so steps after convergence stay no-ops.
+template <typename T>
+__global__ void __launch_bounds__(SC_NT)
+sc_cupd(const int32_t *__restrict__ U, const int64_t *__restrict__ cnt,
+        const T *__restrict__ sres, T *__restrict__ p, T *__restrict__ phat,
+        Ctrl *ctrl, int step, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ctrl->cg_steps[0] != step + 1) return;
+  const double beta = ctrl->cg_beta[0];
+  const int64_t c = *cnt;
+  for (int64_t a = (int64_t)blockIdx.x * SC_NT + threadIdx.x; a < c;
+       a += (int64_t)gridDim.x * SC_NT) {
+    const T pv = sres[a] + (T)beta * p[a];
+    p[a] = pv;
+    phat[U[a]] = pv;
+  }
+}
+
+// rows: res -= alpha v, zz = res / rho, partials of <res, zz> and ||res||^2;
+// the last block forms beta and the stopping test
+template <typename T>
+__global__ void __launch_bounds__(SC_NT)
+sc_rupd1(const int32_t *__restrict__ J, const int64_t *__restrict__ cnt,
+         const double *__restrict__ rho, T *__restrict__ res,
+         T *__restrict__ zz, const T *__restrict__ v,
+         double *__restrict__ part, double tol, Ctrl *ctrl, int step,
+         int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ctrl->cg_steps[1] != step + 1) return;
+  __shared__ double sh[SC_NT / WAVE];
+  const double alpha = ctrl->cg_alpha[1];
+  const int64_t c = *cnt;
+  double rz1 = 0.0, rr = 0.0;
+  for (int64_t a = (int64_t)blockIdx.x * SC_NT + threadIdx.x; a < c;
+       a += (int64_t)gridDim.x * SC_NT) {
+    const T r = res[a] - (T)alpha * v[a];
+    res[a] = r;
+    const double dj = rho[J[a]];
+    const T zv = dj > 0.0 ? (T)((double)r / dj) : (T)0;
+    zz[a] = zv;
+    rz1 += (double)r * (double)zv;
+    rr += (double)r * (double)r;
+  }
+  rz1 = block_sum<SC_NT>(rz1, sh);
+  rr = block_sum<SC_NT>(rr, sh);
+  if (threadIdx.x == 0) {
+    st_agent(&part[2 * blockIdx.x], rz1);
+    st_agent(&part[2 * blockIdx.x + 1], rr);
+  }
+  if (!last_block(&ctrl->ticket[7])) return;
+  rz1 = 0.0;
+  rr = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += SC_NT) {
+    rz1 += ld_agent(&part[2 * b]);
+    rr += ld_agent(&part[2 * b + 1]);
+  }
+  rz1 = block_sum<SC_NT>(rz1, sh);
+  rr = block_sum<SC_NT>(rr, sh);
+  if (threadIdx.x == 0) {
+    const double rz = ctrl->cg_rz[1];
+    ctrl->cg_beta[1] = rz != 0.0 ? rz1 / rz : 0.0;
+    ctrl->cg_rz[1] = rz1;
+    if (rr <= tol * tol * ctrl->cg_rz0[1]) ctrl->cg_done[1] = 1;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SC_NT)
+sc_rupd2(const int32_t *__restrict__ J, const int64_t *__restrict__ cnt,
+         const T *__restrict__ zz, T *__restrict__ p, T *__restrict__ phat,
+         Ctrl *ctrl, int step, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ctrl->cg_steps[1] != step + 1) return;
+  const double beta = ctrl->cg_beta[1];
+  const int64_t c = *cnt;
+  for (int64_t a = (int64_t)blockIdx.x * SC_NT + threadIdx.x; a < c;
+       a += (int64_t)gridDim.x * SC_NT) {
+    const T pn = zz[a] + (T)beta * p[a];
+    p[a] = pn;
+    phat[J[a]] = pn;
+  }
+}
+
+// Long segments of the CG products (one replica of A, rep == 1): one
+// workgroup each, so that a few power-law rows do not hold up the launch
+// that walks all the short ones with G lanes per segment.  The main kernels
+// skip every segment longer than the limit the long lists were built with.
+// Wide products take every long segment (A.longs); listed products only
+// the long segments whose position in the block list is recorded in pos
+// (-1: not in the block).  Each workgroup writes its result and one
+// partial (q^2 for columns' wide product, s^2 or <p, v> for the listed
+// ones) that the main kernel's last block adds in index order.
+template <typename T>
+__global__ void __launch_bounds__(SC_NT)
+sc_long_wide(Csr<T> A, const T *__restrict__ phat, T *__restrict__ out,
+             T *__restrict__ x, double *__restrict__ plong, Ctrl *ctrl,
+             int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[ph])) return;
+  __shared__ double sh[SC_NT / WAVE];
+  const int64_t r = A.longs[blockIdx.x];
+  const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
+  T acc = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += SC_NT)
+    acc += A.val[e] * phat[A.idx[e]];
+  const T sv = (T)block_sum<SC_NT>((double)acc, sh);
+  if (threadIdx.x == 0) {
+    if (x) {   // rows: this column's pending x += alpha_prev u_prev first
+      const double alpha = ctrl->cg_alpha[ph];
+      if (alpha != 0.0) x[r] += (T)alpha * out[r];
+    }
+    out[r] = sv;
+    plong[blockIdx.x] = (double)sv * (double)sv;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SC_NT)
+sc_long_narrow(Csr<T> A, const int32_t *__restrict__ pos,
+               const T *__restrict__ vec, T *__restrict__ dst,
+               const T *__restrict__ p, double *__restrict__ plong,
+               Ctrl *ctrl, int ph, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[ph])) return;
+  __shared__ double sh[SC_NT / WAVE];
+  const int64_t r = A.longs[blockIdx.x];
+  const int32_t a = pos[r];
+  if (a < 0) {
+    if (threadIdx.x == 0) plong[blockIdx.x] = 0.0;
+    return;
+  }
+  const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
+  T acc = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += SC_NT)
+    acc += A.val[e] * vec[A.idx[e]];
+  const T w = (T)block_sum<SC_NT>((double)acc, sh);
+  if (threadIdx.x == 0) {
+    if (ph == 0) {   // columns: s_a -= alpha w
+      const T sv = dst[a] - (T)ctrl->cg_alpha[0] * w;
+      dst[a] = sv;
+      plong[blockIdx.x] = (double)sv * (double)sv;
+    } else {         // rows: v_a = w
+      dst[a] = w;
+      plong[blockIdx.x] = (double)w * (double)p[a];
+    }
+  }
 }
 
 // rows: wide product u = A^T phat over CSC columns, with the pending update
@@ -898,7 +1068,7 @@ sc_clear(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
 template <typename T, int G>
 __global__ void __launch_bounds__(SC_NT)
 sc_wide_row(Csr<T> At, const T *__restrict__ phat, T *__restrict__ u,
-            T *__restrict__ x, Ctrl *ctrl, int respect_done) {
+            T *__restrict__ x, int64_t nlong, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   if (ld_agent(&ctrl->cg_done[1])) return;
   const double alpha = ctrl->cg_alpha[1];
@@ -907,14 +1077,17 @@ sc_wide_row(Csr<T> At, const T *__restrict__ phat, T *__restrict__ u,
   const int64_t slot = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
   int64_t s = 0, br = 0, co = 0;
   T acc = 0;
-  if (slot < At.rows) {
+  bool mine = slot < At.rows;
+  if (mine) {
     vrow(At, slot, s, br, co);
     const T *ph = phat + co;
     const int64_t e0 = At.ptr[br], e1 = At.ptr[br + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * ph[At.idx[e]];
+    if (nlong && e1 - e0 > At.long_limit) mine = false;   // sc_long_wide
+    else
+      for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * ph[At.idx[e]];
   }
   acc = group_sum<G>(acc);
-  if (slot < At.rows && lg == 0) {
+  if (mine && lg == 0) {
     if (alpha != 0.0) x[s] += (T)alpha * u[s];
     u[s] = acc;
   }
@@ -926,8 +1099,9 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
               const int64_t *__restrict__ cnt, const T *__restrict__ u,
               const double *__restrict__ rho, T *__restrict__ res,
               T *__restrict__ zz, T *__restrict__ p, T *__restrict__ v,
-              T *__restrict__ phat, double *__restrict__ part, double tol,
-              Ctrl *ctrl, int respect_done) {
+              T *__restrict__ phat, double *__restrict__ part,
+              const double *__restrict__ plong, int64_t nlong, double tol,
+              int par, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   if (ld_agent(&ctrl->cg_done[1])) return;
   __shared__ double sh[SC_NT / WAVE];
@@ -939,15 +1113,18 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
        a0 += (int64_t)gridDim.x * SPB) {
     const int64_t a = a0 + threadIdx.x / G;
     T acc = 0;
-    if (a < c) {
+    bool mine = a < c;
+    if (mine) {
       int64_t brw, co;
       gsplit(A, (int64_t)J[a], brw, co);
       const T *uv = u + co;
       const int64_t e0 = A.ptr[brw], e1 = A.ptr[brw + 1];
-      for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * uv[A.idx[e]];
+      if (nlong && e1 - e0 > A.long_limit) mine = false;   // sc_long_narrow
+      else
+        for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * uv[A.idx[e]];
     }
     acc = group_sum<G>(acc);
-    if (a < c && lg == 0) {
+    if (mine && lg == 0) {
       v[a] = acc;
       pv += (double)acc * (double)p[a];
     }
@@ -955,11 +1132,21 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
   pv = block_sum<SC_NT>(pv, sh);
   if (threadIdx.x == 0) st_agent(&part[blockIdx.x], pv);
   if (!last_block(&ctrl->ticket[5])) return;
-  double tot = 0.0;
+  double tot = 0.0, tl = 0.0;
   for (int b = threadIdx.x; b < (int)gridDim.x; b += SC_NT) tot += ld_agent(&part[b]);
+  for (int64_t i = threadIdx.x; i < nlong; i += SC_NT) tl += plong[i];
   tot = block_sum<SC_NT>(tot, sh);
+  tot += block_sum<SC_NT>(tl, sh);
   const double rz = ctrl->cg_rz[1];
   const double alpha = tot != 0.0 ? rz / tot : 0.0;
+  if (par) {   // sc_rupd1 and sc_rupd2 finish the step
+    if (threadIdx.x == 0) {
+      ctrl->cg_alpha[1] = alpha;
+      ctrl->cg_steps[1] += 1;
+      if (tot == 0.0) ctrl->cg_done[1] = 1;
+    }
+    return;
+  }
   double rz1 = 0.0, rr = 0.0;
   // one block walks the whole list: keep SC_UNROLL loads in flight
   for (int64_t k0 = threadIdx.x; k0 < c; k0 += SC_UNROLL * SC_NT) {
@@ -1051,25 +1238,46 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
                            int64_t cap, const T *g, T *z, SparseCg<T> &w,
                            int max_steps, double tol, Ctrl *ctrl,
                            int respect_done, hipStream_t st) {
+  // long segments apart only for one replica of A (the lists are built
+  // for it); a replicated operator walks every segment with G lanes
+  const int64_t nlw = csr.rep == 1 && w.pos ? csr.nlong : 0;
+  const int64_t nln = csc.rep == 1 && w.pos ? csc.nlong : 0;
   hipLaunchKernelGGL(sc_init<T>, dim3(sc_init_blocks(cap)), dim3(SC_NT), 0, st,
                      U, count_dev, g, (const double *)nullptr, w.res,
-                     (T *)nullptr, w.p, w.phat, w.part, ctrl, 0, respect_done);
+                     (T *)nullptr, w.p, w.phat, nln ? w.pos : (int32_t *)nullptr,
+                     w.part, ctrl, 0, respect_done);
   const unsigned nbw = std::min<unsigned>(seg_blocks<T>(csr.rows, csr.group), SC_MAXB);
   unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csc.group), SC_MAXB);
   if (nbn < 64) nbn = 64;
+  const int par = (w.split || cap > SC_SERIAL_MAX) ? 1 : 0;
+  const unsigned nbu = std::min<unsigned>(
+      (unsigned)((cap + SC_NT - 1) / SC_NT), SC_MAXB);
   for (int s = 0; s < max_steps; ++s) {
+    if (nlw)
+      hipLaunchKernelGGL(sc_long_wide<T>, dim3((unsigned)nlw), dim3(SC_NT), 0,
+                         st, csr, w.phat, w.wide, (T *)nullptr, w.plong, ctrl,
+                         0, respect_done);
     RG_SWITCH_G(csr.group, hipLaunchKernelGGL((sc_wide_col<T, GG>), dim3(nbw),
                                               dim3(SC_NT), 0, st, csr, w.phat,
-                                              w.wide, w.part, ctrl,
-                                              respect_done));
+                                              w.wide, w.part, w.plong, nlw,
+                                              ctrl, respect_done));
+    if (nln)
+      hipLaunchKernelGGL(sc_long_narrow<T>, dim3((unsigned)nln), dim3(SC_NT),
+                         0, st, csc, w.pos, w.wide, w.res, w.p, w.plong, ctrl,
+                         0, respect_done);
     RG_SWITCH_G(csc.group,
                 hipLaunchKernelGGL((sc_narrow_col<T, GG>), dim3(nbn),
                                    dim3(SC_NT), 0, st, csc, U, count_dev,
                                    w.wide, z, csr.rows, w.res, w.p, w.phat,
-                                   w.part, tol, ctrl, respect_done));
+                                   w.part, w.plong, nln, tol, par, ctrl,
+                                   respect_done));
+    if (par)
+      hipLaunchKernelGGL(sc_cupd<T>, dim3(nbu), dim3(SC_NT), 0, st, U,
+                         count_dev, w.res, w.p, w.phat, ctrl, s, respect_done);
   }
   hipLaunchKernelGGL(sc_clear<T>, dim3(64), dim3(SC_NT), 0, st, U, count_dev,
-                     cap, w.phat, ctrl, respect_done);
+                     cap, w.phat, nln ? w.pos : (int32_t *)nullptr, ctrl,
+                     respect_done);
 }
 
 template <typename T>
@@ -1078,28 +1286,51 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                            int64_t cap, const T *r, const double *rho, T *x,
                            SparseCg<T> &w, int max_steps, double tol,
                            Ctrl *ctrl, int respect_done, hipStream_t st) {
+  const int64_t nlw = csc.rep == 1 && w.pos ? csc.nlong : 0;
+  const int64_t nln = csr.rep == 1 && w.pos ? csr.nlong : 0;
   hipLaunchKernelGGL(sc_init<T>, dim3(sc_init_blocks(cap)), dim3(SC_NT), 0, st,
-                     J, count_dev, r, rho, w.res, w.v, w.p, w.phat, w.part,
-                     ctrl, 1, respect_done);
+                     J, count_dev, r, rho, w.res, w.v, w.p, w.phat,
+                     nln ? w.pos : (int32_t *)nullptr, w.part, ctrl, 1,
+                     respect_done);
   // w.v doubles as the Jacobi-scaled residual buffer zz during steps
   const unsigned nbw = seg_blocks<T>(csc.rows, csc.group);
   const unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csr.group), SC_MAXB);
+  const int par = (w.split || cap > SC_SERIAL_MAX) ? 1 : 0;
+  const unsigned nbu = std::min<unsigned>(
+      (unsigned)((cap + SC_NT - 1) / SC_NT), SC_MAXB);
   for (int s = 0; s < max_steps; ++s) {
+    if (nlw)
+      hipLaunchKernelGGL(sc_long_wide<T>, dim3((unsigned)nlw), dim3(SC_NT), 0,
+                         st, csc, w.phat, w.wide, x, w.plong, ctrl, 1,
+                         respect_done);
     RG_SWITCH_G(csc.group, hipLaunchKernelGGL((sc_wide_row<T, GG>), dim3(nbw),
                                               dim3(SC_NT), 0, st, csc, w.phat,
-                                              w.wide, x, ctrl, respect_done));
+                                              w.wide, x, nlw, ctrl,
+                                              respect_done));
+    if (nln)
+      hipLaunchKernelGGL(sc_long_narrow<T>, dim3((unsigned)nln), dim3(SC_NT),
+                         0, st, csr, w.pos, w.wide, w.v + cap, w.p, w.plong,
+                         ctrl, 1, respect_done);
     RG_SWITCH_G(csr.group,
                 hipLaunchKernelGGL((sc_narrow_row<T, GG>), dim3(nbn),
                                    dim3(SC_NT), 0, st, csr, J, count_dev,
                                    w.wide, rho, w.res, w.v, w.p,
-                                   w.v + cap, w.phat, w.part, tol, ctrl,
-                                   respect_done));
+                                   w.v + cap, w.phat, w.part, w.plong, nln,
+                                   tol, par, ctrl, respect_done));
+    if (par) {
+      hipLaunchKernelGGL(sc_rupd1<T>, dim3(nbu), dim3(SC_NT), 0, st, J,
+                         count_dev, rho, w.res, w.v, w.v + cap, w.part, tol,
+                         ctrl, s, respect_done);
+      hipLaunchKernelGGL(sc_rupd2<T>, dim3(nbu), dim3(SC_NT), 0, st, J,
+                         count_dev, w.v, w.p, w.phat, ctrl, s, respect_done);
+    }
   }
   hipLaunchKernelGGL(sc_row_finish<T>, dim3((unsigned)((csc.rows + SC_NT - 1) / SC_NT)),
                      dim3(SC_NT), 0, st, csc.rows, w.wide, x, ctrl,
                      respect_done);
   hipLaunchKernelGGL(sc_clear<T>, dim3(64), dim3(SC_NT), 0, st, J, count_dev,
-                     cap, w.phat, ctrl, respect_done);
+                     cap, w.phat, nln ? w.pos : (int32_t *)nullptr, ctrl,
+                     respect_done);
 }
 
 // ------------------------------------------------------------ instantiate

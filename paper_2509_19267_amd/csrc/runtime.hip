@@ -344,6 +344,14 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       sc.v = P.alloc<T>(2 * cap);
       const int64_t nb = std::max(e.m, e.n) / 4 + cap / 4 + 1024;
       sc.part = P.alloc<double>(nb);
+      sc.split = (h->p.flags & RGDBEK_FLAG_CG_SPLIT) ? 1 : 0;
+      // long segments (one replica of A): block positions, -1 outside
+      if (h->rep == 1 && (a.nlong || at.nlong)) {
+        const int64_t d = ph == 0 ? e.n : e.m;
+        sc.pos = P.alloc<int32_t>(d, false);
+        HIPCHK(hipMemsetAsync(sc.pos, 0xff, sizeof(int32_t) * d, h->st));
+        sc.plong = P.alloc<double>(std::max(a.nlong, at.nlong) + 64);
+      }
     }
   }
   e.rho = transpose ? h->kappa : h->rho;

@@ -39,7 +39,8 @@ class Solver:
                  k_row=0, tol=1e-8, stop="err_ref", max_iter=10000, seed=0,
                  precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
                  solver=B.SOLVER_AUTO, graph=True, gram_aat=False,
-                 weight_floor=0.0, tile_rows=0, select="random", stream=None):
+                 weight_floor=0.0, tile_rows=0, select="random",
+                 cg_split=False, stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -81,7 +82,9 @@ class Solver:
         p.select_mode = {"random": B.SELECT_RANDOM, "greedy": B.SELECT_GREEDY,
                          "block_law": B.SELECT_BLOCK_LAW,
                          "iid": B.SELECT_IID}[select]
-        p.flags = (B.FLAG_GRAPH if graph else 0) | (B.FLAG_GRAM_AAT if gram_aat else 0)
+        p.flags = ((B.FLAG_GRAPH if graph else 0) |
+                   (B.FLAG_GRAM_AAT if gram_aat else 0) |
+                   (B.FLAG_CG_SPLIT if cg_split else 0))
         self.m, self.n = int(m), int(n)
         self.params = p
         self.stream = stream

@@ -791,3 +791,23 @@ def test_iid_table_iteration_counts(rg):
             its.append(info["iterations"])
         print(f"iid {m}x{n}: {its} paper {ref}", flush=True)
         assert abs(np.mean(its) - ref) <= 0.1 * ref
+
+
+# ------------------------------------------------ sparse CG step variants
+@pytest.mark.parametrize("kind", ["uniform", "powerlaw"])
+def test_sparse_split_cg_finish(rg, kind):
+    # the many-workgroup CG step finish (taken by blocks above 16384
+    # indices) forced on blocks the oracle can check; the power-law matrix
+    # has rows above the long-segment limit in both CG products
+    if kind == "uniform":
+        p = workloads.sparse_uniform(3000, 1500, density=0.01, seed=3)
+        kc, kr, imax = 150, 300, 200
+    else:
+        p = workloads.sparse_powerlaw(6000, 3000, mean_len=10, max_len=400,
+                                      seed=4)
+        kc, kr, imax = 300, 600, 1000
+    x, z, info, xo, zo = run_both(rg, p, kc, kr, 3, sparse=True,
+                                  inner_max=imax, cg_split=True)
+    print(f"split cg {kind}: rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+    assert rel(x, xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
