@@ -711,6 +711,7 @@ void launch_list_resid(const T *Arm, int64_t ld, int64_t len,
 //         res -= alpha v, zz = res/rho, beta, p = zz + beta p
 constexpr int SC_NT = 256;
 constexpr unsigned SC_MAXB = 512;   // blocks of a launch that ends in a ticket
+constexpr unsigned SC_WIDE_MAXB = 1024;  // blocks of the columns' wide product
 // Larger blocks update the CG vectors with separate many-workgroup launches
 // (sc_cupd, sc_rupd1/2) instead of a walk by the last workgroup.
 constexpr int64_t SC_SERIAL_MAX = 16384;
@@ -1246,7 +1247,7 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
                      U, count_dev, g, (const double *)nullptr, w.res,
                      (T *)nullptr, w.p, w.phat, nln ? w.pos : (int32_t *)nullptr,
                      w.part, ctrl, 0, respect_done);
-  const unsigned nbw = std::min<unsigned>(seg_blocks<T>(csr.rows, csr.group), SC_MAXB);
+  const unsigned nbw = std::min<unsigned>(seg_blocks<T>(csr.rows, csr.group), SC_WIDE_MAXB);
   unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csc.group), SC_MAXB);
   if (nbn < 64) nbn = 64;
   const int par = (w.split || cap > SC_SERIAL_MAX) ? 1 : 0;
