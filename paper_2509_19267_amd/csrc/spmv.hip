@@ -315,12 +315,16 @@ template <> struct Vec<double> { using type = df_d2; static constexpr int n = 2;
 template <> struct Vec<float> { using type = df_f4; static constexpr int n = 4; };
 
 constexpr int DF_NT = 256;     // 4 waves
-constexpr int DF_NL = 4;       // 16-byte loads per lane per row
-constexpr int DF_RG = 4;       // rows in flight per wave
-constexpr int DF_RSTEP = (DF_NT / WAVE) * DF_RG;   // rows per workgroup sweep
+// 16-byte loads per lane per row (NL) and rows in flight per wave (RG)
+template <typename T> struct DfShape;
+template <> struct DfShape<double> { static constexpr int NL = 4, RG = 4; };
+template <> struct DfShape<float> { static constexpr int NL = 4, RG = 4; };
+// rows per workgroup sweep
+template <typename T>
+constexpr int df_rstep() { return (DF_NT / WAVE) * DfShape<T>::RG; }
 
 template <typename T>
-constexpr int df_cb() { return WAVE * Vec<T>::n * DF_NL; }
+constexpr int df_cb() { return WAVE * Vec<T>::n * DfShape<T>::NL; }
 
 // Work split of the fused pass: column chunks of df_cb() columns (one per
 // grid column) times row tiles of `rpw` rows (one per grid row).  With
@@ -340,8 +344,9 @@ void dense_work_shape(const Dense<T> &A, int tile_rows, int target_wgs,
     if (want < 1) want = 1;
     r = (A.rows + want - 1) / want;
   }
-  r = (r + DF_RSTEP - 1) / DF_RSTEP * DF_RSTEP;
-  if (r < DF_RSTEP) r = DF_RSTEP;
+  constexpr int64_t RS = df_rstep<T>();
+  r = (r + RS - 1) / RS * RS;
+  if (r < RS) r = RS;
   *rpw = (int)r;
   *nrg = (int)((A.rows + r - 1) / r);
   if (*nrg < 1) *nrg = 1;
@@ -370,6 +375,8 @@ dense_fused_kernel(Dense<T> A, int rpw, const T *__restrict__ x,
   using V = typename Vec<T>::type;
   constexpr int VN = Vec<T>::n;
   constexpr int CB = df_cb<T>();
+  constexpr int DF_NL = DfShape<T>::NL, DF_RG = DfShape<T>::RG;
+  constexpr int DF_RSTEP = df_rstep<T>();
   __shared__ T sg[DF_NT / WAVE][CB];
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const int64_t c0 = (int64_t)blockIdx.x * CB;
