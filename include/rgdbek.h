@@ -136,9 +136,13 @@ enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
  * CG_SPLIT makes the sparse block projections finish every CG step with
  * separate many-workgroup launches whatever the block size (by default only
  * blocks of more than 16384 indices do; smaller ones finish in the last
- * workgroup of the step).  The arithmetic is the same either way. */
+ * workgroup of the step).  The arithmetic is the same either way.
+ * SPARSE_CG keeps the matrix-free CG projections for small sparse single
+ * systems (both dimensions up to 4096), which by default go through Gram
+ * matrices of all columns and rows formed once at create (as dense matrices
+ * do). */
 enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2,
-       RGDBEK_FLAG_CG_SPLIT = 4 };
+       RGDBEK_FLAG_CG_SPLIT = 4, RGDBEK_FLAG_SPARSE_CG = 8 };
 /* Block rule (rgdbek_params.select_mode). */
 enum { RGDBEK_SELECT_RANDOM = 0, RGDBEK_SELECT_GREEDY = 1,
        RGDBEK_SELECT_BLOCK_LAW = 2, RGDBEK_SELECT_IID = 3 };

@@ -18,7 +18,7 @@ F64, F32 = 0, 1
 STOP_NONE, STOP_ERR_REF, STOP_RSE, STOP_RES_EXT = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED_F32, PREC_MIXED_BF16 = 0, 1, 2
 SOLVER_AUTO, SOLVER_CHOL, SOLVER_CG = 0, 1, 2
-FLAG_GRAPH, FLAG_GRAM_AAT, FLAG_CG_SPLIT = 1, 2, 4
+FLAG_GRAPH, FLAG_GRAM_AAT, FLAG_CG_SPLIT, FLAG_SPARSE_CG = 1, 2, 4, 8
 SELECT_RANDOM, SELECT_GREEDY, SELECT_BLOCK_LAW, SELECT_IID = 0, 1, 2, 3
 
 STOP_NAMES = {"none": STOP_NONE, "err_ref": STOP_ERR_REF, "rse": STOP_RSE,

@@ -337,6 +337,18 @@ struct SparseCg {
   double *plong = nullptr;  // one partial per long segment
   int split = 0;            // many-workgroup step finish at any block size
 };
+// Small sparse systems (both dimensions up to SPARSE_GRAM_MAX): dense
+// copies for the Gram matrices, and the block update out += sign A_L coef
+// (A_L the listed columns of A, as rows of the CSR view given).
+constexpr int64_t SPARSE_GRAM_MAX = 4096;
+template <typename T>
+void launch_densify(const Csr<T> &A, T *rm, int64_t ld, T *cm, int64_t ldc,
+                    hipStream_t st);
+template <typename T>
+void launch_sparse_block_update(const Csr<T> &A, const int32_t *list,
+                                const int64_t *count_dev, int64_t cap,
+                                const T *coef, int sign, T *phat, T *out,
+                                Ctrl *ctrl, int respect_done, hipStream_t st);
 template <typename T>
 void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
                            const int32_t *U, const int64_t *count_dev,

@@ -1334,6 +1334,80 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                      respect_done);
 }
 
+// ------------------------------------------------------------ small sparse
+// Dense row- and column-major copies of a sparse A (one thread per row,
+// repeated entries summed in storage order; the buffers come zeroed).
+template <typename T>
+__global__ void __launch_bounds__(256)
+densify_kernel(Csr<T> A, T *__restrict__ rm, int64_t ld, T *__restrict__ cm,
+               int64_t ldc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.rows) return;
+  for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+    const int64_t j = A.idx[e];
+    rm[i * ld + j] += A.val[e];
+    cm[j * ldc + i] += A.val[e];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+list_scatter(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
+             const T *__restrict__ coef, T *__restrict__ dst, Ctrl *ctrl,
+             int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t c = *cnt;
+  for (int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x; a < c;
+       a += (int64_t)gridDim.x * 256)
+    dst[list[a]] = coef[a];
+}
+
+// out_i += sign * sum_e A_ie phat_(idx e), one thread per row of the view
+// (small systems only), in storage order
+template <typename T>
+__global__ void __launch_bounds__(256)
+rows_axpy(Csr<T> A, const T *__restrict__ phat, int sign, T *__restrict__ out,
+          Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.rows) return;
+  T acc = 0;
+  bool any = false;
+  for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+    const T v = phat[A.idx[e]];
+    if (v != (T)0) {
+      acc += A.val[e] * v;
+      any = true;
+    }
+  }
+  if (any) out[i] += sign > 0 ? acc : -acc;
+}
+
+template <typename T>
+void launch_densify(const Csr<T> &A, T *rm, int64_t ld, T *cm, int64_t ldc,
+                    hipStream_t st) {
+  const unsigned nb = (unsigned)((A.rows + 255) / 256);
+  hipLaunchKernelGGL(densify_kernel<T>, dim3(nb > 0 ? nb : 1), dim3(256), 0, st,
+                     A, rm, ld, cm, ldc);
+}
+
+template <typename T>
+void launch_sparse_block_update(const Csr<T> &A, const int32_t *list,
+                                const int64_t *count_dev, int64_t cap,
+                                const T *coef, int sign, T *phat, T *out,
+                                Ctrl *ctrl, int respect_done, hipStream_t st) {
+  const unsigned nl = (unsigned)std::max<int64_t>(1, std::min<int64_t>(
+      (cap + 255) / 256, 256));
+  hipLaunchKernelGGL(list_scatter<T>, dim3(nl), dim3(256), 0, st, list,
+                     count_dev, coef, phat, ctrl, respect_done);
+  const unsigned nr = (unsigned)((A.rows + 255) / 256);
+  hipLaunchKernelGGL(rows_axpy<T>, dim3(nr > 0 ? nr : 1), dim3(256), 0, st, A,
+                     phat, sign, out, ctrl, respect_done);
+  hipLaunchKernelGGL(sc_clear<T>, dim3(64), dim3(SC_NT), 0, st, list,
+                     count_dev, cap, phat, (int32_t *)nullptr, ctrl,
+                     respect_done);
+}
+
 // ------------------------------------------------------------ instantiate
 #define RG_INST(T)                                                            \
   template void launch_gram_gather<T>(const T *, int64_t, const int32_t *,   \
@@ -1383,6 +1457,16 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                                          Ctrl *, int, hipStream_t);
 RG_INST(double)
 RG_INST(float)
+template void launch_densify<double>(const Csr<double> &, double *, int64_t,
+                                     double *, int64_t, hipStream_t);
+template void launch_densify<float>(const Csr<float> &, float *, int64_t,
+                                    float *, int64_t, hipStream_t);
+template void launch_sparse_block_update<double>(
+    const Csr<double> &, const int32_t *, const int64_t *, int64_t,
+    const double *, int, double *, double *, Ctrl *, int, hipStream_t);
+template void launch_sparse_block_update<float>(
+    const Csr<float> &, const int32_t *, const int64_t *, int64_t,
+    const float *, int, float *, float *, Ctrl *, int, hipStream_t);
 #undef RG_INST
 
 }  // namespace rg

@@ -89,6 +89,7 @@ struct Engine {
   Dense<T> arm, acm;          // row-major A (ld), column-major A (ldc)
   Csr<T> csr, csc;
   const T *ata = nullptr, *aat = nullptr;  // precomputed Grams (nullable)
+  bool sgram = false;         // sparse A projected through the Grams
   const double *rho = nullptr, *kappa = nullptr;
   // vectors
   T *x = nullptr, *z = nullptr, *b = nullptr, *q = nullptr, *g = nullptr;
@@ -193,6 +194,32 @@ template <typename T> Engine<T> &forward_engine(rgdbek_ctx *h);
 template <> Engine<double> &forward_engine<double>(rgdbek_ctx *h) { return h->e64; }
 template <> Engine<float> &forward_engine<float>(rgdbek_ctx *h) { return h->e32; }
 
+// Gram-block solve work (dense engines, and sparse engines small enough for
+// the Gram matrices of all columns and rows).
+template <typename T>
+void alloc_gram_blocks(rgdbek_ctx *h, Engine<T> &e) {
+  Pool &P = h->pool;
+  e.GU = P.alloc<T>(e.kc * e.kc);
+  e.GJ = P.alloc<T>(e.kr * e.kr);
+  e.y = P.alloc<T>(e.kc);
+  e.w = P.alloc<T>(e.kr);
+  e.s = P.alloc<T>(e.kr);
+  for (CgWork<T> *cw : {&e.cgc, &e.cgr}) {
+    const int64_t cap = (cw == &e.cgc) ? e.kc : e.kr;
+    cw->cap = cap;
+    cw->res = P.alloc<T>(cap);
+    cw->p = P.alloc<T>(2 * cap);
+    cw->v = P.alloc<T>(cap);
+    cw->zz = P.alloc<T>(cap);
+    cw->pv = P.alloc<double>(cap / 4 + 64);
+    cw->part_cap = cap / 256 + 2;
+    cw->part = P.alloc<double>(4 * cw->part_cap);
+    cw->rzs = P.alloc<double>(2);
+    cw->v2 = P.alloc<T>(2 * cap);
+    cw->pv2 = P.alloc<double>(2 * pcg_persist_grid(cap, h->ncu));
+  }
+}
+
 template <typename T>
 void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   Pool &P = h->pool;
@@ -258,27 +285,9 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       }
       e.aat = aat;
     }
-    e.GU = P.alloc<T>(e.kc * e.kc);
-    e.GJ = P.alloc<T>(e.kr * e.kr);
-    e.y = P.alloc<T>(e.kc);
-    e.w = P.alloc<T>(e.kr);
-    e.s = P.alloc<T>(e.kr);
+    alloc_gram_blocks(h, e);
     e.upd = P.alloc<T>(std::max(thin_update_scratch(e.m, e.kc),
                                 thin_update_scratch(e.n, e.kr)));
-    for (CgWork<T> *cw : {&e.cgc, &e.cgr}) {
-      const int64_t cap = (cw == &e.cgc) ? e.kc : e.kr;
-      cw->cap = cap;
-      cw->res = P.alloc<T>(cap);
-      cw->p = P.alloc<T>(2 * cap);
-      cw->v = P.alloc<T>(cap);
-      cw->zz = P.alloc<T>(cap);
-      cw->pv = P.alloc<double>(cap / 4 + 64);
-      cw->part_cap = cap / 256 + 2;
-      cw->part = P.alloc<double>(4 * cw->part_cap);
-      cw->rzs = P.alloc<double>(2);
-      cw->v2 = P.alloc<T>(2 * cap);
-      cw->pv2 = P.alloc<double>(2 * pcg_persist_grid(cap, h->ncu));
-    }
   } else {
     // CSR / CSC views; the adjoint swaps them
     Csr<T> a, at;
@@ -352,6 +361,25 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
         HIPCHK(hipMemsetAsync(sc.pos, 0xff, sizeof(int32_t) * d, h->st));
         sc.plong = P.alloc<double>(std::max(a.nlong, at.nlong) + 64);
       }
+    }
+    // Small single systems: the Gram matrices of all columns and all rows,
+    // formed once through a dense copy, turn each block projection into a
+    // gather, one Cholesky or persistent PCG launch and one sparse update,
+    // instead of two launches per CG step.
+    if (!(h->p.flags & RGDBEK_FLAG_SPARSE_CG) && h->rep == 1 && h->nseg == 0 &&
+        e.m <= SPARSE_GRAM_MAX && e.n <= SPARSE_GRAM_MAX) {
+      const int64_t ld = round_up(e.n, 8), ldc = round_up(e.m, 8);
+      T *rm = P.alloc<T>(e.m * ld);
+      T *cm = P.alloc<T>(e.n * ldc);
+      launch_densify<T>(a, rm, ld, cm, ldc, h->st);
+      T *F1 = P.alloc<T>(e.n * e.n, false);
+      launch_gram_full<T>(cm, ldc, e.n, e.m, F1, h->st);
+      T *F2 = P.alloc<T>(e.m * e.m, false);
+      launch_gram_full<T>(rm, ld, e.m, e.n, F2, h->st);
+      e.ata = F1;
+      e.aat = F2;
+      alloc_gram_blocks(h, e);
+      e.sgram = true;
     }
   }
   e.rho = transpose ? h->kappa : h->rho;
@@ -509,6 +537,14 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     }
     launch_col_update<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.y, e.z,
                          e.upd, c, 1, st);
+  } else if (e.sgram) {
+    launch_gram_gather<T>(e.ata, e.n, e.U, cntU, e.kc, e.GU, c, 1, st);
+    if (chol_c && e.kc <= CHOL_MAX)
+      launch_chol_solve<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, 1, c, 0, 1, st);
+    else
+      pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0);
+    launch_sparse_block_update<T>(e.csr, e.U, cntU, e.kc, e.y, -1, e.scc.phat,
+                                  e.z, c, 1, st);
   } else {
     launch_sparse_colproj<T>(e.csr, e.csc, e.U, cntU, e.kc, e.g, e.z, e.scc,
                              maxs, itol, c, 1, st);
@@ -570,6 +606,14 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
     }
+  } else if (e.sgram) {
+    launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
+    if (chol_r && e.kr <= CHOL_MAX)
+      launch_chol_solve<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, 1, c, 1, 1, st);
+    else
+      pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1);
+    launch_sparse_block_update<T>(e.csc, e.J, cntJ, e.kr, e.w, 1, e.scr.phat,
+                                  e.x, c, 1, st);
   } else {
     launch_sparse_rowproj<T>(e.csr, e.csc, e.J, cntJ, e.kr, e.r, e.rho, e.x,
                              e.scr, maxs, itol, c, 1, st);

@@ -40,7 +40,7 @@ class Solver:
                  precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
                  solver=B.SOLVER_AUTO, graph=True, gram_aat=False,
                  weight_floor=0.0, tile_rows=0, select="random",
-                 cg_split=False, stream=None):
+                 cg_split=False, sparse_cg=False, stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -84,7 +84,8 @@ class Solver:
                          "iid": B.SELECT_IID}[select]
         p.flags = ((B.FLAG_GRAPH if graph else 0) |
                    (B.FLAG_GRAM_AAT if gram_aat else 0) |
-                   (B.FLAG_CG_SPLIT if cg_split else 0))
+                   (B.FLAG_CG_SPLIT if cg_split else 0) |
+                   (B.FLAG_SPARSE_CG if sparse_cg else 0))
         self.m, self.n = int(m), int(n)
         self.params = p
         self.stream = stream

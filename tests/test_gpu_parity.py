@@ -152,11 +152,14 @@ def test_trajectory_dense_least_squares(rg, kc, kr, solver):
     assert rel(z, zo) <= TRAJ_TOL
 
 
-def test_trajectory_sparse_uniform(rg):
+@pytest.mark.parametrize("sparse_cg", [False, True], ids=["gram", "cg"])
+def test_trajectory_sparse_uniform(rg, sparse_cg):
+    # small enough for the Gram projections (default) and, forced, the
+    # matrix-free CG
     p = workloads.sparse_uniform(3000, 1500, density=0.01, seed=3)
     x, z, info, xo, zo = run_both(rg, p, 150, 300, 4, sparse=True,
-                                  inner_max=200)
-    print(f"sparse uniform rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+                                  inner_max=200, sparse_cg=sparse_cg)
+    print(f"sparse uniform cg={sparse_cg} rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
     assert rel(x, xo) <= TRAJ_TOL
     assert rel(z, zo) <= TRAJ_TOL
 
@@ -694,9 +697,10 @@ def test_block_law_trajectory(rg):
 
 
 # ------------------------------------------------- finite-element systems
+@pytest.mark.parametrize("sparse_cg", [False, True], ids=["gram", "cg"])
 @pytest.mark.parametrize("npts,k,mode", [(25, 0.0, 1), (50, 25.0, 4)],
                          ids=["poisson", "helmholtz"])
-def test_fem_trajectory(rg, npts, k, mode):
+def test_fem_trajectory(rg, npts, k, mode, sparse_cg):
     # Section 6's FEM systems at eta = 0.5 (313 / 1250 of 625 / 2500
     # columns and rows): symmetric, boundary identity rows, and right-hand
     # sides that vanish on the boundary (zero weights that are never drawn)
@@ -704,8 +708,8 @@ def test_fem_trajectory(rg, npts, k, mode):
     p = SimpleNamespace(a=A, b=b)
     kc = kr = int(np.floor(0.5 * A.shape[0] + 0.5))
     x, z, info, xo, zo = run_both(rg, p, kc, kr, 4, sparse=True,
-                                  inner_max=2000)
-    print(f"fem npts={npts} k={k} rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+                                  inner_max=2000, sparse_cg=sparse_cg)
+    print(f"fem npts={npts} k={k} cg={sparse_cg} rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
     assert rel(x, xo) <= TRAJ_TOL
     assert rel(z, zo) <= TRAJ_TOL
 
@@ -807,7 +811,8 @@ def test_sparse_split_cg_finish(rg, kind):
                                       seed=4)
         kc, kr, imax = 300, 600, 1000
     x, z, info, xo, zo = run_both(rg, p, kc, kr, 3, sparse=True,
-                                  inner_max=imax, cg_split=True)
+                                  inner_max=imax, cg_split=True,
+                                  sparse_cg=True)
     print(f"split cg {kind}: rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
     assert rel(x, xo) <= TRAJ_TOL
     assert rel(z, zo) <= TRAJ_TOL
