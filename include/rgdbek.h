@@ -138,9 +138,9 @@ enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
  * blocks of more than 16384 indices do; smaller ones finish in the last
  * workgroup of the step).  The arithmetic is the same either way.
  * SPARSE_CG keeps the matrix-free CG projections for small sparse single
- * systems (both dimensions up to 4096), which by default go through Gram
- * matrices of all columns and rows formed once at create (as dense matrices
- * do). */
+ * systems (both dimensions up to 4096), which by default, when the inner
+ * tolerance is at most 1e-6 (0: the FP64 floor), go through Gram matrices
+ * of all columns and rows formed once at create (as dense matrices do). */
 enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2,
        RGDBEK_FLAG_CG_SPLIT = 4, RGDBEK_FLAG_SPARSE_CG = 8 };
 /* Block rule (rgdbek_params.select_mode). */

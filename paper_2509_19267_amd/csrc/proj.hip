@@ -711,7 +711,7 @@ void launch_list_resid(const T *Arm, int64_t ld, int64_t len,
 //         res -= alpha v, zz = res/rho, beta, p = zz + beta p
 constexpr int SC_NT = 256;
 constexpr unsigned SC_MAXB = 512;   // blocks of a launch that ends in a ticket
-constexpr unsigned SC_WIDE_MAXB = 1024;  // blocks of the columns' wide product
+constexpr unsigned SC_WIDE_MAXB = 512;   // blocks of the columns' wide product
 // Larger blocks update the CG vectors with separate many-workgroup launches
 // (sc_cupd, sc_rupd1/2) instead of a walk by the last workgroup.
 constexpr int64_t SC_SERIAL_MAX = 16384;

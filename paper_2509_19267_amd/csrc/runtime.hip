@@ -366,8 +366,12 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     // formed once through a dense copy, turn each block projection into a
     // gather, one Cholesky or persistent PCG launch and one sparse update,
     // instead of two launches per CG step.
+    // (worth it when the projections are solved to the FP64 floor, i.e. many
+    // CG steps; with a loose inner tolerance a few matrix-free CG steps cost
+    // less than the gather)
+    const bool exact_inner = !(h->p.inner_tol > 1e-6);
     if (!(h->p.flags & RGDBEK_FLAG_SPARSE_CG) && h->rep == 1 && h->nseg == 0 &&
-        e.m <= SPARSE_GRAM_MAX && e.n <= SPARSE_GRAM_MAX) {
+        exact_inner && e.m <= SPARSE_GRAM_MAX && e.n <= SPARSE_GRAM_MAX) {
       const int64_t ld = round_up(e.n, 8), ldc = round_up(e.m, 8);
       T *rm = P.alloc<T>(e.m * ld);
       T *cm = P.alloc<T>(e.n * ldc);
