@@ -319,7 +319,8 @@ def main():
 def spmv_powerlaw(reps=20):
     """Residual passes of the sparse path (CSR row pass + CSC column pass,
     rgdbek_apply) on the 1,000,000 x 500,000 power-law matrix, FP64 and FP32,
-    timed with HIP events on the handle's stream."""
+    timed with HIP events on the handle's stream; then 20 FP64 iterations of
+    a solve on the same matrix (time per iteration of the whole path)."""
     import torch
     import paper_2509_19267_amd as rg
     import workloads
@@ -360,6 +361,24 @@ def spmv_powerlaw(reps=20):
         log(f"sparse passes {prec}: {us:.1f} us per CSR+CSC pair, "
             f"{alg / us / 1e3:.0f} GB/s")
     s.close()
+    # a short FP64 solve on the same matrix (eta = 0.1: blocks of 50 000
+    # columns and 100 000 rows), block projections to 0.1 in at most 16
+    # CG steps: the time per iteration of the whole sparse path
+    b = torch.as_tensor(p.b).cuda()
+    xs = torch.as_tensor(p.x_star).cuda()
+    s = rg.Solver(csr=csr, shape=(m, n), eta=0.1, stop="err_ref", tol=1e-8,
+                  max_iter=20, inner_tol=0.1, inner_max=16, stream=st)
+    s.solve(b, x_ref=xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = s.solve(b, x_ref=xs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.close()
+    out["solve_fp64"] = {"iterations": info["iterations"],
+                         "ms_per_iteration": round(1e3 * el / max(info["iterations"], 1), 2),
+                         "rel_err_after": info["final_metric"]}
+    log(f"sparse solve: {out['solve_fp64']}")
     del csr
     torch.cuda.empty_cache()
     return out
