@@ -747,6 +747,19 @@ def test_select_iid_bit_exact(rg, case):
         assert np.array_equal(got.astype(np.int64), want), name
 
 
+def test_select_iid_size_limit(rg):
+    # the largest supported dimension (4096 chunks of 4096 weights) draws
+    # bit-exactly; one more weight is rejected
+    from oracle.select import select_iid as oiid
+    d = 4096 * 4096
+    eps = np.random.default_rng(63).random(d) ** 2
+    got = rg.select_iid(dev(eps), 100_000, seed=5, it=2).cpu().numpy()
+    assert np.array_equal(got.astype(np.int64), oiid(eps, 100_000, 5, 2, 0))
+    with pytest.raises(rg.RgdbekError) as ei:
+        rg.select_iid(torch.zeros(d + 1, dtype=torch.float64, device="cuda"), 10)
+    assert ei.value.status == 1
+
+
 def test_iid_trajectories(rg):
     # dense least squares and sparse uniform, blocks drawn with replacement
     p = workloads.dense_least_squares(2000, 500, seed=61)
