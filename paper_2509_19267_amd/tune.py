@@ -121,8 +121,11 @@ def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
         return best
 
     best = None
-    for fc in [0.1, 0.2, 0.3, 0.4]:
-        for fr in [0.1, 0.2, 0.3, 0.4, 0.5]:
+    # fractions of n for both blocks, below 1 (the sampling parameter of
+    # Theorem 2.3 lies in (0, 1); row blocks of up to n rows keep the Gram
+    # form); large blocks pay off on tall systems
+    for fc in [0.2, 0.4, 0.6, 0.8, 0.9]:
+        for fr in [0.2, 0.4, 0.6, 0.8, 0.9]:
             kc = max(1, min(int(fc * n), n))
             kr = max(1, min(int(fr * n), m))
             best = run(dict(k_col=kc, k_row=kr, gram_aat=kr > 256,
