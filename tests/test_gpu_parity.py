@@ -829,3 +829,19 @@ def test_sparse_split_cg_finish(rg, kind):
     print(f"split cg {kind}: rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
     assert rel(x, xo) <= TRAJ_TOL
     assert rel(z, zo) <= TRAJ_TOL
+
+
+# ------------------------------------------------ block rules in FP32
+@pytest.mark.parametrize("select", ["greedy", "block_law", "iid"])
+def test_block_rules_mixed_precision(rg, select):
+    # the other block rules inside the FP32 inner iterations (their float
+    # kernels) still refine to the FP64 least-squares solution
+    p = workloads.dense_least_squares(2000, 500, seed=64)
+    kw = dict(eta=0.5) if select == "greedy" else dict(k_col=150, k_row=300)
+    s = rg.Solver(dev(p.a), precision="mixed_f32", select=select,
+                  stop="err_ref", tol=1e-10, max_iter=20000, **kw)
+    x, info = s.solve(dev(p.b), x_ref=dev(p.x_star))
+    s.close()
+    print(f"mixed {select}: {info}", flush=True)
+    assert info["converged"] == 1
+    assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
