@@ -845,3 +845,20 @@ def test_block_rules_mixed_precision(rg, select):
     print(f"mixed {select}: {info}", flush=True)
     assert info["converged"] == 1
     assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
+
+
+@pytest.mark.parametrize("sparse_cg", [False, True], ids=["gram", "cg"])
+def test_block_law_sparse_trajectory(rg, sparse_cg):
+    # Lemma 2.1 blocks on a sparse matrix, both small-system projections
+    p = workloads.sparse_uniform(3000, 1500, density=0.01, seed=65)
+    s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, k_col=150,
+                  k_row=300, select="block_law", stop="none", max_iter=3,
+                  inner_max=300, sparse_cg=sparse_cg)
+    x, _ = s.solve(dev(p.b))
+    z = s.get_z().cpu().numpy()
+    s.close()
+    xo, zo, _ = rgdbek(p.a, p.b, k_col=150, k_row=300, max_iter=3,
+                       block_law=True)
+    print(f"block law sparse cg={sparse_cg}: rel_x {rel(x.cpu().numpy(), xo):.2e} rel_z {rel(z, zo):.2e}", flush=True)
+    assert rel(x.cpu().numpy(), xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
