@@ -134,7 +134,7 @@ def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
         raise RuntimeError("no configuration converged")
     base = best[1]
     for itol in [0.3, 0.1, 0.03, 0.01, 1e-3]:
-        for imax in [8, 16, 32]:
+        for imax in [4, 8, 16, 32]:
             ch = dict(base, inner_tol=itol, inner_max=imax)
             if ch != base:
                 best = run(ch, best)
