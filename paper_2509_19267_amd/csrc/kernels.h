@@ -285,10 +285,14 @@ struct CgWork {
 int64_t pcg_persist_cap(bool f64);
 int pcg_persist_grid(int64_t cap, int ncu);
 template <typename T>
-void launch_pcg_persist(const T *G, int64_t cap, const int64_t *count_dev,
+// F != nullptr: G has not been gathered; the first step reads the block
+// rows of the full Gram F (leading dimension ldf) through hlist and stores
+// them packed into G (cap x cap) for the later steps
+void launch_pcg_persist(T *G, int64_t cap, const int64_t *count_dev,
                         const T *hsrc, const int32_t *hlist, T *y,
                         CgWork<T> &w, int grid, int max_steps, double tol,
-                        Ctrl *ctrl, int ph, int respect_done, hipStream_t st);
+                        Ctrl *ctrl, int ph, int respect_done, hipStream_t st,
+                        const T *F = nullptr, int64_t ldf = 0);
 // largest Gram dimension the PCG kernels accept (direction staged in LDS)
 int64_t pcg_cap_max();
 template <typename T>

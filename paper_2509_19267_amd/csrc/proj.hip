@@ -446,15 +446,16 @@ template <> struct PpCap<float> { static constexpr int64_t v = 8192; };
 
 template <typename T>
 __global__ void __launch_bounds__(PP_NT)
-pcg_persist_kernel(const T *__restrict__ G, int64_t ldg,
+pcg_persist_kernel(T *__restrict__ G, int64_t ldg,
                    const int64_t *__restrict__ cnt, const T *__restrict__ hsrc,
                    const int32_t *__restrict__ hl, T *__restrict__ y,
                    T *__restrict__ vbuf, double *__restrict__ pvbuf,
                    int64_t cap, int max_steps, double tol, Ctrl *ctrl, int ph,
-                   int respect_done) {
+                   int respect_done, const T *__restrict__ F, int64_t ldf) {
   if (respect_done && ctrl_done(ctrl)) return;
   constexpr int64_t CAP = PpCap<T>::v;
   __shared__ T ps[CAP], rs[CAP], dg[CAP];
+  __shared__ int32_t sl[CAP];
   __shared__ double sh[PP_NT / WAVE];
   const int64_t c = *cnt;
   const int P = (int)gridDim.x;
@@ -463,9 +464,20 @@ pcg_persist_kernel(const T *__restrict__ G, int64_t ldg,
   const int64_t r1 = r0 + rpw < c ? r0 + rpw : c;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   double rz = 0.0, rr = 0.0;
+  // F != nullptr: G is not gathered yet.  Every workgroup reads its own
+  // rows of the block straight from the full Gram F (the block list in
+  // LDS) during the first step and stores them packed for the later steps,
+  // which read only the rows the same threads wrote.
   for (int64_t a = threadIdx.x; a < c; a += PP_NT) {
     const T h = hl ? hsrc[hl[a]] : hsrc[a];
-    const T d = G[a * ldg + a];
+    T d;
+    if (F) {
+      const int32_t l = hl[a];
+      sl[a] = l;
+      d = F[(int64_t)l * ldf + l];
+    } else {
+      d = G[a * ldg + a];
+    }
     const T z = d > (T)0 ? h / d : (T)0;
     rs[a] = h;
     dg[a] = d;
@@ -486,17 +498,36 @@ pcg_persist_kernel(const T *__restrict__ G, int64_t ldg,
     double *pvb = pvbuf + (int64_t)par * P;
     double pvp = 0.0;
     for (int64_t row = r0 + wv; row < r1; row += PP_NT / WAVE) {
-      const T *gr = G + row * ldg;
+      T *gr = G + row * ldg;
       T s = (T)0;
       int64_t b = lane;
-      for (; b + (PP_UNROLL - 1) * WAVE < c; b += PP_UNROLL * WAVE) {
-        T gv[PP_UNROLL];
+      if (F && t == 0) {
+        const T *fr = F + (int64_t)sl[row] * ldf;
+        for (; b + (PP_UNROLL - 1) * WAVE < c; b += PP_UNROLL * WAVE) {
+          T gv[PP_UNROLL];
 #pragma unroll
-        for (int u = 0; u < PP_UNROLL; ++u) gv[u] = gr[b + u * WAVE];
+          for (int u = 0; u < PP_UNROLL; ++u) gv[u] = fr[sl[b + u * WAVE]];
 #pragma unroll
-        for (int u = 0; u < PP_UNROLL; ++u) s += gv[u] * ps[b + u * WAVE];
+          for (int u = 0; u < PP_UNROLL; ++u) {
+            gr[b + u * WAVE] = gv[u];
+            s += gv[u] * ps[b + u * WAVE];
+          }
+        }
+        for (; b < c; b += WAVE) {
+          const T gv = fr[sl[b]];
+          gr[b] = gv;
+          s += gv * ps[b];
+        }
+      } else {
+        for (; b + (PP_UNROLL - 1) * WAVE < c; b += PP_UNROLL * WAVE) {
+          T gv[PP_UNROLL];
+#pragma unroll
+          for (int u = 0; u < PP_UNROLL; ++u) gv[u] = gr[b + u * WAVE];
+#pragma unroll
+          for (int u = 0; u < PP_UNROLL; ++u) s += gv[u] * ps[b + u * WAVE];
+        }
+        for (; b < c; b += WAVE) s += gr[b] * ps[b];
       }
-      for (; b < c; b += WAVE) s += gr[b] * ps[b];
       s = wave_sum(s);
       if (lane == 0) {
         vb[row] = s;
@@ -554,13 +585,14 @@ int pcg_persist_grid(int64_t cap, int ncu) {
 }
 
 template <typename T>
-void launch_pcg_persist(const T *G, int64_t cap, const int64_t *count_dev,
+void launch_pcg_persist(T *G, int64_t cap, const int64_t *count_dev,
                         const T *hsrc, const int32_t *hlist, T *y,
                         CgWork<T> &w, int grid, int max_steps, double tol,
-                        Ctrl *ctrl, int ph, int respect_done, hipStream_t st) {
+                        Ctrl *ctrl, int ph, int respect_done, hipStream_t st,
+                        const T *F, int64_t ldf) {
   hipLaunchKernelGGL(pcg_persist_kernel<T>, dim3(grid), dim3(PP_NT), 0, st, G,
                      cap, count_dev, hsrc, hlist, y, w.v2, w.pv2, cap,
-                     max_steps, tol, ctrl, ph, respect_done);
+                     max_steps, tol, ctrl, ph, respect_done, F, ldf);
 }
 
 // ------------------------------------------------------------ thin updates
@@ -1428,10 +1460,11 @@ void launch_sparse_block_update(const Csr<T> &A, const int32_t *list,
   template void launch_pcg_gram_step<T>(const T *, int64_t, const int64_t *, \
                                         T *, CgWork<T> &, int, double,       \
                                         Ctrl *, int, int, hipStream_t);       \
-  template void launch_pcg_persist<T>(const T *, int64_t, const int64_t *,   \
+  template void launch_pcg_persist<T>(T *, int64_t, const int64_t *,         \
                                       const T *, const int32_t *, T *,       \
                                       CgWork<T> &, int, int, double, Ctrl *, \
-                                      int, int, hipStream_t);                 \
+                                      int, int, hipStream_t, const T *,      \
+                                      int64_t);                               \
   template void launch_col_update<T>(const T *, int64_t, int64_t,            \
                                      const int32_t *, const int64_t *,       \
                                      int64_t, const T *, T *, T *, Ctrl *,   \

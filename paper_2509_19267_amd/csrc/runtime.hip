@@ -461,18 +461,22 @@ struct IterOpts {
 };
 
 // Gram solve of a dense block projection: the persistent one-launch PCG when
-// the block fits its LDS staging, else two launches per CG step.
+// the block fits its LDS staging, else two launches per CG step.  With a
+// precomputed full Gram F (leading dimension ldf) the block G is not yet
+// gathered: the persistent PCG gathers it during its first step, the
+// step-per-launch form after a gather launch.
 template <typename T>
-void pcg_solve(rgdbek_ctx *h, const T *G, int64_t cap, const int64_t *cnt,
+void pcg_solve(rgdbek_ctx *h, T *G, int64_t cap, const int64_t *cnt,
                const T *hsrc, const int32_t *hl, T *y, CgWork<T> &w, int maxs,
-               double itol, int ph) {
+               double itol, int ph, const T *F = nullptr, int64_t ldf = 0) {
   const bool f64 = std::is_same<T, double>::value;
   if (cap <= pcg_persist_cap(f64)) {
     launch_pcg_persist<T>(G, cap, cnt, hsrc, hl, y, w,
                           pcg_persist_grid(cap, h->ncu), maxs, itol, h->ctrl,
-                          ph, 1, h->st);
+                          ph, 1, h->st, F, ldf);
     return;
   }
+  if (F) launch_gram_gather<T>(F, ldf, hl, cnt, cap, G, h->ctrl, 1, h->st);
   launch_pcg_gram_init<T>(G, cap, cnt, hsrc, hl, y, w, h->ctrl, ph, 1, h->st);
   for (int k = 0; k < maxs; ++k)
     launch_pcg_gram_step<T>(G, cap, cnt, y, w, k, itol, h->ctrl, ph, 1, h->st);
@@ -528,25 +532,33 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
                       (p.solver == RGDBEK_SOLVER_AUTO && e.kc <= 256);
   const bool chol_r = p.solver == RGDBEK_SOLVER_CHOL ||
                       (p.solver == RGDBEK_SOLVER_AUTO && e.kr <= 256);
+  const bool cg_c = !(chol_c && e.kc <= CHOL_MAX);
+  const bool cg_r = !(chol_r && e.kr <= CHOL_MAX);
   if (e.dense) {
-    if (e.ata)
-      launch_gram_gather<T>(e.ata, e.n, e.U, cntU, e.kc, e.GU, c, 1, st);
-    else
-      launch_gram_rows<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.GU, c, 1,
-                          st);
-    if (chol_c && e.kc <= CHOL_MAX) {
-      launch_chol_solve<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, 1, c, 0, 1, st);
+    if (cg_c && e.ata) {
+      pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0,
+                   e.ata, e.n);
     } else {
-      pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0);
+      if (e.ata)
+        launch_gram_gather<T>(e.ata, e.n, e.U, cntU, e.kc, e.GU, c, 1, st);
+      else
+        launch_gram_rows<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.GU, c,
+                            1, st);
+      if (cg_c)
+        pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0);
+      else
+        launch_chol_solve<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, 1, c, 0, 1, st);
     }
     launch_col_update<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.y, e.z,
                          e.upd, c, 1, st);
   } else if (e.sgram) {
-    launch_gram_gather<T>(e.ata, e.n, e.U, cntU, e.kc, e.GU, c, 1, st);
-    if (chol_c && e.kc <= CHOL_MAX)
+    if (cg_c) {
+      pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0,
+                   e.ata, e.n);
+    } else {
+      launch_gram_gather<T>(e.ata, e.n, e.U, cntU, e.kc, e.GU, c, 1, st);
       launch_chol_solve<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, 1, c, 0, 1, st);
-    else
-      pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0);
+    }
     launch_sparse_block_update<T>(e.csr, e.U, cntU, e.kc, e.y, -1, e.scc.phat,
                                   e.z, c, 1, st);
   } else {
@@ -588,12 +600,14 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1,
                      e.sel, e.J, c, 1, st);
   if (e.dense) {
-    if (e.aat)
-      launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
-    else
-      launch_gram_rows<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.GJ, c, 1,
-                          st);
-    if (chol_r && e.kr <= CHOL_MAX) {
+    if (!cg_r || !e.aat) {
+      if (e.aat)
+        launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
+      else
+        launch_gram_rows<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.GJ, c,
+                            1, st);
+    }
+    if (!cg_r) {
       launch_chol_solve<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, 1, c, 1, 1, st);
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
@@ -606,16 +620,19 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
     } else {
-      pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1);
+      pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1,
+                   e.aat, e.m);
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
     }
   } else if (e.sgram) {
-    launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
-    if (chol_r && e.kr <= CHOL_MAX)
+    if (cg_r) {
+      pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1,
+                   e.aat, e.m);
+    } else {
+      launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
       launch_chol_solve<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, 1, c, 1, 1, st);
-    else
-      pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1);
+    }
     launch_sparse_block_update<T>(e.csc, e.J, cntJ, e.kr, e.w, 1, e.scr.phat,
                                   e.x, c, 1, st);
   } else {
