@@ -443,6 +443,13 @@ constexpr int PP_UNROLL = 8;                     // row loads in flight per lane
 template <typename T> struct PpCap;
 template <> struct PpCap<double> { static constexpr int64_t v = 4096; };
 template <> struct PpCap<float> { static constexpr int64_t v = 8192; };
+// 16-byte row loads of the packed block (rows start 16-byte aligned when
+// the leading dimension is a multiple of the vector width)
+typedef double pp_d2 __attribute__((ext_vector_type(2)));
+typedef float pp_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct PpVec;
+template <> struct PpVec<double> { using type = pp_d2; static constexpr int n = 2; };
+template <> struct PpVec<float> { using type = pp_f4; static constexpr int n = 4; };
 
 template <typename T>
 __global__ void __launch_bounds__(PP_NT)
@@ -518,6 +525,28 @@ pcg_persist_kernel(T *__restrict__ G, int64_t ldg,
           gr[b] = gv;
           s += gv * ps[b];
         }
+      } else if (ldg % PpVec<T>::n == 0) {
+        using V = typename PpVec<T>::type;
+        constexpr int VN = PpVec<T>::n;
+        const V *grv = reinterpret_cast<const V *>(gr);
+        const int64_t cv = c / VN;
+        int64_t q = lane;
+        for (; q + (PP_UNROLL - 1) * WAVE < cv; q += PP_UNROLL * WAVE) {
+          V gv[PP_UNROLL];
+#pragma unroll
+          for (int u = 0; u < PP_UNROLL; ++u) gv[u] = grv[q + u * WAVE];
+#pragma unroll
+          for (int u = 0; u < PP_UNROLL; ++u)
+#pragma unroll
+            for (int v = 0; v < VN; ++v)
+              s += gv[u][v] * ps[(q + u * WAVE) * VN + v];
+        }
+        for (; q < cv; q += WAVE) {
+          const V g = grv[q];
+#pragma unroll
+          for (int v = 0; v < VN; ++v) s += g[v] * ps[q * VN + v];
+        }
+        for (b = cv * VN + lane; b < c; b += WAVE) s += gr[b] * ps[b];
       } else {
         for (; b + (PP_UNROLL - 1) * WAVE < c; b += PP_UNROLL * WAVE) {
           T gv[PP_UNROLL];
