@@ -152,6 +152,22 @@ def test_trajectory_dense_least_squares(rg, kc, kr, solver):
     assert rel(z, zo) <= TRAJ_TOL
 
 
+@pytest.mark.parametrize("kc,kr,gram_aat", [(301, 403, False), (301, 403, True),
+                                            (300, 400, True)])
+def test_trajectory_dense_pcg_gram_sources(rg, kc, kr, gram_aat):
+    # persistent PCG on both projections: the column block gathered from
+    # A^T A inside the first CG step, the row block from A A^T likewise
+    # (gram_aat) or formed from the rows; odd block sizes take the scalar
+    # row loads, even ones the 16-byte loads
+    p = workloads.dense_least_squares(2000, 500, seed=7)
+    x, z, info, xo, zo = run_both(rg, p, kc, kr, 4, seed=3, solver=0,
+                                  inner_max=200, gram_aat=gram_aat)
+    print(f"pcg kc={kc} kr={kr} aat={gram_aat} rel_x={rel(x, xo):.3e} rel_z={rel(z, zo):.3e}", flush=True)
+    assert info["iterations"] == 4
+    assert rel(x, xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
+
+
 @pytest.mark.parametrize("sparse_cg", [False, True], ids=["gram", "cg"])
 def test_trajectory_sparse_uniform(rg, sparse_cg):
     # small enough for the Gram projections (default) and, forced, the
