@@ -459,7 +459,23 @@ dense_finalize(int64_t rows, int64_t cols, int64_t ld, int nch, int nrg,
     const int64_t t = (int64_t)blockIdx.x * WAVE + lane;
     T s0 = (T)0, s1 = (T)0;
     if (t < cols) {
+      // s0 takes tiles wv, wv + 8, ... and s1 tiles wv + 4, wv + 12, ...;
+      // four of those steps load together (eight loads in flight), the
+      // additions keep their order
       int b = wv;
+      for (; b + 28 < nrg; b += 32) {
+        T v0[4], v1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          v0[j] = gpart[(int64_t)(b + 8 * j) * ld + t];
+          v1[j] = gpart[(int64_t)(b + 8 * j + 4) * ld + t];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          s0 += v0[j];
+          s1 += v1[j];
+        }
+      }
       for (; b + 4 < nrg; b += 8) {
         s0 += gpart[(int64_t)b * ld + t];
         s1 += gpart[(int64_t)(b + 4) * ld + t];
@@ -480,7 +496,15 @@ dense_finalize(int64_t rows, int64_t cols, int64_t ld, int nch, int nrg,
   const int64_t t = (int64_t)(blockIdx.x - ncb) * 256 + threadIdx.x;
   if (t < rows) {
     T s = (T)0;
-    for (int c = 0; c < nch; ++c) s += qpart[(int64_t)c * rows + t];
+    int c = 0;
+    for (; c + 4 <= nch; c += 4) {
+      T v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = qpart[(int64_t)(c + j) * rows + t];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s += v[j];
+    }
+    for (; c < nch; ++c) s += qpart[(int64_t)c * rows + t];
     q[t] = s;
   }
 }
