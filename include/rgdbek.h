@@ -132,7 +132,10 @@ typedef struct {
  * preconditioned conjugate gradients on the Gram matrix above that. */
 enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
 /* Flags: GRAPH captures the iteration loop into HIP graphs (default on via
- * rgdbek_params_default); GRAM_AAT precomputes A A^T for dense row blocks;
+ * rgdbek_params_default); GRAM_AAT precomputes A A^T (m x m, m up to 32768,
+ * else ignored) for dense row blocks, as A^T A is always precomputed for
+ * dense column blocks of more than 64 columns when n <= 8192; the blocks
+ * are then gathered from these matrices instead of formed from A;
  * CG_SPLIT makes the sparse block projections finish every CG step with
  * separate many-workgroup launches whatever the block size (by default only
  * blocks of more than 16384 indices do; smaller ones finish in the last
