@@ -68,6 +68,22 @@ def column_projection(a_u, z):
     return z - a_u @ y, y, nr
 
 
+def column_projection_offset(a_u, dz, t_u):
+    """Column update of the refinement's correction system.
+
+    The refinement pass (FP64 x, correction (dx, dz) from (0, 0)) runs
+    Algorithm 1 on the full residual s + dz with s = b - A x, which it knows
+    only through t = A^T s.  The column update of Algorithm 1 applied to it,
+    s + dz -> (I - A_U A_U^+)(s + dz), changes dz by -A_U y with
+    y = A_U^+ (s + dz) = (A_U^T A_U)^+ (A_U^T dz + t_U).  Any v with
+    A_U^T v = t_U inside range(A_U) gives the same y as s; the minimum-norm
+    solution of A_U^T v = t_U is one (t_U lies in range(A_U^T)).
+    Returns (dz_next, y, normal_residual)."""
+    v, _ = pinv_apply(a_u.T, t_u)
+    y, nr = pinv_apply(a_u, dz + v)
+    return dz - a_u @ y, y, nr
+
+
 def row_projection(a_j, r_j):
     """d = (A^J)^+ r^J, the correction added to x.  Returns (d, residual)."""
     d, nr = pinv_apply(a_j, r_j)

@@ -35,8 +35,13 @@ with x_0 = 0 and z_0 = b.  Readings where the paper is silent:
   forward solve, 1 for solves on the adjoint system).
 
 Optional ``col_offset`` t and right-hand side ``b`` make the same loop solve
-the correction system of the extended-residual refinement: the column
-residual becomes A^T z + t.  With t = 0 it is Algorithm 1 unchanged.
+the correction system of the extended-residual refinement: from an FP64
+iterate x with s = b - A x and t = A^T s, Algorithm 1 runs on the
+correction (dx, dz) from (0, 0) with right-hand side 0, so that s + dz
+plays the role of z: the column residual becomes A^T dz + t, the column
+update projects s + dz (``column_projection_offset``), and the row
+residual is -dz - A dx.  Its fixed point is x + dx = A^+ b.  With t = 0 and
+the true right-hand side it is Algorithm 1 unchanged.
 
 Test infrastructure only (see the package docstring).
 """
@@ -47,7 +52,8 @@ import scipy.sparse as sp
 
 from .select import (select, select_threshold, select_block_law, select_iid,
                      block_size, FLOOR_FP64)
-from .blockls import column_projection, row_projection
+from .blockls import (column_projection, column_projection_offset,
+                      row_projection)
 
 
 @dataclass
@@ -144,7 +150,10 @@ def rgdbek(a, b, *, k_col=None, k_row=None, eta=None, max_iter=100, seed=0,
         else:
             u = select(eps_z, k_col, seed, it, 0, sys, key1, floor)
         z_prev = z
-        if u.size:
+        if u.size and col_offset is not None:
+            z, y, nr_c = column_projection_offset(a_csc[:, u], z,
+                                                  col_offset[u])
+        elif u.size:
             z, y, nr_c = column_projection(a_csc[:, u], z)
         else:
             y, nr_c = np.zeros(0), 0.0

@@ -372,11 +372,30 @@ class RGDBEKFunction(torch.autograd.Function):
     estimate of the least-squares residual r = (I - A A^+) b -- and no
     iterate history.  The backward runs RGDBEK on the adjoint system
     A^T w = dL/dx (w = dL/db) and, for least-squares systems, once more on A
-    (lam = A^+ w); then dL/dA = r lam^T - w x^T on A's pattern."""
+    (lam = A^+ w); then dL/dA = r lam^T - w x^T on A's pattern.
+
+    The handle must stop on a residual test ('res_ext', 'rse') or run a
+    fixed count ('none'): inside a layer there is no reference solution,
+    so an 'err_ref' handle is rejected.  Every solve (forward, adjoint,
+    second solve) must meet its stopping test; a solve that runs out of
+    iterations raises instead of returning a wrong gradient."""
+
+    @staticmethod
+    def _checked(what, info):
+        if not info.get("converged", False):
+            raise RuntimeError(
+                f"RGDBEK {what} solve stopped after {info.get('iterations')} "
+                f"iterations without meeting its stopping test (metric "
+                f"{info.get('final_metric')}); the gradient would be wrong")
 
     @staticmethod
     def forward(ctx, values, b, solver, least_squares):
-        x, _ = solver.solve(b)
+        if int(solver.params.stop) == B.STOP_NAMES["err_ref"]:
+            raise ValueError("a differentiable solve needs a handle with stop "
+                             "'res_ext', 'rse' or 'none' (no reference "
+                             "solution exists inside a layer)")
+        x, info = solver.solve(b)
+        RGDBEKFunction._checked("forward", info)
         z = solver.get_z() if least_squares else None
         ctx.solver = solver
         ctx.least_squares = least_squares
@@ -388,9 +407,11 @@ class RGDBEKFunction(torch.autograd.Function):
     def backward(ctx, gx):
         x, z = ctx.saved_tensors
         s = ctx.solver
-        w, _ = s.solve_adjoint(gx.contiguous().to(torch.float64))
+        w, info = s.solve_adjoint(gx.contiguous().to(torch.float64))
+        RGDBEKFunction._checked("adjoint", info)
         if ctx.least_squares:
-            lam, _ = s.solve(w)
+            lam, info = s.solve(w)
+            RGDBEKFunction._checked("second (lam = A^+ w)", info)
             dA = s.grad_pattern(z, lam, w, x, ctx.nnz)
         else:
             dA = s.grad_pattern(None, None, w, x, ctx.nnz)
