@@ -64,15 +64,18 @@ enum { RGDBEK_STOP_NONE = 0, RGDBEK_STOP_ERR_REF = 1, RGDBEK_STOP_RSE = 2,
 /* Arithmetic of the solve (rgdbek_params.precision):
  *  FP64       every step in FP64;
  *  MIXED_F32  inner RGDBEK iterations with FP32 matrix values, vectors and
- *             accumulation, inside an FP64 refinement loop: each pass sets
+ *             accumulation, inside an FP64 refinement loop.  State (x, z) in
+ *             FP64; each pass tests the stop rule in FP64 on it, sets
  *             z = b - A x and forms A^T z in FP64, the FP32 iterations solve
- *             for the correction (dx, dz) from (0, 0), and x += dx in FP64;
- *             norms and the stopping test are FP64.  Stop modes ERR_REF,
- *             RSE and NONE (RES_EXT is UNSUPPORTED in this form);
- *  MIXED_BF16 as MIXED_F32 with the inner matrix values rounded to bfloat16
- *             (accumulation stays FP32). */
-enum { RGDBEK_PREC_FP64 = 0, RGDBEK_PREC_MIXED_F32 = 1,
-       RGDBEK_PREC_MIXED_BF16 = 2 };
+ *             for the correction (dx, dz) from (0, 0), then x += dx and
+ *             z += dz in FP64.  A pass ends on residuals alone: when the
+ *             FP32 extended residual ||dz + A dx|| (that of the refined
+ *             state) has fallen to 1e-5 of its first value in the pass (or
+ *             to tol under RES_EXT), or stops improving.  Every stop mode is
+ *             served; the test is made in FP64 between passes (RES_EXT from
+ *             the second pass on: before the first, z = b and x = 0 meet it
+ *             trivially). */
+enum { RGDBEK_PREC_FP64 = 0, RGDBEK_PREC_MIXED_F32 = 1 };
 
 /* The coefficient matrix A (m x n).  All pointers are device pointers owned
  * by the caller and read only during rgdbek_create: the library copies and
@@ -126,6 +129,10 @@ typedef struct {
                             with replacement, distinct indices kept (see
                             rgdbek_select_iid; at most 16M rows/columns).
                             Modes 1-3: single systems only.                 */
+  double pass_drop;      /* MIXED_F32: a refinement pass ends when its FP32
+                            extended residual has fallen to pass_drop times
+                            its first value in the pass (0 = 1e-5; in
+                            (0, 1))                                         */
 } rgdbek_params;
 
 /* Dense block solvers: AUTO picks Cholesky for blocks up to 256 and
@@ -145,7 +152,25 @@ enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
  * tolerance is at most 1e-6 (0: the FP64 floor), go through Gram matrices
  * of all columns and rows formed once at create (as dense matrices do). */
 enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2,
-       RGDBEK_FLAG_CG_SPLIT = 4, RGDBEK_FLAG_SPARSE_CG = 8 };
+       RGDBEK_FLAG_CG_SPLIT = 4, RGDBEK_FLAG_SPARSE_CG = 8,
+       RGDBEK_FLAG_PROFILE = 16 };
+/* RGDBEK_FLAG_PROFILE times every step of every iteration with HIP events on
+ * the handle's stream (the launches are then issued one by one, not from
+ * captured graphs, so a profiled solve runs a little slower than a plain
+ * one; the arithmetic is the same).  Regions, one per step of Algorithm 1's
+ * iteration, read back with rgdbek_profile_read after a solve: */
+enum { RGDBEK_PROF_COL_RESIDUAL = 0, /* A^T z and eps^z (dense: the fused
+                                        pass that also forms A x)          */
+       RGDBEK_PROF_COL_DRAW = 1,     /* column block draw                   */
+       RGDBEK_PROF_COL_SOLVE = 2,    /* column block least-squares solve    */
+       RGDBEK_PROF_COL_UPDATE = 3,   /* z -= A_U y                          */
+       RGDBEK_PROF_ROW_RESIDUAL = 4, /* b - z - A x and eps^x               */
+       RGDBEK_PROF_ROW_DRAW = 5,     /* row block draw                      */
+       RGDBEK_PROF_ROW_SOLVE = 6,    /* row block least-squares solve       */
+       RGDBEK_PROF_ROW_UPDATE = 7,   /* x += A^J^T w                        */
+       RGDBEK_PROF_STOP = 8,         /* stop tests and iteration counters   */
+       RGDBEK_PROF_REFINE = 9,       /* FP64 passes of the mixed form       */
+       RGDBEK_PROF_COUNT = 10 };
 /* Block rule (rgdbek_params.select_mode). */
 enum { RGDBEK_SELECT_RANDOM = 0, RGDBEK_SELECT_GREEDY = 1,
        RGDBEK_SELECT_BLOCK_LAW = 2, RGDBEK_SELECT_IID = 3 };
@@ -324,6 +349,16 @@ rgdbek_status rgdbek_select_threshold(const double *eps, int64_t d, double eta,
  * nrhs*m entries, right-hand side major). */
 rgdbek_status rgdbek_apply(rgdbek_handle h, int32_t precision, const void *x,
                            const void *z, void *ax, void *atz);
+
+/* Event timing of the last solve on a handle created with
+ * RGDBEK_FLAG_PROFILE (see above): for region `region` (RGDBEK_PROF_*), the
+ * number of timed executions in iterations that did work, their summed
+ * duration in milliseconds, and the summed inner solver steps (CG steps of
+ * the block solves; 0 for other regions).  Any output pointer may be NULL.
+ * INVALID_ARG for an unknown region; UNSUPPORTED without the flag. */
+rgdbek_status rgdbek_profile_read(rgdbek_handle h, int32_t region,
+                                  int64_t *launches, double *ms,
+                                  int64_t *steps);
 
 /* Release everything the handle owns.  NULL is a no-op. */
 rgdbek_status rgdbek_destroy(rgdbek_handle h);

@@ -16,6 +16,12 @@ r = 0 and the first term drops.  ``grad_via_solves`` computes the same
 quantities with two runs of the oracle solver (the adjoint system A^T w = gx,
 then A lam = w) so that a GPU gradient can be compared with either.
 
+Deblurring with Tikhonov rows (Section 6's deblurring problem, solved as
+the least-squares system [A; s I] x ~= [b; 0]): for a separable blur
+A = T kron T with symmetric T = Q diag(lam) Q^T the normal equations
+(A^T A + s^2 I) x = A^T b diagonalise in the basis Q kron Q, so the
+solution is written out directly (``tikhonov_kron``).
+
 Test infrastructure only (see the package docstring).
 """
 import numpy as np
@@ -73,3 +79,25 @@ def grad_via_solves(a, b, gx, x, *, k_col, k_row, max_iter, seed=0, tol=1e-13,
     else:
         da = np.outer(r, lam) - np.outer(w, x)
     return da, w, lam
+
+
+def tikhonov_kron(t, b_img, s):
+    """argmin_x ||(T kron T) x - b||^2 + s^2 ||x||^2 for symmetric T (p x p)
+    and one or more right-hand sides b (columns of b_img, p*p rows each,
+    row-major image order, so (T kron T) vec(X) = vec(T X T)).  With
+    T = Q diag(lam) Q^T, X = Q (F o (Q^T B Q)) Q^T where
+    F_ij = lam_i lam_j / ((lam_i lam_j)^2 + s^2)."""
+    t = np.asarray(t, dtype=np.float64)
+    lam, q = np.linalg.eigh(t)
+    p = t.shape[0]
+    ll = np.outer(lam, lam)
+    f = ll / (ll * ll + s * s)
+    b_img = np.asarray(b_img, dtype=np.float64)
+    single = b_img.ndim == 1
+    bm = b_img.reshape(p * p, -1)
+    out = np.empty_like(bm)
+    for c in range(bm.shape[1]):
+        bimg = bm[:, c].reshape(p, p)
+        y = q.T @ bimg @ q
+        out[:, c] = (q @ (f * y) @ q.T).ravel()
+    return out[:, 0] if single else out

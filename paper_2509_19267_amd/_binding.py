@@ -16,15 +16,18 @@ OK, ERR_INVALID_ARG, ERR_NUMERIC, ERR_NOT_CONVERGED, ERR_OUT_OF_MEMORY, \
 DENSE_ROW_MAJOR, CSR = 0, 1
 F64, F32 = 0, 1
 STOP_NONE, STOP_ERR_REF, STOP_RSE, STOP_RES_EXT = 0, 1, 2, 3
-PREC_FP64, PREC_MIXED_F32, PREC_MIXED_BF16 = 0, 1, 2
+PREC_FP64, PREC_MIXED_F32 = 0, 1
 SOLVER_AUTO, SOLVER_CHOL, SOLVER_CG = 0, 1, 2
-FLAG_GRAPH, FLAG_GRAM_AAT, FLAG_CG_SPLIT, FLAG_SPARSE_CG = 1, 2, 4, 8
+FLAG_GRAPH, FLAG_GRAM_AAT, FLAG_CG_SPLIT, FLAG_SPARSE_CG, FLAG_PROFILE = \
+    1, 2, 4, 8, 16
+PROF_REGIONS = ["col_residual", "col_draw", "col_solve", "col_update",
+                "row_residual", "row_draw", "row_solve", "row_update",
+                "stop", "refine"]
 SELECT_RANDOM, SELECT_GREEDY, SELECT_BLOCK_LAW, SELECT_IID = 0, 1, 2, 3
 
 STOP_NAMES = {"none": STOP_NONE, "err_ref": STOP_ERR_REF, "rse": STOP_RSE,
               "res_ext": STOP_RES_EXT}
-PREC_NAMES = {"fp64": PREC_FP64, "mixed_f32": PREC_MIXED_F32,
-              "mixed_bf16": PREC_MIXED_BF16}
+PREC_NAMES = {"fp64": PREC_FP64, "mixed_f32": PREC_MIXED_F32}
 
 
 class Matrix(ctypes.Structure):
@@ -42,7 +45,8 @@ class Params(ctypes.Structure):
                 ("inner_max", ctypes.c_int32), ("graph_iters", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("solver", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("weight_floor", ctypes.c_double),
-                ("tile_rows", ctypes.c_int32), ("select_mode", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("select_mode", ctypes.c_int32),
+                ("pass_drop", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -106,6 +110,10 @@ SIGNATURES = {
     "rgdbek_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int32)]),
+    "rgdbek_profile_read": (ctypes.c_int, [_vp, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64)]),
     "rgdbek_destroy": (ctypes.c_int, [_vp]),
     "rgdbek_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rgdbek_last_error": (ctypes.c_char_p, [_vp]),

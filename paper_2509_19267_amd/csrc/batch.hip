@@ -37,6 +37,7 @@ __global__ void seg_reset_kernel(SegInfo *seg, int nseg, int64_t it0,
   SegInfo &g = seg[s];
   if (!keep_it) g.it = it0;
   g.iters_run = 0;
+  g.pref = 0.0;
   const int f = fixed ? fixed[s] : 0;
   g.done = f;
   g.converged = f;
@@ -69,7 +70,9 @@ seg_err_ref_kernel(const T *__restrict__ x, const double *__restrict__ xr,
 }
 
 // RSE / RES_EXT per system from r = b - z - A x and z of the row pass:
-// RSE = ||r + z||^2 / ||b_s||^2, RES_EXT = ||r|| / ||b_s||.
+// RSE = ||r + z||^2 / ||b_s||^2, RES_EXT = ||r|| / ||b_s||; in a refinement
+// pass (Ctrl::pass_drop > 0) also passed at pass_drop times the system's
+// first metric of the pass.
 template <typename T>
 __global__ void __launch_bounds__(BT)
 seg_stop_rowres_kernel(const T *__restrict__ r, const T *__restrict__ z,
@@ -90,7 +93,13 @@ seg_stop_rowres_kernel(const T *__restrict__ r, const T *__restrict__ z,
     const double den = g.ref2 > 0.0 ? g.ref2 : 1.0;
     const double m = mode == 2 ? s / den : sqrt(s / den);
     g.metric = m;
-    if (m <= tol) { g.done = 1; g.converged = 1; }
+    double thr = tol;
+    if (ctrl->pass_drop > 0.0) {
+      if (g.pref <= 0.0) g.pref = m;
+      const double rel = ctrl->pass_drop * g.pref;
+      thr = rel > thr ? rel : thr;
+    }
+    if (m <= thr) { g.done = 1; g.converged = 1; }
   }
 }
 

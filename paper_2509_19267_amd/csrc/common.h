@@ -21,6 +21,11 @@ struct Ctrl {
   double tol;          // tolerance of the stop test
   double ref2;         // ||x_ref||^2 or ||b||^2 (denominator of the test)
   double metric;       // last evaluated stop metric
+  // refinement passes of the mixed form: a residual test (RSE/RES_EXT) also
+  // holds once metric <= pass_drop * pass_ref, pass_ref being the first
+  // metric the pass evaluated (pass_drop 0: off)
+  double pass_drop;
+  double pass_ref;
   // block selection state (one per phase: 0 = columns, 1 = rows)
   int64_t sel_count[2];   // indices selected
   int64_t sel_pos[2];     // positive weights seen
@@ -58,6 +63,7 @@ struct SegInfo {
   int32_t converged;
   double metric;
   double ref2;
+  double pref;         // first residual metric of a refinement pass
 };
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -366,6 +366,28 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                            SparseCg<T> &w, int max_steps, double tol,
                            Ctrl *ctrl, int respect_done, hipStream_t st);
 
+// Row blocks taller than A is wide (k_row > n): CGLS on min ||A^J d - r^J||
+// (see proj.hip).  d, p, s: n entries; res, q: cap; rhat: m (sparse only:
+// the residual scattered onto the block's rows, zero elsewhere).
+template <typename T>
+struct TallWork {
+  T *d = nullptr, *p = nullptr, *s = nullptr;
+  T *res = nullptr, *q = nullptr;
+  T *rhat = nullptr;
+};
+template <typename T>
+void launch_tall_rowproj_dense(const Dense<T> &A, const int32_t *J,
+                               const int64_t *count_dev, int64_t cap,
+                               const T *r, T *x, TallWork<T> &w, T *upd,
+                               int max_steps, double tol, Ctrl *ctrl,
+                               hipStream_t st);
+template <typename T>
+void launch_tall_rowproj_sparse(const Csr<T> &csr, const Csr<T> &csc,
+                                const int32_t *J, const int64_t *count_dev,
+                                int64_t cap, const T *r, T *x, TallWork<T> &w,
+                                int max_steps, double tol, Ctrl *ctrl,
+                                hipStream_t st);
+
 // ------------------------------------------------------------ utilities
 template <typename Tout, typename Tin>
 void launch_convert(const Tin *in, Tout *out, int64_t n, hipStream_t st);
@@ -407,5 +429,14 @@ template <typename Ty, typename Tx>
 void launch_axpby(int64_t n, double alpha, Ty *y, double beta, const Tx *x,
                   hipStream_t st);
 void launch_fill_ctrl_it(Ctrl *ctrl, int64_t it, hipStream_t st);
+// Profiling marks (runtime profile mode): post == 0 records whether the
+// solve is still running (Ctrl::done clear), post == 1 the CG steps of
+// phase ph (ph < 0: none).
+struct ProfRec {
+  int32_t live;
+  int32_t steps;
+};
+void launch_prof_mark(const Ctrl *ctrl, ProfRec *rec, int post, int ph,
+                      hipStream_t st);
 
 }  // namespace rg

@@ -48,67 +48,148 @@ void launch_gram_gather(const T *F, int64_t ldf, const int32_t *list,
                      respect_done);
 }
 
-// G[a][b] = <X_{l_a}, X_{l_b}> (list == nullptr: identity), 32x32 output
-// tiles, 16x16 threads with 2x2 outputs each, K staged through LDS.
-constexpr int GT = 32, GK = 32;
+// G[a][b] = <X_{l_a}, X_{l_b}> (list == nullptr: identity) on the matrix
+// cores (MFMA 16x16x4, FP64 or FP32): one
+// workgroup of 4 waves per 64 x 64 lower tile (mirrored on store), each wave
+// a 32 x 32 quarter as 2 x 2 MFMA blocks.  K advances 16 at a time through
+// double-buffered LDS stages stored k-major (tile[k][row]), so the 16 lanes
+// that feed one MFMA row group read consecutive words; the next stage is
+// loaded from global memory into registers while the current one is
+// multiplied.  Operand layout of v_mfma_*_16x16x4 (both precisions): lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element r of
+// lane l is D[row(l / 16, r)][l % 16], row = 4 (l / 16) + r for FP32 and
+// 4 r + l / 16 for FP64 (measured on gfx950).
+template <typename T> struct Mfma16;
+template <> struct Mfma16<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * r + lk; }
+};
+template <> struct Mfma16<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+constexpr int SY_B = 64;             // output tile (rows = columns)
+constexpr int SY_K = 16;             // k per LDS stage
+constexpr int SY_P = SY_B + 16;      // LDS row pitch (k-major rows of 64)
+constexpr int SY_NT = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(256)
-gram_rows_kernel(const T *__restrict__ X, int64_t ld, int64_t len,
+__device__ __forceinline__ void sy_load(const T *__restrict__ X, int64_t ld,
+                                        int64_t len,
+                                        const int32_t *__restrict__ list,
+                                        int64_t c, int64_t r0, int64_t k0,
+                                        T (&v)[4]) {
+  // thread t: row r0 + t / 4, k = k0 + 4 (t % 4) .. + 3
+  const int64_t r = r0 + (threadIdx.x >> 2);
+  const int64_t k = k0 + 4 * (threadIdx.x & 3);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = (T)0;
+  if (r >= c) return;
+  const T *row = X + (list ? (int64_t)list[r] : r) * ld;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (k + u < len) v[u] = row[k + u];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SY_NT)
+gram_mfma_kernel(const T *__restrict__ X, int64_t ld, int64_t len,
                  const int32_t *__restrict__ list,
                  const int64_t *__restrict__ cnt, int64_t cap, int64_t ldg,
                  T *__restrict__ G, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
+  typedef typename Mfma16<T>::v4 v4;
   const int64_t c = cnt ? *cnt : cap;
-  const int64_t ta = (int64_t)blockIdx.y * GT, tb = (int64_t)blockIdx.x * GT;
+  const int64_t ta = (int64_t)blockIdx.y * SY_B, tb = (int64_t)blockIdx.x * SY_B;
   if (ta >= c || tb >= c || tb > ta) return;   // lower tiles only
-  __shared__ T sa[GT][GK + 1], sb[GT][GK + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  T acc[2][2] = {{0, 0}, {0, 0}};
-  for (int64_t k0 = 0; k0 < len; k0 += GK) {
-    for (int e = threadIdx.x; e < GT * GK; e += 256) {
-      const int rr = e / GK, kk = e % GK;
-      const int64_t ra = ta + rr, rb = tb + rr, k = k0 + kk;
-      T va = 0, vb = 0;
-      if (ra < c && k < len) va = X[(list ? (int64_t)list[ra] : ra) * ld + k];
-      if (rb < c && k < len) vb = X[(list ? (int64_t)list[rb] : rb) * ld + k];
-      sa[rr][kk] = va;
-      sb[rr][kk] = vb;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < GK; ++kk) {
-      const T a0 = sa[ty][kk], a1 = sa[ty + 16][kk];
-      const T b0 = sb[tx][kk], b1 = sb[tx + 16][kk];
-      acc[0][0] += a0 * b0; acc[0][1] += a0 * b1;
-      acc[1][0] += a1 * b0; acc[1][1] += a1 * b1;
-    }
-    __syncthreads();
-  }
+  __shared__ T sa[2][SY_K][SY_P], sb[2][SY_K][SY_P];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = threadIdx.x / WAVE;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  const int sr = threadIdx.x >> 2, sk = 4 * (threadIdx.x & 3);
+  v4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t ra = ta + ty + 16 * i, rb = tb + tx + 16 * j;
-      if (ra < c && rb < c) {
-        G[ra * ldg + rb] = acc[i][j];
-        G[rb * ldg + ra] = acc[i][j];
+    for (int j = 0; j < 2; ++j) acc[i][j] = (v4){0, 0, 0, 0};
+  T va[4], vb[4];
+  sy_load<T>(X, ld, len, list, c, ta, 0, va);
+  sy_load<T>(X, ld, len, list, c, tb, 0, vb);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    sa[0][sk + u][sr] = va[u];
+    sb[0][sk + u][sr] = vb[u];
+  }
+  __syncthreads();
+  const int64_t nst = (len + SY_K - 1) / SY_K;
+  for (int64_t st = 0; st < nst; ++st) {
+    const int cur = (int)(st & 1);
+    const bool more = st + 1 < nst;
+    if (more) {
+      sy_load<T>(X, ld, len, list, c, ta, (st + 1) * SY_K, va);
+      sy_load<T>(X, ld, len, list, c, tb, (st + 1) * SY_K, vb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < SY_K / 4; ++kk) {
+      const int k = 4 * kk + lk;
+      T fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        fa[i] = sa[cur][k][wr + 16 * i + li];
+        fb[i] = sb[cur][k][wc + 16 * i + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = Mfma16<T>::mma(fa[i], fb[j], acc[i][j]);
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sa[cur ^ 1][sk + u][sr] = va[u];
+        sb[cur ^ 1][sk + u][sr] = vb[u];
       }
     }
+    __syncthreads();
+  }
+  const bool diag = (ta == tb);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = ta + wr + 16 * i + Mfma16<T>::row(lk, r);
+        const int64_t gj = tb + wc + 16 * j + li;
+        if (gi >= c || gj >= c || (diag && gj > gi)) continue;
+        const T v = acc[i][j][r];
+        G[gi * ldg + gj] = v;
+        G[gj * ldg + gi] = v;
+      }
 }
+
 template <typename T>
 void launch_gram_rows(const T *X, int64_t ld, int64_t len, const int32_t *list,
                       const int64_t *count_dev, int64_t cap, T *G, Ctrl *ctrl,
                       int respect_done, hipStream_t st) {
-  const unsigned nt = (unsigned)((cap + GT - 1) / GT);
-  hipLaunchKernelGGL(gram_rows_kernel<T>, dim3(nt, nt), dim3(256), 0, st, X,
+  const unsigned nt = (unsigned)((cap + SY_B - 1) / SY_B);
+  hipLaunchKernelGGL(gram_mfma_kernel<T>, dim3(nt, nt), dim3(SY_NT), 0, st, X,
                      ld, len, list, count_dev, cap, cap, G, ctrl,
                      respect_done);
 }
 template <typename T>
 void launch_gram_full(const T *X, int64_t ldx, int64_t rows, int64_t len,
                       T *F, hipStream_t st) {
-  const unsigned nt = (unsigned)((rows + GT - 1) / GT);
-  hipLaunchKernelGGL(gram_rows_kernel<T>, dim3(nt, nt), dim3(256), 0, st, X,
+  const unsigned nt = (unsigned)((rows + SY_B - 1) / SY_B);
+  hipLaunchKernelGGL(gram_mfma_kernel<T>, dim3(nt, nt), dim3(SY_NT), 0, st, X,
                      ldx, len, (const int32_t *)nullptr,
                      (const int64_t *)nullptr, rows, rows, F, (Ctrl *)nullptr,
                      0);
@@ -1530,5 +1611,237 @@ template void launch_sparse_block_update<float>(
     const Csr<float> &, const int32_t *, const int64_t *, int64_t,
     const float *, int, float *, float *, Ctrl *, int, hipStream_t);
 #undef RG_INST
+
+// ------------------------------------------------------------ tall row blocks
+// A row block with more rows than A has columns (k_row > n) is in general
+// inconsistent: r^J need not lie in range(A^J), and CG on A^J A^J^T does not
+// reach the pseudoinverse update there.  Such blocks are projected by CGLS on
+// min ||A^J d - r^J|| started at d = 0, whose limit is the minimum-norm
+// least-squares solution (A^J)^+ r^J (for independent columns,
+// (A^J^T A^J)^-1 A^J^T r^J):
+//   res = r^J, s = A^J^T res, p = s, gam = ||s||^2
+//   step: q = A^J p; alpha = gam / ||q||^2; d += alpha p; res -= alpha q;
+//         s = A^J^T res; gam' = ||s||^2 (stop when gam' <= tol^2 gam_0);
+//         p = s + (gam'/gam) p
+//   x += d
+// The vector recurrences and their norms run in one workgroup (fixed
+// order); the products are listed-row dots and the thin row update (dense),
+// or listed CSR segment dots and a CSC pass over the residual scattered
+// onto the block's rows (sparse).  Ctrl::cg_rz[1] holds gam, cg_rz0[1] gam_0.
+constexpr int TL_NT = 1024;
+
+// d = 0, s = 0 (n); rhat = 0 (m); CG flags of the row phase reset
+template <typename T>
+__global__ void __launch_bounds__(256)
+tall_init(int64_t n, int64_t m, T *__restrict__ d, T *__restrict__ s,
+          T *__restrict__ rhat, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = i0; i < n; i += stride) { d[i] = (T)0; s[i] = (T)0; }
+  if (rhat)
+    for (int64_t i = i0; i < m; i += stride) rhat[i] = (T)0;
+  if (i0 == 0) { ctrl->cg_done[1] = 0; ctrl->cg_steps[1] = 0; }
+}
+
+// res_a = r[J_a] (and rhat[J_a] = res_a)
+template <typename T>
+__global__ void __launch_bounds__(256)
+tall_load(const int32_t *__restrict__ J, const int64_t *__restrict__ cnt,
+          const T *__restrict__ r, T *__restrict__ res, T *__restrict__ rhat,
+          Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  const int64_t c = *cnt;
+  for (int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x; a < c;
+       a += (int64_t)gridDim.x * 256) {
+    const T v = r[J[a]];
+    res[a] = v;
+    if (rhat) rhat[J[a]] = v;
+  }
+}
+
+// gam = gam_0 = ||s||^2, p = s
+template <typename T>
+__global__ void __launch_bounds__(TL_NT)
+tall_start(int64_t n, const T *__restrict__ s, T *__restrict__ p, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  __shared__ double sh[TL_NT / WAVE];
+  double g = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += TL_NT) {
+    const T v = s[i];
+    p[i] = v;
+    g += (double)v * (double)v;
+  }
+  g = block_sum<TL_NT>(g, sh);
+  if (threadIdx.x == 0) {
+    ctrl->cg_rz[1] = g;
+    ctrl->cg_rz0[1] = g;
+    if (!(g > 0.0)) ctrl->cg_done[1] = 1;
+  }
+}
+
+// dense q_a = <A_{J_a}, p>: one wave per listed row
+template <typename T>
+__global__ void __launch_bounds__(256)
+tall_rowdot(const T *__restrict__ A, int64_t ld, int64_t n,
+            const int32_t *__restrict__ J, const int64_t *__restrict__ cnt,
+            const T *__restrict__ p, T *__restrict__ q, Ctrl *ctrl) {
+  if (ctrl_done(ctrl) || ctrl->cg_done[1]) return;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t a = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+  if (a >= *cnt) return;
+  const T *row = A + (int64_t)J[a] * ld;
+  T acc = (T)0;
+  for (int64_t t = lane; t < n; t += WAVE) acc += row[t] * p[t];
+  acc = wave_sum(acc);
+  if (lane == 0) q[a] = acc;
+}
+
+// alpha = gam / ||q||^2; d += alpha p; res -= alpha q; then the input of the
+// next transpose product: s = 0 (dense, accumulated into) or rhat[J_a] = res_a
+template <typename T>
+__global__ void __launch_bounds__(TL_NT)
+tall_mid(int64_t n, const int32_t *__restrict__ J,
+         const int64_t *__restrict__ cnt, const T *__restrict__ p,
+         const T *__restrict__ q, T *__restrict__ d, T *__restrict__ res,
+         T *__restrict__ s, T *__restrict__ rhat, Ctrl *ctrl) {
+  if (ctrl_done(ctrl) || ctrl->cg_done[1]) return;
+  __shared__ double sh[TL_NT / WAVE];
+  const int64_t c = *cnt;
+  double qq = 0.0;
+  for (int64_t a = threadIdx.x; a < c; a += TL_NT)
+    qq += (double)q[a] * (double)q[a];
+  qq = block_sum<TL_NT>(qq, sh);
+  const double gam = ctrl->cg_rz[1];
+  if (!(qq > 0.0)) {
+    if (threadIdx.x == 0) ctrl->cg_done[1] = 1;
+    return;
+  }
+  const T alpha = (T)(gam / qq);
+  for (int64_t i = threadIdx.x; i < n; i += TL_NT) {
+    d[i] += alpha * p[i];
+    if (!rhat) s[i] = (T)0;
+  }
+  for (int64_t a = threadIdx.x; a < c; a += TL_NT) {
+    const T v = res[a] - alpha * q[a];
+    res[a] = v;
+    if (rhat) rhat[J[a]] = v;
+  }
+}
+
+// gam' = ||s||^2; stop at gam' <= tol^2 gam_0; p = s + (gam'/gam) p
+template <typename T>
+__global__ void __launch_bounds__(TL_NT)
+tall_end(int64_t n, const T *__restrict__ s, T *__restrict__ p, double tol,
+         int max_steps, Ctrl *ctrl) {
+  if (ctrl_done(ctrl) || ctrl->cg_done[1]) return;
+  __shared__ double sh[TL_NT / WAVE];
+  double g = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += TL_NT)
+    g += (double)s[i] * (double)s[i];
+  g = block_sum<TL_NT>(g, sh);
+  const double gam = ctrl->cg_rz[1];
+  const int steps = ctrl->cg_steps[1] + 1;
+  const bool stop = g <= tol * tol * ctrl->cg_rz0[1] || steps >= max_steps ||
+                    !(gam > 0.0);
+  if (!stop) {
+    const T beta = (T)(g / gam);
+    for (int64_t i = threadIdx.x; i < n; i += TL_NT) p[i] = s[i] + beta * p[i];
+  }
+  __syncthreads();   // every thread has read gam before it is replaced
+  if (threadIdx.x == 0) {
+    ctrl->cg_rz[1] = g;
+    ctrl->cg_steps[1] = steps;
+    if (stop) ctrl->cg_done[1] = 1;
+  }
+}
+
+// x += d
+template <typename T>
+__global__ void __launch_bounds__(256)
+tall_finish(int64_t n, const T *__restrict__ d, T *__restrict__ x, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256)
+    x[i] += d[i];
+}
+
+static unsigned tall_grid(int64_t len) {
+  int64_t g = (len + 255) / 256;
+  if (g > 1024) g = 1024;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+template <typename T>
+void launch_tall_rowproj_dense(const Dense<T> &A, const int32_t *J,
+                               const int64_t *count_dev, int64_t cap,
+                               const T *r, T *x, TallWork<T> &w, T *upd,
+                               int max_steps, double tol, Ctrl *ctrl,
+                               hipStream_t st) {
+  const int64_t n = A.cols;
+  hipLaunchKernelGGL(tall_init<T>, dim3(tall_grid(n)), dim3(256), 0, st, n,
+                     (int64_t)0, w.d, w.s, (T *)nullptr, ctrl);
+  hipLaunchKernelGGL(tall_load<T>, dim3(tall_grid(cap)), dim3(256), 0, st, J,
+                     count_dev, r, w.res, (T *)nullptr, ctrl);
+  thin_update<T>(A.a, A.ld, n, J, count_dev, cap, w.res, w.s, (T)1, upd, ctrl,
+                 1, st);
+  hipLaunchKernelGGL(tall_start<T>, dim3(1), dim3(TL_NT), 0, st, n,
+                     (const T *)w.s, w.p, ctrl);
+  const unsigned gq = (unsigned)((cap + 3) / 4);
+  for (int k = 0; k < max_steps; ++k) {
+    hipLaunchKernelGGL(tall_rowdot<T>, dim3(gq), dim3(256), 0, st, A.a, A.ld,
+                       n, J, count_dev, (const T *)w.p, w.q, ctrl);
+    hipLaunchKernelGGL(tall_mid<T>, dim3(1), dim3(TL_NT), 0, st, n, J,
+                       count_dev, (const T *)w.p, (const T *)w.q, w.d, w.res,
+                       w.s, (T *)nullptr, ctrl);
+    thin_update<T>(A.a, A.ld, n, J, count_dev, cap, w.res, w.s, (T)1, upd,
+                   ctrl, 1, st);
+    hipLaunchKernelGGL(tall_end<T>, dim3(1), dim3(TL_NT), 0, st, n,
+                       (const T *)w.s, w.p, tol, max_steps, ctrl);
+  }
+  hipLaunchKernelGGL(tall_finish<T>, dim3(tall_grid(n)), dim3(256), 0, st, n,
+                     (const T *)w.d, x, ctrl);
+}
+
+template <typename T>
+void launch_tall_rowproj_sparse(const Csr<T> &csr, const Csr<T> &csc,
+                                const int32_t *J, const int64_t *count_dev,
+                                int64_t cap, const T *r, T *x, TallWork<T> &w,
+                                int max_steps, double tol, Ctrl *ctrl,
+                                hipStream_t st) {
+  const int64_t n = csr.cols, m = csr.rows;
+  hipLaunchKernelGGL(tall_init<T>, dim3(tall_grid(std::max(n, m))), dim3(256),
+                     0, st, n, m, w.d, w.s, w.rhat, ctrl);
+  hipLaunchKernelGGL(tall_load<T>, dim3(tall_grid(cap)), dim3(256), 0, st, J,
+                     count_dev, r, w.res, w.rhat, ctrl);
+  SegArgs<T> tp;            // s = A^T rhat over the CSC
+  tp.v = w.rhat;
+  tp.out = w.s;
+  launch_segdot<T>(csc, EPI_STORE, tp, ctrl, 1, st);
+  hipLaunchKernelGGL(tall_start<T>, dim3(1), dim3(TL_NT), 0, st, n,
+                     (const T *)w.s, w.p, ctrl);
+  SegArgs<T> lp;            // q = A^J p over the listed CSR rows
+  lp.v = w.p;
+  lp.out = w.q;
+  lp.list = J;
+  lp.count_dev = count_dev;
+  lp.list_cap = cap;
+  for (int k = 0; k < max_steps; ++k) {
+    launch_segdot<T>(csr, EPI_LIST_STORE, lp, ctrl, 1, st);
+    hipLaunchKernelGGL(tall_mid<T>, dim3(1), dim3(TL_NT), 0, st, n, J,
+                       count_dev, (const T *)w.p, (const T *)w.q, w.d, w.res,
+                       w.s, w.rhat, ctrl);
+    launch_segdot<T>(csc, EPI_STORE, tp, ctrl, 1, st);
+    hipLaunchKernelGGL(tall_end<T>, dim3(1), dim3(TL_NT), 0, st, n,
+                       (const T *)w.s, w.p, tol, max_steps, ctrl);
+  }
+  hipLaunchKernelGGL(tall_finish<T>, dim3(tall_grid(n)), dim3(256), 0, st, n,
+                     (const T *)w.d, x, ctrl);
+}
+
+template void launch_tall_rowproj_dense<double>(const Dense<double> &, const int32_t *, const int64_t *, int64_t, const double *, double *, TallWork<double> &, double *, int, double, Ctrl *, hipStream_t);
+template void launch_tall_rowproj_dense<float>(const Dense<float> &, const int32_t *, const int64_t *, int64_t, const float *, float *, TallWork<float> &, float *, int, double, Ctrl *, hipStream_t);
+template void launch_tall_rowproj_sparse<double>(const Csr<double> &, const Csr<double> &, const int32_t *, const int64_t *, int64_t, const double *, double *, TallWork<double> &, int, double, Ctrl *, hipStream_t);
+template void launch_tall_rowproj_sparse<float>(const Csr<float> &, const Csr<float> &, const int32_t *, const int64_t *, int64_t, const float *, float *, TallWork<float> &, int, double, Ctrl *, hipStream_t);
 
 }  // namespace rg

@@ -102,6 +102,8 @@ struct Engine {
   CgWork<T> cgc, cgr;
   // sparse block work
   SparseCg<T> scc, scr;
+  TallWork<T> tall;          // row blocks taller than A is wide (CGLS)
+  bool tall_rows = false;
   SelectScratch sel;
   Reduce red;
   double *part = nullptr;     // row-residual partials
@@ -167,6 +169,21 @@ struct rgdbek_ctx {
     hipGraph_t graph = nullptr;
   };
   std::vector<GraphEntry> graphs;
+  // RGDBEK_FLAG_PROFILE: event-timed regions of the last solve
+  struct ProfRegion {
+    int cat = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+  };
+  std::vector<ProfRegion> prof_regions;   // enqueued this solve
+  std::vector<hipEvent_t> prof_events;    // pool, reused across solves
+  size_t prof_used_events = 0;
+  ProfRec *prof_log = nullptr;            // device: live flag, CG steps
+  int64_t prof_cap = 0;
+  struct ProfSum {
+    int64_t launches = 0;
+    double ms = 0.0;
+    int64_t steps = 0;
+  } prof[RGDBEK_PROF_COUNT];
 };
 
 static thread_local std::string g_global_err;
@@ -200,7 +217,7 @@ template <typename T>
 void alloc_gram_blocks(rgdbek_ctx *h, Engine<T> &e) {
   Pool &P = h->pool;
   e.GU = P.alloc<T>(e.kc * e.kc);
-  e.GJ = P.alloc<T>(e.kr * e.kr);
+  if (!e.tall_rows) e.GJ = P.alloc<T>(e.kr * e.kr);
   e.y = P.alloc<T>(e.kc);
   e.w = P.alloc<T>(e.kr);
   e.s = P.alloc<T>(e.kr);
@@ -228,6 +245,13 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   e.n = transpose ? h->m : h->n;
   e.kc = transpose ? h->kr : h->kc;
   e.kr = transpose ? h->kc : h->kr;
+  // row blocks with more rows than there are columns: CGLS projections
+  e.tall_rows = e.kr > e.n;
+  for (const SegInfo &g : h->hseg) {
+    const int64_t kr = transpose ? g.kc : g.kr;
+    const int64_t nc = transpose ? g.nrow : g.ncol;
+    if (kr > nc) e.tall_rows = true;
+  }
   const bool f64 = std::is_same<T, double>::value;
   const double wf = h->p.weight_floor;
   e.floor = wf > 0.0 ? wf : (wf < 0.0 ? 0.0 : (f64 ? 1e-20 : 1e-6));
@@ -398,6 +422,14 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   e.eps_z = P.alloc<T>(e.n + 64);
   e.off = P.alloc<T>(e.n + 64);
   e.U = P.alloc<int32_t>(e.kc + 64);
+  if (e.tall_rows) {
+    e.tall.d = P.alloc<T>(e.n + 64);
+    e.tall.p = P.alloc<T>(e.n + 64);
+    e.tall.s = P.alloc<T>(e.n + 64);
+    e.tall.res = P.alloc<T>(e.kr + 64);
+    e.tall.q = P.alloc<T>(e.kr + 64);
+    if (!e.dense) e.tall.rhat = P.alloc<T>(e.m + 64);
+  }
   e.J = P.alloc<int32_t>(e.kr + 64);
   const int64_t dmax = std::max(e.m, e.n);
   e.sel.keys = P.alloc<uint64_t>(dmax + 64, false);
@@ -451,6 +483,75 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
   e.ready = true;
 }
 
+// ------------------------------------------------------------ profiling
+// With RGDBEK_FLAG_PROFILE every group of launches of an iteration (one
+// region: a residual pass, a draw, a block solve, an update, the stop test)
+// is bracketed by HIP events on the handle's stream, plus two tiny marks
+// outside the events: whether the solve was still running when the region
+// started, and the CG steps its block solve took.  Regions of iterations
+// skipped after the stop test are not counted.
+hipEvent_t prof_event(rgdbek_ctx *h) {
+  if (h->prof_used_events == h->prof_events.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    h->prof_events.push_back(e);
+  }
+  return h->prof_events[h->prof_used_events++];
+}
+
+struct ProfScope {
+  rgdbek_ctx *h;
+  int cat, ph;
+  int64_t idx = -1;
+  ProfScope(rgdbek_ctx *hh, int c, int phase = -1) : h(hh), cat(c), ph(phase) {
+    if (!(h->p.flags & RGDBEK_FLAG_PROFILE) || !h->prof_log) return;
+    if ((int64_t)h->prof_regions.size() >= h->prof_cap) return;
+    idx = (int64_t)h->prof_regions.size();
+    rgdbek_ctx::ProfRegion r;
+    r.cat = cat;
+    r.e0 = prof_event(h);
+    r.e1 = prof_event(h);
+    launch_prof_mark(h->ctrl, h->prof_log + idx, 0, ph, h->st);
+    HIPCHK(hipEventRecord(r.e0, h->st));
+    h->prof_regions.push_back(r);
+  }
+  ~ProfScope() {
+    if (idx < 0) return;
+    // an error here resurfaces at the solve's next HIP call
+    (void)hipEventRecord(h->prof_regions[idx].e1, h->st);
+    launch_prof_mark(h->ctrl, h->prof_log + idx, 1, ph, h->st);
+  }
+};
+
+void prof_begin_solve(rgdbek_ctx *h) {
+  if (!(h->p.flags & RGDBEK_FLAG_PROFILE)) return;
+  if (!h->prof_log) {
+    h->prof_cap = 1 << 16;
+    h->prof_log = h->pool.alloc<ProfRec>(h->prof_cap);
+  }
+  h->prof_regions.clear();
+  h->prof_used_events = 0;
+  for (auto &p : h->prof) p = rgdbek_ctx::ProfSum{};
+}
+
+void prof_end_solve(rgdbek_ctx *h) {
+  if (!(h->p.flags & RGDBEK_FLAG_PROFILE) || h->prof_regions.empty()) return;
+  HIPCHK(hipStreamSynchronize(h->st));
+  std::vector<ProfRec> log(h->prof_regions.size());
+  HIPCHK(hipMemcpy(log.data(), h->prof_log, sizeof(ProfRec) * log.size(),
+                   hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < log.size(); ++i) {
+    if (!log[i].live) continue;
+    const auto &r = h->prof_regions[i];
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
+    auto &sum = h->prof[r.cat];
+    sum.launches += 1;
+    sum.ms += ms;
+    sum.steps += log[i].steps;
+  }
+}
+
 // ------------------------------------------------------------ iteration
 struct IterOpts {
   uint64_t key1 = 0;
@@ -497,6 +598,7 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
 
   const int ns = e.nseg;
   if (o.stop == RGDBEK_STOP_ERR_REF) {
+    ProfScope ps(h, RGDBEK_PROF_STOP);
     if (ns) {
       launch_seg_err_ref<T>(e.x, o.xref, o.xbase, e.seg, ns, c, 1, st);
       launch_seg_fold(e.seg, ns, c, 0, p.max_iter, 0, st);
@@ -505,6 +607,8 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     }
   }
   // ---- column phase: g = A^T z (+ t), eps^z, select U, project z
+  {
+  ProfScope ps(h, RGDBEK_PROF_COL_RESIDUAL);
   if (e.dense) {
     launch_dense_fused<T>(e.arm, e.x, e.z, e.dw, off, e.kappa, e.g, e.eps_z,
                           e.q, c, 1, st);
@@ -513,6 +617,9 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     a.v = e.z; a.g = e.g; a.off = off; a.eps = e.eps_z; a.nrm = e.kappa;
     launch_segdot<T>(e.csc, EPI_COLRES, a, c, 1, st);
   }
+  }
+  {
+  ProfScope ps(h, RGDBEK_PROF_COL_DRAW);
   if (ns)
     launch_select_seg<T>(e.eps_z, e.seg, ns, 0, e.seg_dmax[0], e.floor, p.seed,
                          o.key1, 0, e.sel.keys, e.segmax, e.seltmp, e.selcnt,
@@ -528,6 +635,7 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
   else
     launch_select<T>(e.eps_z, e.n, e.kc, e.floor, p.seed, o.key1, 0, 0, 0,
                      e.sel, e.U, c, 1, st);
+  }
   const bool chol_c = p.solver == RGDBEK_SOLVER_CHOL ||
                       (p.solver == RGDBEK_SOLVER_AUTO && e.kc <= 256);
   const bool chol_r = p.solver == RGDBEK_SOLVER_CHOL ||
@@ -535,6 +643,8 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
   const bool cg_c = !(chol_c && e.kc <= CHOL_MAX);
   const bool cg_r = !(chol_r && e.kr <= CHOL_MAX);
   if (e.dense) {
+    {
+    ProfScope ps(h, RGDBEK_PROF_COL_SOLVE, 0);
     if (cg_c && e.ata) {
       pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0,
                    e.ata, e.n);
@@ -549,9 +659,13 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       else
         launch_chol_solve<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, 1, c, 0, 1, st);
     }
+    }
+    ProfScope pu(h, RGDBEK_PROF_COL_UPDATE);
     launch_col_update<T>(e.acm.a, e.acm.ld, e.m, e.U, cntU, e.kc, e.y, e.z,
                          e.upd, c, 1, st);
   } else if (e.sgram) {
+    {
+    ProfScope ps(h, RGDBEK_PROF_COL_SOLVE, 0);
     if (cg_c) {
       pcg_solve<T>(h, e.GU, e.kc, cntU, e.g, e.U, e.y, e.cgc, maxs, itol, 0,
                    e.ata, e.n);
@@ -559,14 +673,19 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_gram_gather<T>(e.ata, e.n, e.U, cntU, e.kc, e.GU, c, 1, st);
       launch_chol_solve<T>(e.GU, e.kc, cntU, e.g, e.U, e.y, 1, c, 0, 1, st);
     }
+    }
+    ProfScope pu(h, RGDBEK_PROF_COL_UPDATE);
     launch_sparse_block_update<T>(e.csr, e.U, cntU, e.kc, e.y, -1, e.scc.phat,
                                   e.z, c, 1, st);
   } else {
+    ProfScope ps(h, RGDBEK_PROF_COL_SOLVE, 0);
     launch_sparse_colproj<T>(e.csr, e.csc, e.U, cntU, e.kc, e.g, e.z, e.scc,
                              maxs, itol, c, 1, st);
   }
   // ---- row phase: r = b - z - A x, eps^x, stop test, select J, project x
   int nparts;
+  {
+  ProfScope ps(h, RGDBEK_PROF_ROW_RESIDUAL);
   if (e.dense) {
     nparts = launch_rowres_dense<T>(e.m, e.b, e.z, e.q, e.rho, e.r, e.eps_x,
                                     e.part, c, 1, st);
@@ -576,7 +695,9 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     a.nrm = e.rho; a.part = e.part;
     nparts = launch_segdot<T>(e.csr, EPI_ROWRES, a, c, 1, st);
   }
+  }
   if (o.stop == RGDBEK_STOP_RSE || o.stop == RGDBEK_STOP_RES_EXT) {
+    ProfScope ps(h, RGDBEK_PROF_STOP);
     if (ns) {
       launch_seg_stop_rowres<T>(e.r, e.z, e.seg, ns, o.stop, c, 1, st);
       launch_seg_fold(e.seg, ns, c, 0, p.max_iter, 0, st);
@@ -584,6 +705,8 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_stop_rowres(e.part, nparts, c, st);
     }
   }
+  {
+  ProfScope ps(h, RGDBEK_PROF_ROW_DRAW);
   if (ns)
     launch_select_seg<T>(e.eps_x, e.seg, ns, 1, e.seg_dmax[1], e.floor, p.seed,
                          o.key1, 1, e.sel.keys, e.segmax, e.seltmp, e.selcnt,
@@ -599,7 +722,18 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
   else
     launch_select<T>(e.eps_x, e.m, e.kr, e.floor, p.seed, o.key1, 1, 0, 1,
                      e.sel, e.J, c, 1, st);
-  if (e.dense) {
+  }
+  if (e.tall_rows) {
+    ProfScope ps(h, RGDBEK_PROF_ROW_SOLVE, 1);
+    if (e.dense)
+      launch_tall_rowproj_dense<T>(e.arm, e.J, cntJ, e.kr, e.r, e.x, e.tall,
+                                   e.upd, maxs, itol, c, st);
+    else
+      launch_tall_rowproj_sparse<T>(e.csr, e.csc, e.J, cntJ, e.kr, e.r, e.x,
+                                    e.tall, maxs, itol, c, st);
+  } else if (e.dense) {
+    {
+    ProfScope ps(h, RGDBEK_PROF_ROW_SOLVE, 1);
     if (!cg_r || !e.aat) {
       if (e.aat)
         launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
@@ -609,6 +743,13 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
     }
     if (!cg_r) {
       launch_chol_solve<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, 1, c, 1, 1, st);
+    } else {
+      pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1,
+                   e.aat, e.m);
+    }
+    }
+    ProfScope pu(h, RGDBEK_PROF_ROW_UPDATE);
+    if (!cg_r) {
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
       // corrected semi-normal equations: one sweep with the residual of the
@@ -620,12 +761,12 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
     } else {
-      pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1,
-                   e.aat, e.m);
       launch_row_update<T>(e.arm.a, e.arm.ld, e.n, e.J, cntJ, e.kr, e.w, e.x,
                            e.upd, c, 1, st);
     }
   } else if (e.sgram) {
+    {
+    ProfScope ps(h, RGDBEK_PROF_ROW_SOLVE, 1);
     if (cg_r) {
       pcg_solve<T>(h, e.GJ, e.kr, cntJ, e.r, e.J, e.w, e.cgr, maxs, itol, 1,
                    e.aat, e.m);
@@ -633,12 +774,16 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
       launch_gram_gather<T>(e.aat, e.m, e.J, cntJ, e.kr, e.GJ, c, 1, st);
       launch_chol_solve<T>(e.GJ, e.kr, cntJ, e.r, e.J, e.w, 1, c, 1, 1, st);
     }
+    }
+    ProfScope pu(h, RGDBEK_PROF_ROW_UPDATE);
     launch_sparse_block_update<T>(e.csc, e.J, cntJ, e.kr, e.w, 1, e.scr.phat,
                                   e.x, c, 1, st);
   } else {
+    ProfScope ps(h, RGDBEK_PROF_ROW_SOLVE, 1);
     launch_sparse_rowproj<T>(e.csr, e.csc, e.J, cntJ, e.kr, e.r, e.rho, e.x,
                              e.scr, maxs, itol, c, 1, st);
   }
+  ProfScope ps(h, RGDBEK_PROF_STOP);
   if (ns) launch_seg_fold(e.seg, ns, c, 1, p.max_iter, 0, st);
   else launch_end_iter(c, st);
 }
@@ -701,7 +846,8 @@ void ctrl_fetch(rgdbek_ctx *h) {
 // Run iterations until done; the host looks at the device flag once per graph.
 template <typename T>
 void run_loop(rgdbek_ctx *h, Engine<T> &e, int which, const IterOpts &o) {
-  const bool use_graph = (h->p.flags & RGDBEK_FLAG_GRAPH) != 0;
+  const bool use_graph = (h->p.flags & RGDBEK_FLAG_GRAPH) != 0 &&
+                         !(h->p.flags & RGDBEK_FLAG_PROFILE);
   hipGraphExec_t ge = use_graph ? get_graph<T>(h, e, which, o) : nullptr;
   while (true) {
     if (use_graph) {
@@ -770,6 +916,7 @@ rgdbek_status solve64(rgdbek_ctx *h, Engine<double> &e, int which,
     x_ref = h->xref;
   }
   check_b(h, b, e.m);
+  prof_begin_solve(h);
   HIPCHK(hipMemcpyAsync(e.b, b, sizeof(double) * e.m, hipMemcpyDeviceToDevice, st));
   if (resume) {
     HIPCHK(hipMemcpyAsync(e.x, x, sizeof(double) * e.n, hipMemcpyDeviceToDevice, st));
@@ -806,22 +953,30 @@ rgdbek_status solve64(rgdbek_ctx *h, Engine<double> &e, int which,
   ctrl_fetch(h);
   const double secs = std::chrono::duration<double>(
                           std::chrono::steady_clock::now() - t0).count();
+  prof_end_solve(h);
   return finish_status(h, info, secs, 1);
 }
 
 // ------------------------------------------------------------ mixed solve
-// Refinement with FP32 inner RGDBEK.  FP64 state x; each pass:
+// Refinement with FP32 inner RGDBEK.  FP64 state (x, z); each pass:
+//   stop test in FP64 on the state (ERR_REF on x; RSE on b - A x; RES_EXT on
+//   b - z - A x with the carried z, from the second pass on)
 //   z = b - A x                        (FP64, so z - b stays in range(A))
 //   t = A^T z                          (FP64, the normal-equation residual)
 //   FP32 RGDBEK on the correction (dx, dz) from (0, 0): column residual
 //   A^T dz + t, row residual -dz - A dx (right-hand side s = b - z - A x = 0)
-//   x += dx (FP64)
+//   x += dx, z += dz (FP64)
 // The fixed point of a pass is x + dx = A^+ b exactly; FP32 only limits how
 // far one pass contracts the error (about u_32 * cond).  Carrying z across
 // passes instead would freeze FP32 rounding in its null(A^T) component and
-// stall the refinement.  An inner pass ends when the global stop test holds
-// on x + dx, or when its metric has not improved by 5% for 4 graphs.
-constexpr double MIXED_PASS_DROP = 1e-5;
+// stall the refinement.  An inner pass ends on residuals only: its FP32
+// extended residual ||dz + A dx|| (the extended residual b - z - A x of the
+// refined state) falls to pass_drop (default 1e-5) times its first value in the pass
+// (or to tol for an outer RES_EXT test), on an FP32 plateau (no 1% gain over
+// 8 graphs once the residual is falling), or, after the first pass, at twice
+// the first pass's length.  The outer loop ends when the FP64 test holds, or
+// when a pass no longer cuts the FP64 metric by 10%.
+constexpr double MIXED_PASS_DROP = 1e-5;   // default pass_drop
 
 rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
                           const double *x_ref_user, rgdbek_info *info) {
@@ -837,44 +992,70 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
   Engine<float> &F = h->e32;
   const int stop = h->p.stop;
   check_b(h, b, E.m);
+  prof_begin_solve(h);
   HIPCHK(hipMemcpyAsync(E.b, b, sizeof(double) * E.m, hipMemcpyDeviceToDevice, st));
   launch_axpby<double, double>(E.n, 0.0, h->x64, 0.0, (const double *)nullptr, st);
+  HIPCHK(hipMemcpyAsync(h->z64, b, sizeof(double) * E.m, hipMemcpyDeviceToDevice, st));
   if (E.nseg) {
     HIPCHK(hipMemsetAsync(h->fixed, 0, sizeof(int32_t) * E.nseg, st));
     launch_seg_reset(E.seg, E.nseg, 0, 0, nullptr, st);
   }
-  int64_t total_it = 0, outer = 0;
+  int64_t total_it = 0, outer = 0, pass1_its = -1;
   const int max_outer = 12;
   double metric = 0.0, prev_metric = 1e300;
   bool converged = false;
   int numeric = 0, sync_fail = 0;
   for (outer = 1; outer <= max_outer; ++outer) {
-    // z = b - A x and the stop metric, then t = A^T z (FP64 passes)
-    ctrl_reset(h, 0, 1, stop, h->p.tol);
+    // the FP64 stop test, then z = b - A x and t = A^T z (FP64 passes).
+    // RES_EXT uses the carried z; before the first pass (x = 0, z = b) it
+    // holds trivially, so it is first tested after one pass.
+    const bool test_now = stop != RGDBEK_STOP_NONE &&
+                          !(stop == RGDBEK_STOP_RES_EXT && outer == 1);
+    ctrl_reset(h, 0, 1, test_now ? stop : RGDBEK_STOP_NONE, h->p.tol);
     int nparts;
+    {
+    ProfScope pr(h, RGDBEK_PROF_REFINE);
     if (E.dense) {
       launch_dense_fused<double>(E.arm, h->x64, h->z64, E.dw, nullptr, E.kappa,
                                  h->t64, E.eps_z, E.q, h->ctrl, 0, st);
-      nparts = launch_rowres_dense<double>(E.m, E.b, h->zero64, E.q, E.rho,
-                                           h->z64, E.eps_x, E.part, h->ctrl, 0,
-                                           st);
+      if (stop == RGDBEK_STOP_RES_EXT) {
+        // r = b - z - A x with the carried z; then b - A x = r + z
+        nparts = launch_rowres_dense<double>(E.m, E.b, h->z64, E.q, E.rho,
+                                             E.r, E.eps_x, E.part, h->ctrl, 0,
+                                             st);
+        launch_axpby<double, double>(E.m, 1.0, h->z64, 1.0, E.r, st);
+      } else {
+        nparts = launch_rowres_dense<double>(E.m, E.b, h->zero64, E.q, E.rho,
+                                             h->z64, E.eps_x, E.part, h->ctrl,
+                                             0, st);
+      }
       launch_dense_fused<double>(E.arm, h->x64, h->z64, E.dw, nullptr, E.kappa,
                                  h->t64, E.eps_z, E.q, h->ctrl, 0, st);
     } else {
       SegArgs<double> r;
-      r.v = h->x64; r.b = E.b; r.z = h->zero64; r.r = h->z64; r.eps = E.eps_x;
-      r.nrm = E.rho; r.part = E.part;
+      r.v = h->x64; r.b = E.b; r.eps = E.eps_x; r.nrm = E.rho; r.part = E.part;
+      if (stop == RGDBEK_STOP_RES_EXT) {
+        r.z = h->z64; r.r = E.r;
+      } else {
+        r.z = h->zero64; r.r = h->z64;
+      }
       nparts = launch_segdot<double>(E.csr, EPI_ROWRES, r, h->ctrl, 0, st);
+      if (stop == RGDBEK_STOP_RES_EXT)
+        launch_axpby<double, double>(E.m, 1.0, h->z64, 1.0, E.r, st);
       SegArgs<double> a;
       a.v = h->z64; a.g = h->t64; a.eps = E.eps_z; a.nrm = E.kappa;
       launch_segdot<double>(E.csc, EPI_COLRES, a, h->ctrl, 0, st);
     }
-    if (E.nseg && stop != RGDBEK_STOP_NONE) {
+    if (E.nseg && test_now) {
       launch_seg_reset(E.seg, E.nseg, 0, 1, nullptr, st);
       if (stop == RGDBEK_STOP_ERR_REF) {
         launch_seg_ref2<double>(x_ref, E.seg, E.nseg, 1, st);
         launch_seg_err_ref<double>(h->x64, x_ref, nullptr, E.seg, E.nseg,
                                    h->ctrl, 0, st);
+      } else if (stop == RGDBEK_STOP_RES_EXT) {
+        launch_seg_ref2<double>(E.b, E.seg, E.nseg, 0, st);
+        launch_seg_stop_rowres<double>(E.r, h->zero64, E.seg, E.nseg, stop,
+                                       h->ctrl, 0, st);
       } else {
         launch_seg_ref2<double>(E.b, E.seg, E.nseg, 0, st);
         launch_seg_stop_rowres<double>(h->z64, h->zero64, E.seg, E.nseg,
@@ -882,68 +1063,67 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
       }
       launch_seg_fold(E.seg, E.nseg, h->ctrl, 0, h->p.max_iter, 1, st);
       launch_seg_converged(E.seg, E.nseg, h->fixed, st);
-    } else if (stop == RGDBEK_STOP_ERR_REF) {
+    } else if (test_now && stop == RGDBEK_STOP_ERR_REF) {
       launch_set_ref2<double>(E.n, x_ref, h->ctrl, st);
       launch_err_ref<double>(E.n, h->x64, x_ref, nullptr, E.red, h->ctrl, 0, st);
-    } else if (stop == RGDBEK_STOP_RSE) {
+    } else if (test_now) {
       launch_set_ref2<double>(E.m, E.b, h->ctrl, st);
       launch_stop_rowres(E.part, nparts, h->ctrl, st);
     }
+    }
     ctrl_fetch(h);
     metric = h->hctrl->metric;
-    if (E.nseg && stop != RGDBEK_STOP_NONE && h->hctrl->converged) {
-      converged = true;
-      break;
-    }
     if (trace_on())
       std::fprintf(stderr, "[rgdbek] pass %lld fp64 metric %.3e (inner its so far %lld)\n",
                    (long long)outer, metric, (long long)total_it);
-    if (!E.nseg && stop != RGDBEK_STOP_NONE && metric <= h->p.tol) {
+    if (test_now && h->hctrl->converged) {
       converged = true;
       break;
     }
     if (total_it >= h->p.max_iter) break;
-    // refinement stalled: a pass that no longer cuts the error by 10%
-    if (outer > 2 && metric > 0.9 * prev_metric) break;
-    prev_metric = metric;
+    // refinement stalled: a pass that no longer cuts the metric by 10%
+    if (test_now && outer > 2 && metric > 0.9 * prev_metric) break;
+    if (test_now) prev_metric = metric;
     // FP32 pass on the correction system: s = 0, offset t
     launch_axpby<float, float>(F.m, 0.0, F.b, 0.0, (const float *)nullptr, st);
     launch_convert<float, double>(h->t64, F.off, E.n, st);
     launch_axpby<float, float>(F.n, 0.0, F.x, 0.0, (const float *)nullptr, st);
     launch_axpby<float, float>(F.m, 0.0, F.z, 0.0, (const float *)nullptr, st);
-    const int istop = (stop == RGDBEK_STOP_ERR_REF) ? RGDBEK_STOP_ERR_REF
-                      : (stop == RGDBEK_STOP_NONE ? RGDBEK_STOP_NONE
-                                                  : RGDBEK_STOP_RES_EXT);
-    // inner RES_EXT runs with tol 0: it only feeds the stall detector.  An
-    // inner ERR_REF pass stops at the global tolerance or once it has cut
-    // the error of this pass by MIXED_PASS_DROP: FP32 rounding of the
-    // correction limits one pass to roughly u_32 * cond(A), so iterating
-    // further only burns iterations the next pass redoes in FP64 context.
-    const double itol = istop == RGDBEK_STOP_ERR_REF
-                            ? std::max(h->p.tol, MIXED_PASS_DROP * metric)
-                            : 0.0;
-    ctrl_reset(h, total_it, h->p.max_iter - total_it, istop, itol);
-    if (istop == RGDBEK_STOP_ERR_REF) launch_set_ref2<double>(E.n, x_ref, h->ctrl, st);
-    else launch_set_ref2<double>(E.m, E.b, h->ctrl, st);
+    const int istop = stop == RGDBEK_STOP_NONE ? RGDBEK_STOP_NONE
+                                               : RGDBEK_STOP_RES_EXT;
+    ctrl_reset(h, total_it, h->p.max_iter - total_it, istop,
+               stop == RGDBEK_STOP_RES_EXT ? h->p.tol : 0.0);
+    if (istop == RGDBEK_STOP_RES_EXT) {
+      h->hctrl->pass_drop = h->p.pass_drop > 0.0 ? h->p.pass_drop
+                                                 : MIXED_PASS_DROP;
+      HIPCHK(hipMemcpyAsync(&h->ctrl->pass_drop, &h->hctrl->pass_drop,
+                            sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    launch_set_ref2<double>(E.m, E.b, h->ctrl, st);
     if (E.nseg) {
       launch_seg_reset(E.seg, E.nseg, 0, 1, h->fixed, st);
-      if (istop == RGDBEK_STOP_ERR_REF) launch_seg_ref2<double>(x_ref, E.seg, E.nseg, 1, st);
-      else launch_seg_ref2<double>(E.b, E.seg, E.nseg, 0, st);
+      launch_seg_ref2<double>(E.b, E.seg, E.nseg, 0, st);
     }
     IterOpts o;
     o.key1 = 0;
     o.stop = istop;
-    o.xref = istop == RGDBEK_STOP_ERR_REF ? x_ref : nullptr;
-    o.xbase = istop == RGDBEK_STOP_ERR_REF ? h->x64 : nullptr;
     o.use_off = true;
     {
-      const bool use_graph = (h->p.flags & RGDBEK_FLAG_GRAPH) != 0;
+      const bool use_graph = (h->p.flags & RGDBEK_FLAG_GRAPH) != 0 &&
+                         !(h->p.flags & RGDBEK_FLAG_PROFILE);
       hipGraphExec_t ge = use_graph ? get_graph<float>(h, F, 2, o) : nullptr;
-      double best = 1e300;
-      // FP32 plateau: the best metric has not improved by 1% over `window`
-      // graphs (a slowly converging pass still gains far more than that)
+      // The extended residual of a pass that starts from a nonzero state
+      // first grows (the column steps remove components of z faster than
+      // the row steps let A x follow), then falls.  FP32 plateau: once it
+      // has fallen below its first reading, the best value has not improved
+      // by 1% over `window` graphs.  Passes after the first are also capped
+      // at twice the first pass's length (each cuts the error by about the
+      // same factor).
+      double first = -1.0, best = 1e300;
+      bool falling = false;
       int since_best = 0;
       const int window = 8;
+      const int64_t cap = pass1_its > 0 ? 2 * pass1_its + graph_iters(h) : -1;
       while (true) {
         if (use_graph) HIPCHK(hipGraphLaunch(ge, st));
         else for (int i = 0; i < graph_iters(h); ++i) enqueue_iteration<float>(h, F, o);
@@ -960,12 +1140,16 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
                        (long long)h->hctrl->iters_run, h->hctrl->metric,
                        h->hctrl->done);
         if (h->hctrl->done) break;
+        if (cap > 0 && h->hctrl->iters_run >= cap) break;
         const double mt = h->hctrl->metric;
+        if (first < 0.0) first = mt;
+        if (!falling && mt < first) falling = true;
         if (mt < 0.99 * best) { best = mt; since_best = 0; }
-        else if (++since_best >= window) break;
+        else if (falling && ++since_best >= window) break;
       }
     }
     ctrl_fetch(h);
+    if (pass1_its < 0) pass1_its = h->hctrl->iters_run;
     total_it += h->hctrl->iters_run;
     numeric |= h->hctrl->numeric;
     sync_fail |= h->hctrl->sync_fail;
@@ -981,6 +1165,7 @@ rgdbek_status solve_mixed(rgdbek_ctx *h, const double *b, double *x,
   HIPCHK(hipStreamSynchronize(st));
   const double secs = std::chrono::duration<double>(
                           std::chrono::steady_clock::now() - t0).count();
+  prof_end_solve(h);
   Ctrl &c = *h->hctrl;
   c.iters_run = total_it;
   c.metric = metric;
@@ -1011,14 +1196,10 @@ void validate_params(const rgdbek_params *p, int64_t m, int64_t n,
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "block sizes must be positive"};
   if (p->stop < RGDBEK_STOP_NONE || p->stop > RGDBEK_STOP_RES_EXT)
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "unknown stop mode"};
-  if (p->precision < RGDBEK_PREC_FP64 || p->precision > RGDBEK_PREC_MIXED_BF16)
+  if (p->precision < RGDBEK_PREC_FP64 || p->precision > RGDBEK_PREC_MIXED_F32)
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "unknown precision"};
-  if (p->precision == RGDBEK_PREC_MIXED_BF16)
-    throw ApiError{RGDBEK_ERR_UNSUPPORTED, "bfloat16 inner values are not built"};
-  if (p->precision == RGDBEK_PREC_MIXED_F32 && p->stop == RGDBEK_STOP_RES_EXT)
-    throw ApiError{RGDBEK_ERR_UNSUPPORTED,
-                   "the mixed form restarts z = b - A x each pass; use ERR_REF, "
-                   "RSE or NONE"};
+  if (!(p->pass_drop >= 0.0) || p->pass_drop >= 1.0)
+    throw ApiError{RGDBEK_ERR_INVALID_ARG, "pass_drop must lie in [0, 1)"};
   if (p->max_iter < 0 || !(p->tol >= 0.0))
     throw ApiError{RGDBEK_ERR_INVALID_ARG, "max_iter and tol must be >= 0"};
   if (p->solver < 0 || p->solver > RGDBEK_SOLVER_CG)
@@ -1130,10 +1311,18 @@ void build_merge_plan(rgdbek_ctx *h, const int64_t *ptr_dev, int64_t rows,
 void create_impl(rgdbek_ctx *h, const rgdbek_matrix *A) {
   hipStream_t st = h->st;
   Pool &P = h->pool;
-  if (h->dense && std::max(h->kc, h->kr) > pcg_cap_max())
+  // Gram-based dense blocks are limited by the PCG's staging; row blocks
+  // taller than A is wide go through CGLS and have no such limit (the
+  // adjoint engine swaps the roles: its row blocks are the column blocks)
+  if (h->dense && h->kc > pcg_cap_max())
     throw ApiError{RGDBEK_ERR_UNSUPPORTED,
-                   "dense blocks larger than " + std::to_string(pcg_cap_max()) +
-                       " are not supported"};
+                   "dense column blocks larger than " +
+                       std::to_string(pcg_cap_max()) + " are not supported"};
+  if (h->dense && (h->kr > pcg_cap_max() && h->kr <= h->n))
+    throw ApiError{RGDBEK_ERR_UNSUPPORTED,
+                   "dense row blocks larger than " +
+                       std::to_string(pcg_cap_max()) +
+                       " are not supported unless taller than A is wide"};
   h->ctrl = P.alloc<Ctrl>(1);
   HIPCHK(hipHostMalloc((void **)&h->hctrl, sizeof(Ctrl), hipHostMallocDefault));
   int *flag = P.alloc<int>(1);
@@ -1242,6 +1431,8 @@ void destroy_impl(rgdbek_ctx *h) {
     if (g.graph) (void)hipGraphDestroy(g.graph);
   }
   h->graphs.clear();
+  for (hipEvent_t e : h->prof_events) (void)hipEventDestroy(e);
+  h->prof_events.clear();
   h->pool.release();
   if (h->hctrl) (void)hipHostFree(h->hctrl);
   h->hctrl = nullptr;
@@ -1633,6 +1824,12 @@ rgdbek_status rgdbek_solve_adjoint(rgdbek_handle h, const void *g, void *w,
   if (!g || !w) { set_err(h, "g and w are required"); return RGDBEK_ERR_INVALID_ARG; }
   return guarded(h, [&]() {
     HIPCHK(hipStreamSynchronize(h->user_st));
+    // the adjoint's column blocks are the forward row blocks: a tall row
+    // block above the Gram limit has no column projection on A^T
+    if (h->dense && h->kr > pcg_cap_max())
+      throw ApiError{RGDBEK_ERR_UNSUPPORTED,
+                     "adjoint solve: dense row blocks larger than " +
+                         std::to_string(pcg_cap_max()) + " are not supported"};
     if (!h->e64t.ready) build_engine<double>(h, h->e64t, true);
     int stop = h->p.stop == RGDBEK_STOP_ERR_REF ? RGDBEK_STOP_RES_EXT : h->p.stop;
     return solve64(h, h->e64t, 1, 1, stop, (const double *)g, (double *)w,
@@ -1870,6 +2067,25 @@ rgdbek_status rgdbek_select_threshold(const double *eps, int64_t d, double eta,
   });
   P.release();
   return s;
+}
+
+rgdbek_status rgdbek_profile_read(rgdbek_handle h, int32_t region,
+                                  int64_t *launches, double *ms,
+                                  int64_t *steps) {
+  if (!h) return RGDBEK_ERR_INVALID_ARG;
+  if (region < 0 || region >= RGDBEK_PROF_COUNT) {
+    set_err(h, "unknown profile region");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (!(h->p.flags & RGDBEK_FLAG_PROFILE)) {
+    set_err(h, "the handle was created without RGDBEK_FLAG_PROFILE");
+    return RGDBEK_ERR_UNSUPPORTED;
+  }
+  const auto &r = h->prof[region];
+  if (launches) *launches = r.launches;
+  if (ms) *ms = r.ms;
+  if (steps) *steps = r.steps;
+  return RGDBEK_OK;
 }
 
 rgdbek_status rgdbek_destroy(rgdbek_handle h) {

@@ -655,6 +655,7 @@ template void launch_set_ref2<float>(int64_t, const float *, Ctrl *,
 
 // RSE  : sum(b - Ax)^2 / ||b||^2 <= tol
 // RES_EXT: sqrt(sum r^2 / ||b||^2) <= tol
+// (or <= pass_drop times the first metric of a mixed-form refinement pass)
 __global__ void __launch_bounds__(256)
 stop_rowres_kernel(const double *__restrict__ part, int nparts, Ctrl *ctrl) {
   if (ctrl_done(ctrl)) return;
@@ -672,7 +673,13 @@ stop_rowres_kernel(const double *__restrict__ part, int nparts, Ctrl *ctrl) {
     const double den = ctrl->ref2 > 0.0 ? ctrl->ref2 : 1.0;
     const double metric = (mode == 2) ? pb / den : sqrt(pr / den);
     ctrl->metric = metric;
-    if (metric <= ctrl->tol) { ctrl->done = 1; ctrl->converged = 1; }
+    double thr = ctrl->tol;
+    if (ctrl->pass_drop > 0.0) {
+      if (ctrl->pass_ref <= 0.0) ctrl->pass_ref = metric;
+      const double rel = ctrl->pass_drop * ctrl->pass_ref;
+      thr = rel > thr ? rel : thr;
+    }
+    if (metric <= thr) { ctrl->done = 1; ctrl->converged = 1; }
   }
 }
 void launch_stop_rowres(const double *part, int nparts, Ctrl *ctrl,
@@ -697,6 +704,18 @@ __global__ void fill_it_kernel(Ctrl *ctrl, int64_t it) {
 }
 void launch_fill_ctrl_it(Ctrl *ctrl, int64_t it, hipStream_t st) {
   hipLaunchKernelGGL(fill_it_kernel, dim3(1), dim3(64), 0, st, ctrl, it);
+}
+
+__global__ void prof_mark_kernel(const Ctrl *ctrl, ProfRec *rec, int post,
+                                 int ph) {
+  if (threadIdx.x != 0) return;
+  if (post == 0) rec->live = ctrl->done ? 0 : 1;
+  else rec->steps = ph >= 0 ? ctrl->cg_steps[ph] : 0;
+}
+void launch_prof_mark(const Ctrl *ctrl, ProfRec *rec, int post, int ph,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(prof_mark_kernel, dim3(1), dim3(64), 0, st, ctrl, rec,
+                     post, ph);
 }
 
 }  // namespace rg

@@ -40,7 +40,8 @@ class Solver:
                  precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
                  solver=B.SOLVER_AUTO, graph=True, gram_aat=False,
                  weight_floor=0.0, tile_rows=0, select="random",
-                 cg_split=False, sparse_cg=False, stream=None):
+                 cg_split=False, sparse_cg=False, profile=False, pass_drop=0.0,
+                 stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -79,13 +80,15 @@ class Solver:
         p.solver = int(solver)
         p.weight_floor = float(weight_floor)
         p.tile_rows = int(tile_rows)
+        p.pass_drop = float(pass_drop)
         p.select_mode = {"random": B.SELECT_RANDOM, "greedy": B.SELECT_GREEDY,
                          "block_law": B.SELECT_BLOCK_LAW,
                          "iid": B.SELECT_IID}[select]
         p.flags = ((B.FLAG_GRAPH if graph else 0) |
                    (B.FLAG_GRAM_AAT if gram_aat else 0) |
                    (B.FLAG_CG_SPLIT if cg_split else 0) |
-                   (B.FLAG_SPARSE_CG if sparse_cg else 0))
+                   (B.FLAG_SPARSE_CG if sparse_cg else 0) |
+                   (B.FLAG_PROFILE if profile else 0))
         self.m, self.n = int(m), int(n)
         self.params = p
         self.stream = stream
@@ -157,6 +160,22 @@ class Solver:
                                     _ptr(x), _ptr(z), _ptr(ax), _ptr(atz))
         B.check(st, self._h)
         return ax, atz
+
+    def profile(self):
+        """Event timing of the last solve of a handle made with
+        profile=True: {region: {"launches", "ms", "steps"}} for the steps of
+        the iteration (residual passes, draws, block solves, updates, stop
+        tests, FP64 refinement passes)."""
+        out = {}
+        for i, name in enumerate(B.PROF_REGIONS):
+            n, ms, steps = ctypes.c_int64(0), ctypes.c_double(0), ctypes.c_int64(0)
+            st = self._lib.rgdbek_profile_read(self._h, i, ctypes.byref(n),
+                                               ctypes.byref(ms),
+                                               ctypes.byref(steps))
+            B.check(st, self._h)
+            out[name] = {"launches": n.value, "ms": ms.value,
+                         "steps": steps.value}
+        return out
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -127,6 +127,25 @@ def test_dense_ls_fullsize_first_iteration(rg):
     free()
 
 
+def test_dense_ls_fullsize_eta_half_first_iteration(rg):
+    # Section 3's eta = 0.5 on the 20000 x 5000 system: 2500-column and
+    # 10000-row blocks (row blocks twice as tall as A is wide, beyond the
+    # Gram limit; projected by CGLS); exact projections, one iteration
+    p = workloads.dense_least_squares(20000, 5000, seed=0)
+    kc, kr = 2500, 10000
+    s = rg.Solver(dev(p.a), k_col=kc, k_row=kr, stop="none", max_iter=1,
+                  inner_max=400, inner_tol=1e-14, graph_iters=1)
+    x, _ = s.solve(dev(p.b))
+    z = s.get_z().cpu().numpy()
+    s.close()
+    free()
+    xo, zo, _ = rgdbek(p.a, p.b, k_col=kc, k_row=kr, max_iter=1)
+    print(f"dense 20000x5000 eta=0.5 k={kc}/{kr}: rel_x "
+          f"{rel(x.cpu().numpy(), xo):.2e} rel_z {rel(z, zo):.2e}", flush=True)
+    assert rel(x.cpu().numpy(), xo) <= 1e-10
+    assert rel(z, zo) <= 1e-10
+
+
 @pytest.mark.parametrize("form", ["fp64", "mixed_f32"])
 def test_dense_ls_fullsize_bench_config(rg, form):
     from paper_2509_19267_amd import tune

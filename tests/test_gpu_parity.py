@@ -168,6 +168,22 @@ def test_trajectory_dense_pcg_gram_sources(rg, kc, kr, gram_aat):
     assert rel(z, zo) <= TRAJ_TOL
 
 
+@pytest.mark.parametrize("gram_aat", [True, False])
+def test_trajectory_dense_two_launch_pcg(rg, gram_aat):
+    # FP64 blocks of 4097..8192 indices: beyond the persistent PCG's LDS
+    # staging, so the Gram block is gathered (or formed from the rows) by its
+    # own launch and every CG step takes two launches
+    p = workloads.dense_least_squares(6000, 5000, seed=9)
+    x, z, info, xo, zo = run_both(rg, p, 4500, 4200, 1, seed=6, solver=0,
+                                  inner_max=800, graph_iters=1,
+                                  gram_aat=gram_aat)
+    print(f"two-launch pcg aat={gram_aat} rel_x={rel(x, xo):.3e} "
+          f"rel_z={rel(z, zo):.3e}", flush=True)
+    assert rel(x, xo) <= TRAJ_TOL
+    assert rel(z, zo) <= TRAJ_TOL
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("sparse_cg", [False, True], ids=["gram", "cg"])
 def test_trajectory_sparse_uniform(rg, sparse_cg):
     # small enough for the Gram projections (default) and, forced, the
@@ -357,7 +373,7 @@ def test_mixed_first_pass_within_1e5(rg):
     s.close()
 
 
-def test_mixed_rse_and_unsupported(rg):
+def test_mixed_rse(rg):
     p = workloads.dense_consistent(400, 200, seed=15)
     s = rg.Solver(dev(p.a), k_col=50, k_row=100, precision="mixed_f32",
                   stop="rse", tol=1e-24, max_iter=5000)
@@ -365,10 +381,54 @@ def test_mixed_rse_and_unsupported(rg):
     assert info["converged"] == 1
     assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
     s.close()
-    with pytest.raises(rg.RgdbekError) as ei:
-        rg.Solver(dev(p.a), k_col=50, k_row=100, precision="mixed_f32",
-                  stop="res_ext")
-    assert ei.value.status == 6
+
+
+@pytest.mark.parametrize("kind", ["dense_ls", "dense_consistent", "sparse"])
+def test_mixed_res_ext_refines_without_reference(rg, kind):
+    """The mixed form under RES_EXT: no planted solution anywhere in the
+    solve (its passes end on residuals only); the refined iterate reaches
+    the least-squares solution (dense, with a component of b in null(A^T))
+    or the planted solution (consistent) to 1e-10."""
+    if kind == "dense_ls":
+        p = workloads.dense_least_squares(2000, 500, seed=31)
+        s = rg.Solver(dev(p.a), k_col=100, k_row=100, precision="mixed_f32",
+                      stop="res_ext", tol=1e-12, max_iter=20000)
+    elif kind == "dense_consistent":
+        p = workloads.dense_consistent(1500, 400, seed=32)
+        s = rg.Solver(dev(p.a), k_col=200, k_row=300, precision="mixed_f32",
+                      stop="res_ext", tol=1e-12, max_iter=20000)
+    else:
+        p = workloads.sparse_powerlaw(6000, 3000, mean_len=10, max_len=400,
+                                      seed=33)
+        s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, eta=0.1,
+                      precision="mixed_f32", stop="res_ext", tol=1e-12,
+                      max_iter=20000, inner_max=100)
+    x, info = s.solve(dev(p.b))
+    print(f"mixed res_ext {kind}", info, flush=True)
+    assert info["converged"] == 1 and info["final_metric"] <= 1e-12
+    assert info["outer_iterations"] >= 2
+    assert rel(x.cpu().numpy(), p.x_star) <= 1e-10
+    # the FP64 form under the same test agrees
+    s.close()
+
+
+def test_batch_mixed_res_ext(rg):
+    ps = workloads.laplacian_batch(count=6, n_min=500, n_max=4000, seed=34)
+    mats = [rounded_f32(p.a) for p in ps]
+    csr, ro, co = batch_tensors([SimpleNamespace(a=a) for a in mats])
+    b = np.concatenate([a @ p.x_star for a, p in zip(mats, ps)])
+    csr32 = (csr[0], csr[1], csr[2].to(torch.float32))
+    s = rg.BatchSolver(csr32, ro, co, eta=0.1, stop="res_ext", tol=1e-12,
+                       max_iter=20000, inner_max=200, precision="mixed_f32")
+    x, info = s.solve(dev(b))
+    its, met, conv = s.batch_info()
+    print("batch mixed res_ext", info, list(met), flush=True)
+    assert info["converged"] == 1 and all(conv)
+    assert max(met) <= 1e-12
+    x = x.cpu().numpy()
+    for i, p in enumerate(ps):
+        assert rel(x[co[i]:co[i + 1]], p.x_star) <= 1e-9
+    s.close()
 
 
 def test_apply_matches_products(rg):

@@ -142,3 +142,27 @@ def test_theorem_2_3_residual_decay_over_seeds():
     # geometric: the log-mean falls at a steady rate (least-squares slope)
     slope = np.polyfit(np.arange(K + 1), np.log(errs), 1)[0]
     assert slope < np.log(gamma)
+
+
+def test_tikhonov_kron_closed_form_against_lstsq():
+    """The Kronecker closed form of the regularised deblurring solution
+    against a dense least-squares solve of the stacked system [A; s I]
+    (8 x 8 image), on the exact-in-FP32 operator the workload builds."""
+    import workloads
+    from oracle.refsol import tikhonov_kron
+    aug, t, s = workloads.blur_tikhonov(npix=8, mu=1e-2)
+    n = 64
+    a = aug[:n].toarray()
+    assert np.allclose(a, np.kron(t, t), rtol=0, atol=0)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((n, 3))
+    want = np.linalg.lstsq(aug.toarray(), np.vstack([b, np.zeros((n, 3))]),
+                           rcond=None)[0]
+    got = tikhonov_kron(t, b, s)
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    # a dropped regulariser or a transposed factor fails the normal equations
+    ne = a.T @ (a @ got - b) + s * s * got
+    assert np.linalg.norm(ne) <= 1e-12 * np.linalg.norm(a.T @ b)
+    # without the regulariser the answer moves well beyond the tolerance
+    assert (np.linalg.norm(tikhonov_kron(t, b[:, 0], 0.0) - want[:, 0])
+            > 1e-3 * np.linalg.norm(want[:, 0]))

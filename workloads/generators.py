@@ -202,6 +202,34 @@ def smooth_fields(npix, count, seed, corr=8.0):
     return out
 
 
+def _round_mantissa(v, bits):
+    """v rounded to `bits` significant bits (so that products of two such
+    numbers are exact in FP32 when 2 * bits <= 24)."""
+    m, e = np.frexp(v)
+    return np.ldexp(np.round(m * 2.0 ** bits) / 2.0 ** bits, e)
+
+
+def blur_tikhonov(npix=512, mu=1e-2, sigma=2.0, half=7):
+    """The deblurring operator with Tikhonov rows, [A; s I] with A = T kron T
+    (``blur_operator``'s structure) and s = sqrt(mu): a least-squares system
+    of 2 npix^2 rows whose solution is the regularised deblurred image.  The
+    1-D weights are rounded to 12 significant bits, so every entry of A (a
+    product of two of them) and s (rounded to FP32) is exact in FP32 storage:
+    the stored matrix is exactly T kron T.  Returns (CSR in FP64 with
+    FP32-exact values, T as a dense FP64 array, s)."""
+    w = _round_mantissa(gaussian_psf_1d(sigma, half), 12)
+    offs = np.arange(-half, half + 1)
+    t = sp.diags([np.full(npix - abs(o), w[i]) for i, o in enumerate(offs)],
+                 offs, shape=(npix, npix), format="csr")
+    a = sp.kron(t, t, format="csr")
+    s = float(np.float32(np.sqrt(mu)))
+    n = npix * npix
+    aug = sp.vstack([a, s * sp.identity(n, format="csr")]).tocsr()
+    aug.sort_indices()
+    assert np.array_equal(aug.data.astype(np.float32).astype(np.float64), aug.data)
+    return aug, t.toarray(), s
+
+
 def blur_rhs(a, npix=512, nrhs=64, seed=0, noise=0.01):
     """Smooth random fields x_true and b = A x_true + noise, the noise std
     being ``noise`` times std(A x_true) per right-hand side."""
