@@ -322,6 +322,27 @@ rgdbek_status rgdbek_select_iid(const double *eps, int64_t d, int64_t k,
                                 int32_t *out_idx, int64_t *out_count,
                                 void *stream);
 
+/* Largest d that rgdbek_select_noalloc accepts. */
+#define RGDBEK_NOALLOC_MAX_D 1048576
+
+/* rgdbek_select for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same draw, with the
+ * same arguments and results bit for bit, but all of its work space lives
+ * in one static device array of the library (about 8.6 MB, one copy per
+ * GPU, held until the process ends) instead of hipMalloc'ed buffers; the
+ * call allocates nothing, host or device.
+ *  d must not exceed RGDBEK_NOALLOC_MAX_D (INVALID_ARG otherwise).
+ *  Every call on one GPU shares that GPU's array: calls that overlap in
+ *  time on one GPU (other threads, other streams) race and must not be
+ *  issued; each call clears the parts it needs before its draw and
+ *  synchronises the stream before returning.
+ * Errors as rgdbek_select. */
+rgdbek_status rgdbek_select_noalloc(const double *eps, int64_t d, int64_t k,
+                                    double floor, uint64_t seed, uint64_t key1,
+                                    uint64_t it, uint32_t phase, uint32_t sys,
+                                    int32_t *out_idx, int64_t *out_count,
+                                    void *stream);
+
 /* GDBEK's greedy set (Section 2) on a weight vector: the indices j with
  * eps[j] > 0 and eps[j] >= eta * max(eps) (the product and comparison in
  * FP64), in ascending order, at most cap of them (the lowest indices when

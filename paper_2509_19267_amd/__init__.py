@@ -7,9 +7,10 @@ include/rgdbek.h); this package only marshals arguments to it.
 from ._binding import RgdbekError, LIB_PATH, load  # noqa: F401
 from .solver import (Solver, BatchSolver, MultiRhsSolver,  # noqa: F401
                      block_diagonal, select, select_threshold,
-                     select_block_law, select_iid, solve,
+                     select_block_law, select_iid, select_noalloc, solve,
                      RGDBEKFunction)
 
 __all__ = ["Solver", "BatchSolver", "MultiRhsSolver", "block_diagonal", "select",
-           "select_threshold", "select_block_law", "select_iid", "solve", "RGDBEKFunction", "RgdbekError",
+           "select_threshold", "select_block_law", "select_iid",
+           "select_noalloc", "solve", "RGDBEKFunction", "RgdbekError",
            "LIB_PATH", "load"]

@@ -78,6 +78,13 @@ SIGNATURES = {
                                      ctypes.c_uint64, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32, _vp,
                                      ctypes.POINTER(ctypes.c_int64), _vp]),
+    "rgdbek_select_noalloc": (ctypes.c_int, [_vp, ctypes.c_int64,
+                                             ctypes.c_int64, ctypes.c_double,
+                                             ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.c_uint64, ctypes.c_uint32,
+                                             ctypes.c_uint32, _vp,
+                                             ctypes.POINTER(ctypes.c_int64),
+                                             _vp]),
     "rgdbek_select_block_law": (ctypes.c_int, [_vp, ctypes.c_int64,
                                                ctypes.c_int64, ctypes.c_double,
                                                ctypes.c_uint64, ctypes.c_uint64,

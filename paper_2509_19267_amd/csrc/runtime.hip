@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -1462,6 +1463,53 @@ rgdbek_status guarded(rgdbek_ctx *h, F &&f) {
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free draw
+// rgdbek_select_noalloc works in one static device array instead of
+// hipMalloc'ed scratch.  Layout (byte offsets, each 256-aligned): the
+// control block, the persistent draw's histograms and candidates, the
+// multi-launch pipeline's histogram, candidates and per-chunk counts, then
+// the d keys.  Every region but the keys is cleared at each call.
+constexpr size_t na_align(size_t v) { return (v + 255) / 256 * 256; }
+constexpr int64_t NA_BLK_N = RGDBEK_NOALLOC_MAX_D / 256 + 64;
+constexpr size_t NA_CTRL = 0;
+constexpr size_t NA_PERS = na_align(NA_CTRL + sizeof(Ctrl));
+constexpr size_t NA_HIST = na_align(NA_PERS + sizeof(SelPersist));
+constexpr size_t NA_CKEY = na_align(NA_HIST + 2048 * sizeof(unsigned));
+constexpr size_t NA_CIDX = na_align(NA_CKEY + 4096 * sizeof(uint64_t));
+constexpr size_t NA_BLK = na_align(NA_CIDX + 4096 * sizeof(int64_t));
+constexpr size_t NA_KEYS = na_align(NA_BLK + NA_BLK_N * sizeof(int32_t));
+constexpr size_t NA_BYTES =
+    na_align(NA_KEYS + (RGDBEK_NOALLOC_MAX_D + 64) * sizeof(uint64_t));
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+__global__ void __launch_bounds__(256)
+noalloc_zero_kernel(uint4 *p, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16;
+       i += (int64_t)gridDim.x * 256)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+namespace {
+// Device address of `scratch` on the current device, looked up once per
+// device: the host-side name is only a stand-in for the symbol.
+unsigned char *noalloc_scratch_ptr() {
+  static std::mutex mu;
+  static std::vector<unsigned char *> addr;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw ApiError{RGDBEK_ERR_DEVICE, "no address for the static work space"};
+    addr[dev] = (unsigned char *)p;
+  }
+  return addr[dev];
+}
+}  // namespace
+
 // ============================================================ C-ABI
 extern "C" {
 
@@ -2067,6 +2115,57 @@ rgdbek_status rgdbek_select_threshold(const double *eps, int64_t d, double eta,
   });
   P.release();
   return s;
+}
+
+rgdbek_status rgdbek_select_noalloc(const double *eps, int64_t d, int64_t k,
+                                    double floor, uint64_t seed, uint64_t key1,
+                                    uint64_t it, uint32_t phase, uint32_t sys,
+                                    int32_t *out_idx, int64_t *out_count,
+                                    void *stream) {
+  g_global_err.clear();
+  if (!eps || !out_idx || !out_count || d <= 0 || k < 0) {
+    set_err(nullptr, "eps, out_idx, out_count required; d > 0, k >= 0");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  if (d > RGDBEK_NOALLOC_MAX_D) {
+    set_err(nullptr, "rgdbek_select_noalloc: d = " + std::to_string(d) +
+                         " exceeds its static work space (at most " +
+                         std::to_string((long long)RGDBEK_NOALLOC_MAX_D) +
+                         " weights); use rgdbek_select");
+    return RGDBEK_ERR_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  return guarded(nullptr, [&]() {
+    unsigned char *base = noalloc_scratch_ptr();
+    if (select_scratch_blocks(d) + 64 > NA_BLK_N)
+      throw ApiError{RGDBEK_ERR_INVALID_ARG, "block count exceeds the work space"};
+    SelectScratch sc;
+    sc.pers = (SelPersist *)(base + NA_PERS);
+    sc.ncu = device_cus();
+    sc.keys = (uint64_t *)(base + NA_KEYS);
+    sc.hist = (unsigned *)(base + NA_HIST);
+    sc.ckey = (uint64_t *)(base + NA_CKEY);
+    sc.cidx = (int64_t *)(base + NA_CIDX);
+    sc.blk = (int32_t *)(base + NA_BLK);
+    Ctrl *c = (Ctrl *)(base + NA_CTRL);
+    // the previous call's contents stay in the array: clear everything but
+    // the keys (which every draw writes before reading) with a kernel
+    hipLaunchKernelGGL(noalloc_zero_kernel, dim3(64), dim3(256), 0, st,
+                       (uint4 *)base, (int64_t)(NA_KEYS / sizeof(uint4)));
+    launch_fill_ctrl_it(c, (int64_t)it, st);
+    launch_select<double>(eps, d, k, floor, seed, key1, phase, sys, 0, sc,
+                          out_idx, c, 0, st);
+    Ctrl hc;
+    HIPCHK(hipMemcpyAsync(&hc, c, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    *out_count = hc.sel_count[0];
+    if (hc.sync_fail)
+      throw ApiError{RGDBEK_ERR_DEVICE, "a grid-barrier wait timed out"};
+    if (hc.numeric)
+      throw ApiError{RGDBEK_ERR_NUMERIC, "weights must be finite and >= 0"};
+    return RGDBEK_OK;
+  });
 }
 
 rgdbek_status rgdbek_profile_read(rgdbek_handle h, int32_t region,

@@ -332,6 +332,27 @@ def select(eps, k, seed=0, it=0, phase=0, sys=0, key1=0, floor=1e-20,
     return out[:cnt.value]
 
 
+def select_noalloc(eps, k, seed=0, it=0, phase=0, sys=0, key1=0, floor=1e-20,
+                   out=None, stream=None):
+    """select() through the allocation-free entry point: the library's draw
+    allocates no device memory (its work space is a static device array;
+    overlapping calls on one GPU race).  `out` (device int32, room for
+    min(k, d)) may be passed in so that nothing is allocated here either."""
+    lib = B.load()
+    _need_cuda(eps, "eps", torch.float64)
+    d = eps.numel()
+    if out is None:
+        out = torch.empty(max(1, min(int(k), d)), dtype=torch.int32,
+                          device=eps.device)
+    cnt = ctypes.c_int64(0)
+    st = lib.rgdbek_select_noalloc(_ptr(eps), d, int(k), float(floor),
+                                   int(seed), int(key1), int(it), int(phase),
+                                   int(sys), _ptr(out), ctypes.byref(cnt),
+                                   _stream(stream))
+    B.check(st, None)
+    return out[:cnt.value]
+
+
 def select_block_law(eps, s, seed=0, it=0, phase=0, sys=0, key1=0,
                      floor=1e-20, stream=None):
     """Block of size s from the law of Lemma 2.1 on given weights (device
