@@ -153,7 +153,13 @@ enum { RGDBEK_SOLVER_AUTO = 0, RGDBEK_SOLVER_CHOL = 1, RGDBEK_SOLVER_CG = 2 };
  * of all columns and rows formed once at create (as dense matrices do). */
 enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2,
        RGDBEK_FLAG_CG_SPLIT = 4, RGDBEK_FLAG_SPARSE_CG = 8,
-       RGDBEK_FLAG_PROFILE = 16 };
+       RGDBEK_FLAG_PROFILE = 16, RGDBEK_FLAG_SPARSE_FULL = 32 };
+/* RGDBEK_FLAG_SPARSE_FULL: the matrix-free sparse block projections stream
+ * all of A in every CG step (as a product with a vector that is zero off the
+ * block) instead of a copy of the block's own entries made once per
+ * iteration (the default for one stored matrix; the many-right-hand-side
+ * operator always streams A).  The same sums, grouped differently across
+ * lanes: results agree to rounding. */
 /* RGDBEK_FLAG_PROFILE times every step of every iteration with HIP events on
  * the handle's stream (the launches are then issued one by one, not from
  * captured graphs, so a profiled solve runs a little slower than a plain

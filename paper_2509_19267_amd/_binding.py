@@ -18,8 +18,8 @@ F64, F32 = 0, 1
 STOP_NONE, STOP_ERR_REF, STOP_RSE, STOP_RES_EXT = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED_F32 = 0, 1
 SOLVER_AUTO, SOLVER_CHOL, SOLVER_CG = 0, 1, 2
-FLAG_GRAPH, FLAG_GRAM_AAT, FLAG_CG_SPLIT, FLAG_SPARSE_CG, FLAG_PROFILE = \
-    1, 2, 4, 8, 16
+FLAG_GRAPH, FLAG_GRAM_AAT, FLAG_CG_SPLIT, FLAG_SPARSE_CG, FLAG_PROFILE, \
+    FLAG_SPARSE_FULL = 1, 2, 4, 8, 16, 32
 PROF_REGIONS = ["col_residual", "col_draw", "col_solve", "col_update",
                 "row_residual", "row_draw", "row_solve", "row_update",
                 "stop", "refine"]

@@ -121,6 +121,9 @@ struct Csr {                 // CSR (or CSC viewed as CSR of the transpose)
   const int32_t *longs = nullptr;  // base segments longer than the limit
   int64_t nlong = 0;
   int64_t long_limit = 0;
+  // rows handled as long segments, when that is decided by membership rather
+  // than by length (the block copies keep the long rows of A as long)
+  const uint8_t *long_flag = nullptr;
   // Merge-chunk plan of full passes (rep == 1): chunk c holds nonzeros
   // [c*MP_CH, (c+1)*MP_CH) and owns the rows whose first nonzero position
   // ptr[r] lies in it (mp_rs[c] .. mp_rs[c+1]-1; mp_rs[nchunk] = rows); rows
@@ -337,6 +340,7 @@ struct SparseCg {
   T *wide = nullptr;    // wide product (m for columns, n for rows)
   T *p = nullptr, *res = nullptr, *v = nullptr;  // narrow (cap)
   double *part = nullptr;
+  int64_t part_cap = 0;     // entries of part
   int32_t *pos = nullptr;   // block position of each index, -1 outside
   double *plong = nullptr;  // one partial per long segment
   int split = 0;            // many-workgroup step finish at any block size
@@ -365,6 +369,30 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                            int64_t cap, const T *r, const double *rho, T *x,
                            SparseCg<T> &w, int max_steps, double tol,
                            Ctrl *ctrl, int respect_done, hipStream_t st);
+
+// Block-restricted copy of a CSR (or of the CSC, as the CSR of A^T): the
+// entries whose column is in the current block, in storage order, with
+// their original indices, rebuilt once per iteration so that every CG step
+// of the block projection streams only them (see proj.hip).
+struct SubWork {
+  int64_t *ptr = nullptr;    // rows + 1
+  int64_t *cnt = nullptr;    // rows + 1 (counts, then scratch)
+  int64_t *tile = nullptr;   // per-tile sums of the scan
+  int32_t *idx = nullptr;    // capacity nnz
+  void *val = nullptr;       // capacity nnz values
+  int32_t *mask = nullptr;   // one flag per column, zero between calls
+  uint8_t *long_flag = nullptr;  // rows of A that are long segments
+  int64_t cap = 0;           // entry capacity
+  int group = 1;             // lanes per row for the compact matrix
+};
+template <typename T>
+Csr<T> launch_sub_matrix(const Csr<T> &A, const int32_t *list,
+                         const int64_t *count_dev, int64_t list_cap,
+                         SubWork &w, Ctrl *ctrl, hipStream_t st);
+int64_t sub_scan_tiles(int64_t n);
+// long_flag[r] = 1 for the rows of A longer than A.long_limit
+template <typename T>
+void launch_mark_long(const Csr<T> &A, uint8_t *flag, hipStream_t st);
 
 // Row blocks taller than A is wide (k_row > n): CGLS on min ||A^J d - r^J||
 // (see proj.hip).  d, p, s: n entries; res, q: cap; rhat: m (sparse only:

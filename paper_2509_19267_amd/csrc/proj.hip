@@ -854,6 +854,8 @@ void launch_list_resid(const T *Arm, int64_t ld, int64_t len,
 constexpr int SC_NT = 256;
 constexpr unsigned SC_MAXB = 512;   // blocks of a launch that ends in a ticket
 constexpr unsigned SC_WIDE_MAXB = 512;   // blocks of the columns' wide product
+constexpr unsigned SC_WIDE_GRID_MIN = 8;  // slots per group above which the
+                                          // wide product takes a full grid
 // Larger blocks update the CG vectors with separate many-workgroup launches
 // (sc_cupd, sc_rupd1/2) instead of a walk by the last workgroup.
 constexpr int64_t SC_SERIAL_MAX = 16384;
@@ -882,7 +884,8 @@ sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
       vrow(A, slot, s, br, co);
       const T *ph = phat + co;
       const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
-      if (nlong && e1 - e0 > A.long_limit) mine = false;   // sc_long_wide
+      if (nlong && (A.long_flag ? A.long_flag[br] != 0 : e1 - e0 > A.long_limit))
+        mine = false;   // sc_long_wide
       else
         for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * ph[A.idx[e]];
     }
@@ -907,6 +910,63 @@ sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
   }
 }
 
+// The same product over a full grid (one row slot per thread group, no
+// grid-stride loop) for matrices with many rows, where a bounded grid walks
+// its rows as a long chain of dependent loads; each workgroup leaves its
+// partial of ||q||^2, and sc_wide_col_fin sums them (in block order, then
+// the long segments) and forms alpha.
+template <typename T, int G>
+__global__ void __launch_bounds__(SC_NT)
+sc_wide_col_grid(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
+                 double *__restrict__ part, int64_t nlong, Ctrl *ctrl,
+                 int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[0])) return;
+  __shared__ double sh[SC_NT / WAVE];
+  constexpr int SPB = SC_NT / G;
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t slot = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  double qq = 0.0;
+  int64_t s = 0, br = 0, co = 0;
+  T acc = 0;
+  bool mine = slot < A.rows;
+  if (mine) {
+    vrow(A, slot, s, br, co);
+    const T *ph = phat + co;
+    const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
+    if (nlong && (A.long_flag ? A.long_flag[br] != 0 : e1 - e0 > A.long_limit))
+      mine = false;   // sc_long_wide
+    else
+      for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * ph[A.idx[e]];
+  }
+  acc = group_sum<G>(acc);
+  if (mine && lg == 0) {
+    q[s] = acc;
+    qq = (double)acc * (double)acc;
+  }
+  qq = block_sum<SC_NT>(qq, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = qq;
+}
+template <typename T>
+__global__ void __launch_bounds__(1024)
+sc_wide_col_fin(const double *__restrict__ part, int64_t nb,
+                const double *__restrict__ plong, int64_t nlong, Ctrl *ctrl,
+                int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[0])) return;
+  __shared__ double sh[1024 / WAVE];
+  double tot = 0.0, tl = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += 1024) tot += part[b];
+  for (int64_t i = threadIdx.x; i < nlong; i += 1024) tl += plong[i];
+  tot = block_sum<1024>(tot, sh);
+  tot += block_sum<1024>(tl, sh);
+  if (threadIdx.x == 0) {
+    const double gam = ctrl->cg_rz[0];
+    ctrl->cg_alpha[0] = tot > 0.0 ? gam / tot : 0.0;
+    if (tot == 0.0) ctrl->cg_done[0] = 1;
+  }
+}
+
 // narrow: w_a = <A_(U_a), q> over listed CSC columns; s -= alpha w;
 // and z -= alpha q over a slice of rows; last block: gam', beta, p, phat.
 template <typename T, int G>
@@ -916,7 +976,7 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
               T *__restrict__ z, int64_t m, T *__restrict__ sres,
               T *__restrict__ p, T *__restrict__ phat,
               double *__restrict__ part, const double *__restrict__ plong,
-              int64_t nlong, double tol, int par, Ctrl *ctrl,
+              int64_t nlong, double tol, int par, int gridm, Ctrl *ctrl,
               int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   if (ld_agent(&ctrl->cg_done[0])) return;
@@ -954,6 +1014,10 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
     }
   }
   ss = block_sum<SC_NT>(ss, sh);
+  if (gridm) {   // full grid: sc_narrow_col_fin reduces the partials
+    if (threadIdx.x == 0) part[blockIdx.x] = ss;
+    return;
+  }
   if (threadIdx.x == 0) st_agent(&part[blockIdx.x], ss);
   if (!last_block(&ctrl->ticket[4])) return;
   double tot = 0.0, tl = 0.0;
@@ -1053,6 +1117,51 @@ sc_clear(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
        a += (int64_t)gridDim.x * SC_NT) {
     phat[list[a]] = (T)0;
     if (pos) pos[list[a]] = -1;
+  }
+}
+
+// Finish of a listed product launched over a full grid (large blocks, many
+// listed segments): the partials in block order, then the long segments,
+// give what the last workgroup of the bounded launch forms.
+//   columns: gam' = ||s||^2, beta = gam'/gam, stop at gam' <= tol^2 gam_0
+//   rows:    alpha = rz / <p, v>
+__global__ void __launch_bounds__(1024)
+sc_narrow_col_fin(const double *__restrict__ part, int64_t nb,
+                  const double *__restrict__ plong, int64_t nlong, double tol,
+                  Ctrl *ctrl, int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[0])) return;
+  __shared__ double sh[1024 / WAVE];
+  double tot = 0.0, tl = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += 1024) tot += part[b];
+  for (int64_t i = threadIdx.x; i < nlong; i += 1024) tl += plong[i];
+  tot = block_sum<1024>(tot, sh);
+  tot += block_sum<1024>(tl, sh);
+  if (threadIdx.x == 0) {
+    const double gam = ctrl->cg_rz[0];
+    ctrl->cg_beta[0] = gam > 0.0 ? tot / gam : 0.0;
+    ctrl->cg_rz[0] = tot;
+    ctrl->cg_steps[0] += 1;
+    if (tot <= tol * tol * ctrl->cg_rz0[0]) ctrl->cg_done[0] = 1;
+  }
+}
+__global__ void __launch_bounds__(1024)
+sc_narrow_row_fin(const double *__restrict__ part, int64_t nb,
+                  const double *__restrict__ plong, int64_t nlong, Ctrl *ctrl,
+                  int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ld_agent(&ctrl->cg_done[1])) return;
+  __shared__ double sh[1024 / WAVE];
+  double tot = 0.0, tl = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += 1024) tot += part[b];
+  for (int64_t i = threadIdx.x; i < nlong; i += 1024) tl += plong[i];
+  tot = block_sum<1024>(tot, sh);
+  tot += block_sum<1024>(tl, sh);
+  if (threadIdx.x == 0) {
+    const double rz = ctrl->cg_rz[1];
+    ctrl->cg_alpha[1] = tot != 0.0 ? rz / tot : 0.0;
+    ctrl->cg_steps[1] += 1;
+    if (tot == 0.0) ctrl->cg_done[1] = 1;
   }
 }
 
@@ -1225,7 +1334,8 @@ sc_wide_row(Csr<T> At, const T *__restrict__ phat, T *__restrict__ u,
     vrow(At, slot, s, br, co);
     const T *ph = phat + co;
     const int64_t e0 = At.ptr[br], e1 = At.ptr[br + 1];
-    if (nlong && e1 - e0 > At.long_limit) mine = false;   // sc_long_wide
+    if (nlong && (At.long_flag ? At.long_flag[br] != 0 : e1 - e0 > At.long_limit))
+      mine = false;   // sc_long_wide
     else
       for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * ph[At.idx[e]];
   }
@@ -1244,7 +1354,7 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
               T *__restrict__ zz, T *__restrict__ p, T *__restrict__ v,
               T *__restrict__ phat, double *__restrict__ part,
               const double *__restrict__ plong, int64_t nlong, double tol,
-              int par, Ctrl *ctrl, int respect_done) {
+              int par, int gridm, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   if (ld_agent(&ctrl->cg_done[1])) return;
   __shared__ double sh[SC_NT / WAVE];
@@ -1273,6 +1383,10 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
     }
   }
   pv = block_sum<SC_NT>(pv, sh);
+  if (gridm) {   // full grid: sc_narrow_row_fin reduces the partials
+    if (threadIdx.x == 0) part[blockIdx.x] = pv;
+    return;
+  }
   if (threadIdx.x == 0) st_agent(&part[blockIdx.x], pv);
   if (!last_block(&ctrl->ticket[5])) return;
   double tot = 0.0, tl = 0.0;
@@ -1390,9 +1504,18 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
                      (T *)nullptr, w.p, w.phat, nln ? w.pos : (int32_t *)nullptr,
                      w.part, ctrl, 0, respect_done);
   const unsigned nbw = std::min<unsigned>(seg_blocks<T>(csr.rows, csr.group), SC_WIDE_MAXB);
+  // many rows: a full grid and a separate reduction instead of a bounded
+  // grid walking SC_WIDE_GRID_MIN or more row slots per thread group
+  const unsigned nbg = seg_blocks<T>(csr.rows, csr.group);
+  const bool wide_grid = nbg >= SC_WIDE_GRID_MIN * SC_WIDE_MAXB &&
+                         (int64_t)nbg <= w.part_cap;
   unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csc.group), SC_MAXB);
   if (nbn < 64) nbn = 64;
   const int par = (w.split || cap > SC_SERIAL_MAX) ? 1 : 0;
+  // large blocks: the listed product over a full grid, reduced by a
+  // separate launch (no grid-stride walk, no last-workgroup ticket)
+  const unsigned nbnf = seg_blocks<T>(cap, csc.group);
+  const bool narrow_grid = par && nbnf > SC_MAXB && (int64_t)nbnf <= w.part_cap;
   const unsigned nbu = std::min<unsigned>(
       (unsigned)((cap + SC_NT - 1) / SC_NT), SC_MAXB);
   for (int s = 0; s < max_steps; ++s) {
@@ -1400,20 +1523,36 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
       hipLaunchKernelGGL(sc_long_wide<T>, dim3((unsigned)nlw), dim3(SC_NT), 0,
                          st, csr, w.phat, w.wide, (T *)nullptr, w.plong, ctrl,
                          0, respect_done);
-    RG_SWITCH_G(csr.group, hipLaunchKernelGGL((sc_wide_col<T, GG>), dim3(nbw),
-                                              dim3(SC_NT), 0, st, csr, w.phat,
-                                              w.wide, w.part, w.plong, nlw,
-                                              ctrl, respect_done));
+    if (wide_grid) {
+      RG_SWITCH_G(csr.group,
+                  hipLaunchKernelGGL((sc_wide_col_grid<T, GG>), dim3(nbg),
+                                     dim3(SC_NT), 0, st, csr, w.phat, w.wide,
+                                     w.part, nlw, ctrl, respect_done));
+      hipLaunchKernelGGL(sc_wide_col_fin<T>, dim3(1), dim3(1024), 0, st,
+                         (const double *)w.part, (int64_t)nbg,
+                         (const double *)w.plong, nlw, ctrl, respect_done);
+    } else {
+      RG_SWITCH_G(csr.group, hipLaunchKernelGGL((sc_wide_col<T, GG>), dim3(nbw),
+                                                dim3(SC_NT), 0, st, csr, w.phat,
+                                                w.wide, w.part, w.plong, nlw,
+                                                ctrl, respect_done));
+    }
     if (nln)
       hipLaunchKernelGGL(sc_long_narrow<T>, dim3((unsigned)nln), dim3(SC_NT),
                          0, st, csc, w.pos, w.wide, w.res, w.p, w.plong, ctrl,
                          0, respect_done);
     RG_SWITCH_G(csc.group,
-                hipLaunchKernelGGL((sc_narrow_col<T, GG>), dim3(nbn),
+                hipLaunchKernelGGL((sc_narrow_col<T, GG>),
+                                   dim3(narrow_grid ? nbnf : nbn),
                                    dim3(SC_NT), 0, st, csc, U, count_dev,
                                    w.wide, z, csr.rows, w.res, w.p, w.phat,
-                                   w.part, w.plong, nln, tol, par, ctrl,
-                                   respect_done));
+                                   w.part, w.plong, nln, tol, par,
+                                   narrow_grid ? 1 : 0, ctrl, respect_done));
+    if (narrow_grid)
+      hipLaunchKernelGGL(sc_narrow_col_fin, dim3(1), dim3(1024), 0, st,
+                         (const double *)w.part, (int64_t)nbnf,
+                         (const double *)w.plong, nln, tol, ctrl,
+                         respect_done);
     if (par)
       hipLaunchKernelGGL(sc_cupd<T>, dim3(nbu), dim3(SC_NT), 0, st, U,
                          count_dev, w.res, w.p, w.phat, ctrl, s, respect_done);
@@ -1439,6 +1578,8 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
   const unsigned nbw = seg_blocks<T>(csc.rows, csc.group);
   const unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csr.group), SC_MAXB);
   const int par = (w.split || cap > SC_SERIAL_MAX) ? 1 : 0;
+  const unsigned nbnf = seg_blocks<T>(cap, csr.group);
+  const bool narrow_grid = par && nbnf > SC_MAXB && (int64_t)nbnf <= w.part_cap;
   const unsigned nbu = std::min<unsigned>(
       (unsigned)((cap + SC_NT - 1) / SC_NT), SC_MAXB);
   for (int s = 0; s < max_steps; ++s) {
@@ -1455,11 +1596,17 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                          0, st, csr, w.pos, w.wide, w.v + cap, w.p, w.plong,
                          ctrl, 1, respect_done);
     RG_SWITCH_G(csr.group,
-                hipLaunchKernelGGL((sc_narrow_row<T, GG>), dim3(nbn),
+                hipLaunchKernelGGL((sc_narrow_row<T, GG>),
+                                   dim3(narrow_grid ? nbnf : nbn),
                                    dim3(SC_NT), 0, st, csr, J, count_dev,
                                    w.wide, rho, w.res, w.v, w.p,
                                    w.v + cap, w.phat, w.part, w.plong, nln,
-                                   tol, par, ctrl, respect_done));
+                                   tol, par, narrow_grid ? 1 : 0, ctrl,
+                                   respect_done));
+    if (narrow_grid)
+      hipLaunchKernelGGL(sc_narrow_row_fin, dim3(1), dim3(1024), 0, st,
+                         (const double *)w.part, (int64_t)nbnf,
+                         (const double *)w.plong, nln, ctrl, respect_done);
     if (par) {
       hipLaunchKernelGGL(sc_rupd1<T>, dim3(nbu), dim3(SC_NT), 0, st, J,
                          count_dev, rho, w.res, w.v, w.v + cap, w.part, tol,
@@ -1611,6 +1758,276 @@ template void launch_sparse_block_update<float>(
     const Csr<float> &, const int32_t *, const int64_t *, int64_t,
     const float *, int, float *, float *, Ctrl *, int, hipStream_t);
 #undef RG_INST
+
+// ------------------------------------------------------------ block restriction
+// The wide products of the sparse CG (columns: q = A phat over CSR rows;
+// rows: u = A^T phat over CSC columns) multiply by a vector that is zero
+// outside the block, so only the entries of the block's columns (rows) can
+// contribute.  Once per iteration those entries are copied, in storage
+// order and with their original indices, into a compact matrix of the same
+// row count; every CG step then streams it instead of all of A (about the
+// block's share of the nonzeros).  The long rows of A (one workgroup each
+// in the CG products) stay long in the copy.  The sums drop only zero terms
+// and stay deterministic; their grouping across lanes differs from the full
+// pass's, so the two agree to rounding.
+//   mark:   mask[list_a] = 1
+//   count:  cnt_r = #{e in row r : mask[idx_e]}            (G lanes per row)
+//   scan:   ptr = exclusive prefix sum of cnt             (three launches)
+//   fill:   each row's marked entries, in order, to ptr_r (ballot ranks)
+//   unmark: mask[list_a] = 0
+constexpr int SB_NT = 256;
+constexpr int SB_TILE = 2048;          // scan elements per workgroup
+
+__global__ void __launch_bounds__(SB_NT)
+sub_mark(const int32_t *__restrict__ list, const int64_t *__restrict__ cnt,
+         int32_t *__restrict__ mask, int32_t v, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  const int64_t c = *cnt;
+  for (int64_t a = (int64_t)blockIdx.x * SB_NT + threadIdx.x; a < c;
+       a += (int64_t)gridDim.x * SB_NT)
+    mask[list[a]] = v;
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(SB_NT)
+sub_count(Csr<T> A, const int32_t *__restrict__ mask, int64_t *__restrict__ cnt,
+          const uint8_t *__restrict__ long_flag, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  constexpr int SPB = SB_NT / G;
+  const int lg = threadIdx.x & (G - 1);
+  const int64_t r = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  int64_t k = 0;
+  const bool mine = r < A.rows && !(long_flag && long_flag[r]);   // sub_count_long
+  if (mine) {
+    const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) k += mask[A.idx[e]] ? 1 : 0;
+  }
+  k = group_sum<G>(k);
+  if (mine && lg == 0) cnt[r] = k;
+  if (r == A.rows && lg == 0) cnt[r] = 0;   // sentinel: ptr[rows] = total
+}
+
+// exclusive scan of n int64 values: per-tile sums, scan of the tile sums in
+// one workgroup, then per-tile scans with the tile offset
+__global__ void __launch_bounds__(SB_NT)
+sub_scan_a(const int64_t *__restrict__ v, int64_t n,
+           int64_t *__restrict__ tile, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  __shared__ int64_t sh[SB_NT / WAVE];
+  const int64_t i0 = (int64_t)blockIdx.x * SB_TILE;
+  int64_t s = 0;
+  for (int64_t i = i0 + threadIdx.x; i < i0 + SB_TILE && i < n; i += SB_NT)
+    s += v[i];
+  s = block_sum_i64<SB_NT>(s, sh);
+  if (threadIdx.x == 0) tile[blockIdx.x] = s;
+}
+__global__ void __launch_bounds__(1024)
+sub_scan_b(int64_t *__restrict__ tile, int64_t ntile, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  __shared__ int64_t sh[1024];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < ntile; b0 += 1024) {
+    const int64_t b = b0 + threadIdx.x;
+    const int64_t v = b < ntile ? tile[b] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int64_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (b < ntile) tile[b] = carry + sh[threadIdx.x] - v;   // exclusive
+    const int64_t tot = sh[1023];
+    __syncthreads();
+    carry += tot;
+  }
+}
+__global__ void __launch_bounds__(SB_NT)
+sub_scan_c(const int64_t *__restrict__ v, int64_t n,
+           const int64_t *__restrict__ tile, int64_t *__restrict__ out,
+           Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  constexpr int PER = SB_TILE / SB_NT;   // consecutive elements per thread
+  __shared__ int64_t sh[SB_NT];
+  const int64_t i0 = (int64_t)blockIdx.x * SB_TILE + (int64_t)threadIdx.x * PER;
+  int64_t loc[PER];
+  int64_t s = 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t i = i0 + u;
+    loc[u] = s;
+    s += i < n ? v[i] : 0;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < SB_NT; o <<= 1) {
+    const int64_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  const int64_t base = tile[blockIdx.x] + sh[threadIdx.x] - s;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t i = i0 + u;
+    if (i < n) out[i] = base + loc[u];
+  }
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(SB_NT)
+sub_fill(Csr<T> A, const int32_t *__restrict__ mask,
+         const int64_t *__restrict__ ptr, int32_t *__restrict__ idx,
+         T *__restrict__ val, const uint8_t *__restrict__ long_flag,
+         Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  constexpr int SPB = SB_NT / G;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int lg = threadIdx.x & (G - 1);
+  const int gbase = lane & ~(G - 1);          // first lane of the group
+  const int64_t r = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
+  const bool live = r < A.rows && !(long_flag && long_flag[r]);  // sub_fill_long
+  const int64_t e0 = live ? A.ptr[r] : 0, e1 = live ? A.ptr[r + 1] : 0;
+  int64_t pos = live ? ptr[r] : 0;
+  // every lane of a wave runs the same trip count (ballots need the whole
+  // wave): the longest segment of the wave's groups
+  int64_t len = e1 - e0;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t t = __shfl_xor(len, o, WAVE);
+    len = t > len ? t : len;
+  }
+  const unsigned long long gmask =
+      (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
+  for (int64_t c = 0; c < len; c += G) {
+    const int64_t e = e0 + c + lg;
+    const bool in = e < e1;
+    const int32_t j = in ? A.idx[e] : 0;
+    const bool take = in && mask[j] != 0;
+    const unsigned long long bal = __ballot(take);
+    const unsigned long long mine = bal & gmask;
+    const unsigned long long below = mine & ((1ull << lane) - 1ull);
+    if (take) {
+      const int64_t o = pos + __popcll(below);
+      idx[o] = j;
+      val[o] = A.val[e];
+    }
+    pos += __popcll(mine);
+  }
+}
+
+// long rows (A.longs): one workgroup each, in storage order
+template <typename T>
+__global__ void __launch_bounds__(SB_NT)
+sub_count_long(Csr<T> A, const int32_t *__restrict__ mask,
+               int64_t *__restrict__ cnt, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  __shared__ int64_t sh[SB_NT / WAVE];
+  const int64_t r = A.longs[blockIdx.x];
+  const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
+  int64_t k = 0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += SB_NT)
+    k += mask[A.idx[e]] ? 1 : 0;
+  k = block_sum_i64<SB_NT>(k, sh);
+  if (threadIdx.x == 0) cnt[r] = k;
+}
+template <typename T>
+__global__ void __launch_bounds__(SB_NT)
+sub_fill_long(Csr<T> A, const int32_t *__restrict__ mask,
+              const int64_t *__restrict__ ptr, int32_t *__restrict__ idx,
+              T *__restrict__ val, Ctrl *ctrl) {
+  if (ctrl_done(ctrl)) return;
+  __shared__ int64_t wsum[SB_NT / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = threadIdx.x / WAVE;
+  const int64_t r = A.longs[blockIdx.x];
+  const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
+  int64_t pos = ptr[r];
+  for (int64_t c = e0; c < e1; c += SB_NT) {
+    const int64_t e = c + threadIdx.x;
+    const bool in = e < e1;
+    const int32_t j = in ? A.idx[e] : 0;
+    const bool take = in && mask[j] != 0;
+    const unsigned long long bal = __ballot(take);
+    if (lane == 0) wsum[w] = __popcll(bal);
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+    for (int i = 0; i < SB_NT / WAVE; ++i) {
+      before += i < w ? wsum[i] : 0;
+      tot += wsum[i];
+    }
+    if (take) {
+      const int64_t o = pos + before + __popcll(bal & ((1ull << lane) - 1ull));
+      idx[o] = j;
+      val[o] = A.val[e];
+    }
+    pos += tot;
+    __syncthreads();
+  }
+}
+
+int64_t sub_scan_tiles(int64_t n) { return (n + SB_TILE - 1) / SB_TILE; }
+
+template <typename T>
+__global__ void __launch_bounds__(SB_NT)
+mark_long_kernel(Csr<T> A, uint8_t *__restrict__ flag) {
+  const int64_t r = (int64_t)blockIdx.x * SB_NT + threadIdx.x;
+  if (r < A.rows)
+    flag[r] = (A.long_limit > 0 && A.ptr[r + 1] - A.ptr[r] > A.long_limit) ? 1 : 0;
+}
+template <typename T>
+void launch_mark_long(const Csr<T> &A, uint8_t *flag, hipStream_t st) {
+  hipLaunchKernelGGL(mark_long_kernel<T>, dim3((unsigned)((A.rows + SB_NT - 1) / SB_NT)),
+                     dim3(SB_NT), 0, st, A, flag);
+}
+template void launch_mark_long<double>(const Csr<double> &, uint8_t *, hipStream_t);
+template void launch_mark_long<float>(const Csr<float> &, uint8_t *, hipStream_t);
+
+template <typename T>
+Csr<T> launch_sub_matrix(const Csr<T> &A, const int32_t *list,
+                         const int64_t *count_dev, int64_t list_cap,
+                         SubWork &w, Ctrl *ctrl, hipStream_t st) {
+  const unsigned gm = (unsigned)std::min<int64_t>(
+      std::max<int64_t>((list_cap + SB_NT - 1) / SB_NT, 1), 1024);
+  hipLaunchKernelGGL(sub_mark, dim3(gm), dim3(SB_NT), 0, st, list, count_dev,
+                     w.mask, 1, ctrl);
+  const int64_t rows = A.rows;
+  const int G = A.group;
+  const unsigned nb = (unsigned)((rows + 1 + SB_NT / G - 1) / (SB_NT / G));
+  const uint8_t *lf = A.nlong ? w.long_flag : nullptr;
+  RG_SWITCH_G(G, hipLaunchKernelGGL((sub_count<T, GG>), dim3(nb), dim3(SB_NT),
+                                    0, st, A, w.mask, w.cnt, lf, ctrl));
+  if (lf)
+    hipLaunchKernelGGL(sub_count_long<T>, dim3((unsigned)A.nlong), dim3(SB_NT),
+                       0, st, A, w.mask, w.cnt, ctrl);
+  const int64_t nt = sub_scan_tiles(rows + 1);
+  hipLaunchKernelGGL(sub_scan_a, dim3((unsigned)nt), dim3(SB_NT), 0, st, w.cnt,
+                     rows + 1, w.tile, ctrl);
+  hipLaunchKernelGGL(sub_scan_b, dim3(1), dim3(1024), 0, st, w.tile, nt, ctrl);
+  hipLaunchKernelGGL(sub_scan_c, dim3((unsigned)nt), dim3(SB_NT), 0, st, w.cnt,
+                     rows + 1, w.tile, w.ptr, ctrl);
+  RG_SWITCH_G(G, hipLaunchKernelGGL((sub_fill<T, GG>), dim3(nb), dim3(SB_NT),
+                                    0, st, A, w.mask, w.ptr, w.idx, (T *)w.val,
+                                    lf, ctrl));
+  if (lf)
+    hipLaunchKernelGGL(sub_fill_long<T>, dim3((unsigned)A.nlong), dim3(SB_NT),
+                       0, st, A, w.mask, w.ptr, w.idx, (T *)w.val, ctrl);
+  hipLaunchKernelGGL(sub_mark, dim3(gm), dim3(SB_NT), 0, st, list, count_dev,
+                     w.mask, 0, ctrl);
+  Csr<T> B = A;
+  B.ptr = w.ptr;
+  B.idx = w.idx;
+  B.val = (const T *)w.val;
+  B.nnz = w.cap;
+  B.group = w.group;
+  // A's long rows stay long segments (one workgroup each) in the copy
+  B.long_flag = w.long_flag;
+  B.mp_rs = nullptr;     // no merge plan: row-split passes only
+  B.mp_nchunk = 0;
+  return B;
+}
+template Csr<double> launch_sub_matrix<double>(const Csr<double> &, const int32_t *, const int64_t *, int64_t, SubWork &, Ctrl *, hipStream_t);
+template Csr<float> launch_sub_matrix<float>(const Csr<float> &, const int32_t *, const int64_t *, int64_t, SubWork &, Ctrl *, hipStream_t);
 
 // ------------------------------------------------------------ tall row blocks
 // A row block with more rows than A has columns (k_row > n) is in general

@@ -104,6 +104,7 @@ struct Engine {
   // sparse block work
   SparseCg<T> scc, scr;
   TallWork<T> tall;          // row blocks taller than A is wide (CGLS)
+  SubWork subc, subr;        // block-restricted CSR (columns U) / CSC (rows J)
   bool tall_rows = false;
   SelectScratch sel;
   Reduce red;
@@ -378,6 +379,7 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       sc.v = P.alloc<T>(2 * cap);
       const int64_t nb = std::max(e.m, e.n) / 4 + cap / 4 + 1024;
       sc.part = P.alloc<double>(nb);
+      sc.part_cap = nb;
       sc.split = (h->p.flags & RGDBEK_FLAG_CG_SPLIT) ? 1 : 0;
       // long segments (one replica of A): block positions, -1 outside
       if (h->rep == 1 && (a.nlong || at.nlong)) {
@@ -386,6 +388,28 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
         HIPCHK(hipMemsetAsync(sc.pos, 0xff, sizeof(int32_t) * d, h->st));
         sc.plong = P.alloc<double>(std::max(a.nlong, at.nlong) + 64);
       }
+    }
+    // block-restricted copies for the CG's wide products (one replica of
+    // A; the many-right-hand-side operator keeps the full passes)
+    if (h->rep == 1 && !(h->p.flags & RGDBEK_FLAG_SPARSE_FULL)) {
+      auto sub = [&](SubWork &w, const Csr<T> &M, int64_t kblk, int64_t dcol) {
+        w.cap = h->nnz;
+        w.ptr = P.alloc<int64_t>(M.rows + 2);
+        w.cnt = P.alloc<int64_t>(M.rows + 2);
+        w.tile = P.alloc<int64_t>(sub_scan_tiles(M.rows + 1) + 2);
+        w.idx = P.alloc<int32_t>(h->nnz + 64, false);
+        w.val = P.alloc<T>(h->nnz + 64, false);
+        w.mask = P.alloc<int32_t>(dcol + 64);
+        w.long_flag = P.alloc<uint8_t>(M.rows + 64);
+        launch_mark_long<T>(M, w.long_flag, h->st);
+        // the copy's rows are shorter, but keep A's lanes per row: the
+        // lanes of a row load their entries' gathers in parallel, and a
+        // row of moderate length would otherwise walk them one by one
+        (void)kblk;
+        w.group = M.group;
+      };
+      sub(e.subc, a, e.kc, e.n);
+      sub(e.subr, at, e.kr, e.m);
     }
     // Small single systems: the Gram matrices of all columns and all rows,
     // formed once through a dense copy, turn each block projection into a
@@ -680,7 +704,10 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
                                   e.z, c, 1, st);
   } else {
     ProfScope ps(h, RGDBEK_PROF_COL_SOLVE, 0);
-    launch_sparse_colproj<T>(e.csr, e.csc, e.U, cntU, e.kc, e.g, e.z, e.scc,
+    const Csr<T> wcsr = e.subc.idx ? launch_sub_matrix<T>(e.csr, e.U, cntU, e.kc,
+                                                          e.subc, c, st)
+                                   : e.csr;
+    launch_sparse_colproj<T>(wcsr, e.csc, e.U, cntU, e.kc, e.g, e.z, e.scc,
                              maxs, itol, c, 1, st);
   }
   // ---- row phase: r = b - z - A x, eps^x, stop test, select J, project x
@@ -781,7 +808,10 @@ void enqueue_iteration(rgdbek_ctx *h, Engine<T> &e, const IterOpts &o) {
                                   e.x, c, 1, st);
   } else {
     ProfScope ps(h, RGDBEK_PROF_ROW_SOLVE, 1);
-    launch_sparse_rowproj<T>(e.csr, e.csc, e.J, cntJ, e.kr, e.r, e.rho, e.x,
+    const Csr<T> wcsc = e.subr.idx ? launch_sub_matrix<T>(e.csc, e.J, cntJ, e.kr,
+                                                          e.subr, c, st)
+                                   : e.csc;
+    launch_sparse_rowproj<T>(e.csr, wcsc, e.J, cntJ, e.kr, e.r, e.rho, e.x,
                              e.scr, maxs, itol, c, 1, st);
   }
   ProfScope ps(h, RGDBEK_PROF_STOP);

@@ -41,7 +41,7 @@ class Solver:
                  solver=B.SOLVER_AUTO, graph=True, gram_aat=False,
                  weight_floor=0.0, tile_rows=0, select="random",
                  cg_split=False, sparse_cg=False, profile=False, pass_drop=0.0,
-                 stream=None):
+                 sparse_full=False, stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -88,7 +88,8 @@ class Solver:
                    (B.FLAG_GRAM_AAT if gram_aat else 0) |
                    (B.FLAG_CG_SPLIT if cg_split else 0) |
                    (B.FLAG_SPARSE_CG if sparse_cg else 0) |
-                   (B.FLAG_PROFILE if profile else 0))
+                   (B.FLAG_PROFILE if profile else 0) |
+                   (B.FLAG_SPARSE_FULL if sparse_full else 0))
         self.m, self.n = int(m), int(n)
         self.params = p
         self.stream = stream
@@ -205,7 +206,8 @@ class BatchSolver(Solver):
     def __init__(self, csr, row_off, col_off, *, eta=0.1, k_col=0, k_row=0,
                  tol=1e-8, stop="err_ref", max_iter=10000, seed=0,
                  precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
-                 graph=True, weight_floor=0.0, select="random", stream=None):
+                 graph=True, weight_floor=0.0, select="random", pass_drop=0.0,
+                 profile=False, sparse_full=False, stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -230,8 +232,11 @@ class BatchSolver(Solver):
                        else int(precision))
         p.max_iter, p.seed = max_iter, seed
         p.inner_max, p.inner_tol, p.graph_iters = inner_max, inner_tol, graph_iters
-        p.flags = B.FLAG_GRAPH if graph else 0
+        p.flags = ((B.FLAG_GRAPH if graph else 0) |
+                   (B.FLAG_PROFILE if profile else 0) |
+                   (B.FLAG_SPARSE_FULL if sparse_full else 0))
         p.weight_floor = float(weight_floor)
+        p.pass_drop = float(pass_drop)
         p.select_mode = {"random": B.SELECT_RANDOM, "greedy": B.SELECT_GREEDY,
                          "block_law": B.SELECT_BLOCK_LAW,
                          "iid": B.SELECT_IID}[select]
@@ -257,7 +262,8 @@ class MultiRhsSolver(BatchSolver):
     def __init__(self, csr, shape, nrhs, *, eta=0.1, k_col=0, k_row=0,
                  tol=1e-8, stop="err_ref", max_iter=10000, seed=0,
                  precision="fp64", inner_max=0, inner_tol=0.0, graph_iters=0,
-                 graph=True, weight_floor=0.0, stream=None):
+                 graph=True, weight_floor=0.0, pass_drop=0.0, profile=False,
+                 stream=None):
         lib = B.load()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -279,8 +285,10 @@ class MultiRhsSolver(BatchSolver):
                        else int(precision))
         p.max_iter, p.seed = max_iter, seed
         p.inner_max, p.inner_tol, p.graph_iters = inner_max, inner_tol, graph_iters
-        p.flags = B.FLAG_GRAPH if graph else 0
+        p.flags = ((B.FLAG_GRAPH if graph else 0) |
+                   (B.FLAG_PROFILE if profile else 0))
         p.weight_floor = float(weight_floor)
+        p.pass_drop = float(pass_drop)
         self.nsys = int(nrhs)
         self.base_shape = (int(m), int(n))
         self.m, self.n, self.params, self.stream = m * nrhs, n * nrhs, p, stream

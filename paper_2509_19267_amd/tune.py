@@ -192,3 +192,68 @@ def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
             str(g).lower(): round(1e3 * (t + c), 1) for g, (t, c) in costs.items()}
     store("dense", m, n, precision, ch)
     return ch
+
+
+def tune_sparse(make, b, x_ref, *, key, tol=1e-8, log=print, reps=1,
+                etas=(0.05, 0.1, 0.2), inner=((0.3, 4), (0.1, 8), (0.1, 16),
+                                              (0.03, 16)),
+                graph_iters=(4, 8, 16), pass_drops=()):
+    """Tune a sparse solve (single system, batch or many right-hand sides):
+    `make(eta=, inner_tol=, inner_max=, graph_iters=[, pass_drop=])` builds a
+    handle with stop ERR_REF at tol; each setting is timed over `reps`
+    solves after one warm-up solve (graph capture).  Block fraction and
+    inner settings first, then the iterations per captured graph, then (for
+    the mixed form) the drop that ends a refinement pass, each at the best
+    of the earlier stages; the fastest converging choice is cached under
+    `key` and returned."""
+    import torch
+
+    def run(ch, best):
+        try:
+            s = make(**ch)
+        except Exception as e:  # noqa: BLE001
+            log(f"tune {key} {ch}: failed: {e}")
+            return best
+        try:
+            s.solve(b, x_ref=x_ref)
+            ts, ok, its = [], True, 0
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = s.solve(b, x_ref=x_ref)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                ok = ok and bool(info["converged"])
+                its = info["iterations"]
+        finally:
+            s.close()
+        t = min(ts)
+        log(f"tune {key} {ch}: {1e3 * t:.1f} ms ({its} it, converged={ok})")
+        if ok and (best is None or t < best[0]):
+            return (t, dict(ch, solve_ms=round(1e3 * t, 2), iterations=its))
+        return best
+
+    best = None
+    for eta in etas:
+        for itol, imax in inner:
+            best = run(dict(eta=eta, inner_tol=itol, inner_max=imax,
+                            graph_iters=8), best)
+    if best is None:
+        raise RuntimeError(f"no configuration of {key} converged")
+    base = {k: best[1][k] for k in ("eta", "inner_tol", "inner_max")}
+    for gi in graph_iters:
+        if gi != 8:
+            best = run(dict(base, graph_iters=gi), best)
+    if pass_drops:
+        base = {k: best[1][k] for k in ("eta", "inner_tol", "inner_max",
+                                        "graph_iters")}
+        for pd in pass_drops:
+            best = run(dict(base, pass_drop=pd), best)
+    c = _load()
+    c[key] = best[1]
+    try:
+        with open(CACHE, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+    except OSError:
+        pass
+    return best[1]

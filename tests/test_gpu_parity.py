@@ -208,6 +208,38 @@ def test_trajectory_sparse_powerlaw(rg):
     assert rel(z, zo) <= TRAJ_TOL
 
 
+@pytest.mark.parametrize("shape,kc,kr,mean,rows", [((6000, 3000), 300, 600, 10, 400),
+                                                   ((20000, 9000), 900, 2000, 30, 2000)])
+def test_sparse_block_restricted_equals_full(rg, shape, kc, kr, mean, rows):
+    # the CG's wide products over the block's own entries (copied once per
+    # iteration) against the products over all of A: the same sums grouped
+    # differently across lanes, so both at the oracle's trajectory and at
+    # rounding distance of each other; power-law rows include long ones (up
+    # to `rows` entries: one workgroup each in the full passes, G lanes in
+    # the block copy); with mean length 10 some row blocks are
+    # rank-deficient (rows sharing their single column), and CG on the
+    # singular consistent Gram needs many steps
+    m, n = shape
+    p = workloads.sparse_powerlaw(m, n, mean_len=mean, max_len=rows, seed=21)
+    xs = []
+    for full in (False, True):
+        s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, k_col=kc,
+                      k_row=kr, stop="none", max_iter=3, seed=4,
+                      inner_max=1000, graph_iters=1, sparse_cg=True,
+                      sparse_full=full)
+        x, _ = s.solve(dev(p.b))
+        xs.append((x.cpu().numpy(), s.get_z().cpu().numpy()))
+        s.close()
+    xo, zo, _ = rgdbek(p.a, p.b, k_col=kc, k_row=kr, max_iter=3, seed=4)
+    print(f"restricted sparse {shape}: rel_x {rel(xs[0][0], xo):.3e} "
+          f"full {rel(xs[1][0], xo):.3e} between {rel(xs[0][0], xs[1][0]):.3e}",
+          flush=True)
+    for x, z in xs:
+        assert rel(x, xo) <= TRAJ_TOL
+        assert rel(z, zo) <= TRAJ_TOL
+    assert rel(xs[0][0], xs[1][0]) <= 1e-12
+
+
 def test_solution_sparse_consistent(rg):
     p = workloads.sparse_powerlaw(6000, 3000, mean_len=10, max_len=400, seed=5)
     s = rg.Solver(csr=csr_tensors(p.a), shape=p.a.shape, eta=0.1,
