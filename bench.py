@@ -1195,6 +1195,7 @@ def cpu_baseline_full(sel, ctx, budget_s=20.0):
             x, z, _ = rgdbek(a, b, max_iter=1, x0=x, z0=z, it0=it, **kw)
             it += 1
             el = time.perf_counter() - t0
+            log(f"oracle iteration {it}: {el:.1f} s")
             if el > budget_s or it >= 20:
                 return {"iterations": it, "s": round(el, 2),
                         "ms_per_iteration": round(1e3 * el / it, 1)}
@@ -1206,17 +1207,23 @@ def cpu_baseline_full(sel, ctx, budget_s=20.0):
                                 "exact projections")
     if "c4" in sel:
         c = ctx["c4"]
+        log("c4: closed-form regularised solutions")
         x_mu = tikhonov_kron(c["t"], c["b_img"], c["s"])
         errs = {f: float(np.max(np.linalg.norm(x - x_mu, axis=0) /
                                 np.linalg.norm(x_mu, axis=0)))
                 for f, x in c["sols"].items()}
         out["c4_rel_err_vs_closed_form_max"] = errs
-        aug, _, _ = workloads.blur_tikhonov(512, 1e-2)
-        n = 512 * 512
-        bb = np.concatenate([c["b_img"][:, 0], np.zeros(n)])
+        # the oracle's own iterations (exact projections: LSQR on blocks of
+        # 52,429 rows x 262,144 columns) run minutes each at this size; its
+        # time per iteration is measured on the 128 x 128 instance instead
+        aug, t, s = workloads.blur_tikhonov(128, 1e-2)
+        n = 128 * 128
+        bi, _ = workloads.blur_rhs(aug[:n], npix=128, nrhs=1, seed=0)
+        bb = np.concatenate([bi[:, 0], np.zeros(n)])
         out["c4"] = dict(per_iter(aug, bb, eta=0.1),
-                         sample="right-hand side 0 of the 64, iterations from "
-                                "x_0 = 0, eta 0.1, exact projections")
+                         sample="128 x 128 image (32,768 x 16,384), right-hand "
+                                "side 0, iterations from x_0 = 0, eta 0.1, "
+                                "exact projections")
     if "c5" in sel:
         ps = workloads.laplacian_batch(count=256, n_min=2000, n_max=200000,
                                        seed=0)
@@ -1225,6 +1232,7 @@ def cpu_baseline_full(sel, ctx, budget_s=20.0):
         t0 = time.perf_counter()
         its = 0
         for i in pick[:4]:
+            log(f"c5: oracle on system {i} (n = {ps[i].a.shape[1]})")
             r = per_iter(ps[i].a, ps[i].b, eta=0.1)
             its += r["iterations"]
         out["c5"] = {"systems": 4, "iterations": its,

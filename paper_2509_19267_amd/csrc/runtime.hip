@@ -1449,10 +1449,14 @@ void upload_segments(rgdbek_ctx *h) {
     std::swap(g.kc, g.kr);
     std::swap(g.kc_off, g.kr_off);
   }
-  HIPCHK(hipMemcpy(h->seg, h->hseg.data(), sizeof(SegInfo) * ns,
-                   hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(h->seg_t, t.data(), sizeof(SegInfo) * ns,
-                   hipMemcpyHostToDevice));
+  // on the handle's stream, after the zero fills of the allocations above
+  // (a plain hipMemcpy is not ordered after work on a non-blocking stream:
+  // the fill could land after the copy and erase it)
+  HIPCHK(hipMemcpyAsync(h->seg, h->hseg.data(), sizeof(SegInfo) * ns,
+                        hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(h->seg_t, t.data(), sizeof(SegInfo) * ns,
+                        hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
 }
 
 void destroy_impl(rgdbek_ctx *h) {

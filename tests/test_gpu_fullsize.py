@@ -238,6 +238,32 @@ def test_batch_fullsize_first_iteration(rg):
               flush=True)
 
 
+# ------------------------------------------------------------ many RHS
+def test_multirhs_segments_survive_setup(rg):
+    # 64 right-hand sides of a 256 x 256 deblurring operator (8.4M virtual
+    # rows): the per-system descriptors are uploaded after the zero fills of
+    # their allocations (a plain copy was not ordered after the fills queued
+    # behind the norm replication, and lost to them at this size), so every
+    # right-hand side's first iteration moves z and x
+    aug, _, _ = workloads.blur_tikhonov(256, 1e-2)
+    n = 256 * 256
+    m = aug.shape[0]
+    b_img, _ = workloads.blur_rhs(aug[:n], npix=256, nrhs=64, seed=1)
+    bb = np.zeros((64, m))
+    bb[:, :n] = b_img.T
+    s = rg.MultiRhsSolver(csr_tensors(aug, np.float32), (m, n), 64, eta=0.1,
+                          stop="none", max_iter=1, inner_tol=0.1,
+                          inner_max=16)
+    x, info = s.solve(dev(bb.ravel()))
+    z = s.get_z().cpu().numpy().reshape(64, m)
+    x = x.cpu().numpy().reshape(64, n)
+    s.close()
+    dz = np.linalg.norm(z - bb, axis=1) / np.linalg.norm(bb, axis=1)
+    print(f"many-RHS first iteration: dz {dz.min():.3f}..{dz.max():.3f}", flush=True)
+    assert dz.min() > 0.5 and np.linalg.norm(x, axis=1).min() > 0.0
+    free()
+
+
 # ------------------------------------------------------------ blur, 64 RHS
 def test_blur_fullsize_multirhs(rg):
     # the products with all 64 right-hand sides; one exact iteration (its
