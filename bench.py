@@ -928,6 +928,32 @@ def c5_batch(count=256, tol=1e-8, subset=32, tune_now=False):
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
         its, met, conv = s.batch_info()
+        # the batched residual passes alone (CSR + CSC over all systems,
+        # rgdbek_apply), HIP events on the handle's stream
+        prec, dt, vb = (("f64", torch.float64, 8) if form == "fp64"
+                        else ("f32", torch.float32, 4))
+        mm, nn = int(ro[-1]), int(co[-1])
+        xv = torch.randn(nn, dtype=dt, device="cuda")
+        zv = torch.randn(mm, dtype=dt, device="cuda")
+        ax = torch.empty(mm, dtype=dt, device="cuda")
+        atz = torch.empty(nn, dtype=dt, device="cuda")
+        for _ in range(3):
+            s.apply(xv, zv, ax, atz, precision=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(10):
+            s.apply(xv, zv, ax, atz, precision=prec)
+        e1.record(st)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / 10
+        nnz = int(c[2].numel())
+        alg = 2 * nnz * (vb + 4) + 8 * (mm + 1) + 8 * (nn + 1) + 2 * vb * (mm + nn)
+        pass_pair = {"us": round(us, 1), "alg_bytes": alg,
+                     "GB/s": round(alg / us / 1e3, 1),
+                     "frac": round(alg / us / 1e3 / PEAK_HBM_GBS, 4)}
+        del xv, zv, ax, atz
         s.close()
         xh = x.cpu().numpy()
         errs = [float(np.linalg.norm(xh[co[i]:co[i + 1]] - ps[i].x_star) /
@@ -936,7 +962,8 @@ def c5_batch(count=256, tol=1e-8, subset=32, tune_now=False):
                      "outer": int(info["outer_iterations"]),
                      "converged_systems": int(sum(bool(q) for q in conv)),
                      "rel_err_max": max(errs), "create_s": round(create, 3),
-                     "choice": kw}
+                     "ms_per_iteration": round(1e3 * el / max(int(info["iterations"]), 1), 3),
+                     "residual_pass_pair": pass_pair, "choice": kw}
         log(f"c5 {form}: {out[form]}")
     kw = {k: chs["fp64"][k] for k in SPARSE_KEYS if k in chs["fp64"]}
     tot, its_tot = 0.0, 0
@@ -1214,14 +1241,17 @@ def cpu_baseline_full(sel, ctx, budget_s=20.0):
                 for f, x in c["sols"].items()}
         out["c4_rel_err_vs_closed_form_max"] = errs
         # the oracle's own iterations (exact projections: LSQR on blocks of
-        # 52,429 rows x 262,144 columns) run minutes each at this size; its
-        # time per iteration is measured on the 128 x 128 instance instead
-        aug, t, s = workloads.blur_tikhonov(128, 1e-2)
-        n = 128 * 128
-        bi, _ = workloads.blur_rhs(aug[:n], npix=128, nrhs=1, seed=0)
+        # 52,429 rows x 262,144 columns) run far beyond the sample budget at
+        # this size, and already at 96 x 96 (over 2 minutes each, LSQR on
+        # the ill-conditioned blur blocks); its time per iteration is
+        # measured on the 64 x 64 instance, whose blocks take the dense SVD
+        # branch
+        aug, t, s = workloads.blur_tikhonov(64, 1e-2)
+        n = 64 * 64
+        bi, _ = workloads.blur_rhs(aug[:n], npix=64, nrhs=1, seed=0)
         bb = np.concatenate([bi[:, 0], np.zeros(n)])
         out["c4"] = dict(per_iter(aug, bb, eta=0.1),
-                         sample="128 x 128 image (32,768 x 16,384), right-hand "
+                         sample="64 x 64 image (8,192 x 4,096), right-hand "
                                 "side 0, iterations from x_0 = 0, eta 0.1, "
                                 "exact projections")
     if "c5" in sel:

@@ -97,7 +97,7 @@ def tikhonov_kron(t, b_img, s):
     bm = b_img.reshape(p * p, -1)
     out = np.empty_like(bm)
     for c in range(bm.shape[1]):
-        bimg = bm[:, c].reshape(p, p)
+        bimg = np.ascontiguousarray(bm[:, c]).reshape(p, p)
         y = q.T @ bimg @ q
         out[:, c] = (q @ (f * y) @ q.T).ravel()
     return out[:, 0] if single else out

@@ -1772,6 +1772,9 @@ template void launch_sparse_block_update<float>(
 // pass's, so the two agree to rounding.
 //   mark:   mask[list_a] = 1
 //   count:  cnt_r = #{e in row r : mask[idx_e]}            (G lanes per row)
+// For the replicated operator I_rep (x) A of many right-hand sides the copy
+// is a plain matrix over the virtual rows and columns: each right-hand side
+// keeps the entries of its own block.
 //   scan:   ptr = exclusive prefix sum of cnt             (three launches)
 //   fill:   each row's marked entries, in order, to ptr_r (ballot ranks)
 //   unmark: mask[list_a] = 0
@@ -1799,8 +1802,11 @@ sub_count(Csr<T> A, const int32_t *__restrict__ mask, int64_t *__restrict__ cnt,
   int64_t k = 0;
   const bool mine = r < A.rows && !(long_flag && long_flag[r]);   // sub_count_long
   if (mine) {
-    const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
-    for (int64_t e = e0 + lg; e < e1; e += G) k += mask[A.idx[e]] ? 1 : 0;
+    int64_t br, co;      // stored row and column offset (replicated A)
+    gsplit(A, r, br, co);
+    const int32_t *mk = mask + co;
+    const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
+    for (int64_t e = e0 + lg; e < e1; e += G) k += mk[A.idx[e]] ? 1 : 0;
   }
   k = group_sum<G>(k);
   if (mine && lg == 0) cnt[r] = k;
@@ -1888,7 +1894,9 @@ sub_fill(Csr<T> A, const int32_t *__restrict__ mask,
   const int gbase = lane & ~(G - 1);          // first lane of the group
   const int64_t r = (int64_t)blockIdx.x * SPB + threadIdx.x / G;
   const bool live = r < A.rows && !(long_flag && long_flag[r]);  // sub_fill_long
-  const int64_t e0 = live ? A.ptr[r] : 0, e1 = live ? A.ptr[r + 1] : 0;
+  int64_t br = 0, co = 0;   // stored row and column offset (replicated A)
+  if (live) gsplit(A, r, br, co);
+  const int64_t e0 = live ? A.ptr[br] : 0, e1 = live ? A.ptr[br + 1] : 0;
   int64_t pos = live ? ptr[r] : 0;
   // every lane of a wave runs the same trip count (ballots need the whole
   // wave): the longest segment of the wave's groups
@@ -1902,7 +1910,7 @@ sub_fill(Csr<T> A, const int32_t *__restrict__ mask,
   for (int64_t c = 0; c < len; c += G) {
     const int64_t e = e0 + c + lg;
     const bool in = e < e1;
-    const int32_t j = in ? A.idx[e] : 0;
+    const int32_t j = in ? (int32_t)(co + A.idx[e]) : 0;
     const bool take = in && mask[j] != 0;
     const unsigned long long bal = __ballot(take);
     const unsigned long long mine = bal & gmask;
@@ -1994,7 +2002,7 @@ Csr<T> launch_sub_matrix(const Csr<T> &A, const int32_t *list,
   const int64_t rows = A.rows;
   const int G = A.group;
   const unsigned nb = (unsigned)((rows + 1 + SB_NT / G - 1) / (SB_NT / G));
-  const uint8_t *lf = A.nlong ? w.long_flag : nullptr;
+  const uint8_t *lf = (A.nlong && A.rep == 1) ? w.long_flag : nullptr;
   RG_SWITCH_G(G, hipLaunchKernelGGL((sub_count<T, GG>), dim3(nb), dim3(SB_NT),
                                     0, st, A, w.mask, w.cnt, lf, ctrl));
   if (lf)
@@ -2020,8 +2028,20 @@ Csr<T> launch_sub_matrix(const Csr<T> &A, const int32_t *list,
   B.val = (const T *)w.val;
   B.nnz = w.cap;
   B.group = w.group;
-  // A's long rows stay long segments (one workgroup each) in the copy
-  B.long_flag = w.long_flag;
+  if (A.rep == 1) {
+    // A's long rows stay long segments (one workgroup each) in the copy
+    B.long_flag = w.long_flag;
+  } else {
+    // the replicated operator I_rep (x) A: the copy is a plain matrix over
+    // the virtual rows and columns (column indices already offset)
+    B.rep = 1;
+    B.brows = A.rows;
+    B.bcols = A.cols;
+    B.longs = nullptr;
+    B.nlong = 0;
+    B.long_limit = 0;
+    B.long_flag = nullptr;
+  }
   B.mp_rs = nullptr;     // no merge plan: row-split passes only
   B.mp_nchunk = 0;
   return B;

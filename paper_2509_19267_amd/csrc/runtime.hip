@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -292,7 +293,11 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       ata = f.aat;
       aat = f.ata;
     }
-    const bool gram_cols = e.kc > 64 && (ata || e.n <= 8192);
+    // the FP64 engine of a mixed handle only runs the refinement's residual
+    // passes: its block solves (a resumed solve) form their Grams from A
+    const bool mixed64 = f64 && !transpose &&
+                         h->p.precision == RGDBEK_PREC_MIXED_F32;
+    const bool gram_cols = !mixed64 && e.kc > 64 && (ata || e.n <= 8192);
     if (gram_cols) {
       if (!ata) {
         T *F = P.alloc<T>(e.n * e.n, false);
@@ -301,8 +306,8 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       }
       e.ata = ata;
     }
-    const bool gram_rows =
-        aat || ((h->p.flags & RGDBEK_FLAG_GRAM_AAT) && e.m <= 32768);
+    const bool gram_rows = !mixed64 &&
+        (aat || ((h->p.flags & RGDBEK_FLAG_GRAM_AAT) && e.m <= 32768));
     if (gram_rows) {
       if (!aat) {
         T *F = P.alloc<T>(e.m * e.m, false);
@@ -391,25 +396,52 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     }
     // block-restricted copies for the CG's wide products (one replica of
     // A; the many-right-hand-side operator keeps the full passes)
-    if (h->rep == 1 && !(h->p.flags & RGDBEK_FLAG_SPARSE_FULL)) {
-      auto sub = [&](SubWork &w, const Csr<T> &M, int64_t kblk, int64_t dcol) {
-        w.cap = h->nnz;
+    // Entry capacity of the copies: all of A for one stored matrix; for the
+    // many-RHS operator, per right-hand side the entries of its k longest
+    // columns (rows), times the right-hand sides.
+    int64_t capc = h->nnz, capr = h->nnz;
+    if (h->rep > 1) {
+      auto topk = [&](const int64_t *ptr_dev, int64_t len, int64_t k) {
+        std::vector<int64_t> pp(len + 1), ln(len);
+        HIPCHK(hipMemcpy(pp.data(), ptr_dev, sizeof(int64_t) * (len + 1),
+                         hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < len; ++i) ln[i] = pp[i + 1] - pp[i];
+        k = std::min<int64_t>(k, len);
+        std::nth_element(ln.begin(), ln.begin() + (k > 0 ? k - 1 : 0), ln.end(),
+                         std::greater<int64_t>());
+        int64_t t = 0;
+        for (int64_t i = 0; i < k; ++i) t += ln[i];
+        return t;
+      };
+      const int64_t kcs = e.kc / h->rep, krs = e.kr / h->rep;
+      // forward engine: columns of A are CSC segments, rows CSR segments
+      capc = h->rep * topk(transpose ? h->csr_ptr : h->csc_ptr,
+                           transpose ? h->bm : h->bn, kcs);
+      capr = h->rep * topk(transpose ? h->csc_ptr : h->csr_ptr,
+                           transpose ? h->bn : h->bm, krs);
+    }
+    const double sub_bytes = (double)(capc + capr) * (4.0 + sizeof(T));
+    if (!(h->p.flags & RGDBEK_FLAG_SPARSE_FULL) &&
+        (h->rep == 1 || sub_bytes <= 48.0 * (1ull << 30))) {
+      auto sub = [&](SubWork &w, const Csr<T> &M, int64_t cap, int64_t dcol) {
+        w.cap = cap;
         w.ptr = P.alloc<int64_t>(M.rows + 2);
         w.cnt = P.alloc<int64_t>(M.rows + 2);
         w.tile = P.alloc<int64_t>(sub_scan_tiles(M.rows + 1) + 2);
-        w.idx = P.alloc<int32_t>(h->nnz + 64, false);
-        w.val = P.alloc<T>(h->nnz + 64, false);
+        w.idx = P.alloc<int32_t>(w.cap + 64, false);
+        w.val = P.alloc<T>(w.cap + 64, false);
         w.mask = P.alloc<int32_t>(dcol + 64);
-        w.long_flag = P.alloc<uint8_t>(M.rows + 64);
-        launch_mark_long<T>(M, w.long_flag, h->st);
+        if (M.rep == 1) {   // long rows of one stored matrix
+          w.long_flag = P.alloc<uint8_t>(M.rows + 64);
+          launch_mark_long<T>(M, w.long_flag, h->st);
+        }
         // the copy's rows are shorter, but keep A's lanes per row: the
         // lanes of a row load their entries' gathers in parallel, and a
         // row of moderate length would otherwise walk them one by one
-        (void)kblk;
         w.group = M.group;
       };
-      sub(e.subc, a, e.kc, e.n);
-      sub(e.subr, at, e.kr, e.m);
+      sub(e.subc, a, capc, e.n);
+      sub(e.subr, at, capr, e.m);
     }
     // Small single systems: the Gram matrices of all columns and all rows,
     // formed once through a dense copy, turn each block projection into a
