@@ -18,7 +18,7 @@ LIBNAME = "librgdbek.so"
 ARCH = "gfx950"
 
 SOURCES = ["select.hip", "spmv.hip", "proj.hip", "utils.hip", "batch.hip",
-           "runtime.hip"]
+           "rep.hip", "runtime.hip"]
 # Bit-exact selection needs unfused, correctly rounded FP64 operations.
 EXTRA = {"select.hip": ["-ffp-contract=off"]}
 

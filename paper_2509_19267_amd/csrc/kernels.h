@@ -139,6 +139,9 @@ struct Csr {                 // CSR (or CSC viewed as CSR of the transpose)
   // Virtual segments are visited in RHS-minor order (slot = i * rep + s) so
   // the rep reads of one stored row follow each other and hit in cache.
   int64_t rep = 1, brows = 0, bcols = 0;
+  // Interleaved scratch of the many-right-hand-side products (rep >=
+  // REP_MM_MIN): max(brows, bcols) * rep entries each, input and output.
+  T *rep_in = nullptr, *rep_out = nullptr;
 };
 
 // slot of a full sweep -> global row, stored row, column offset
@@ -344,6 +347,9 @@ struct SparseCg {
   int32_t *pos = nullptr;   // block position of each index, -1 outside
   double *plong = nullptr;  // one partial per long segment
   int split = 0;            // many-workgroup step finish at any block size
+  // many right-hand sides (rep >= REP_MM_MIN): interleaved product buffers,
+  // max(brows, bcols) * rep entries each
+  T *t0 = nullptr, *t1 = nullptr, *t2 = nullptr;
 };
 // Small sparse systems (both dimensions up to SPARSE_GRAM_MAX): dense
 // copies for the Gram matrices, and the block update out += sign A_L coef
@@ -466,5 +472,28 @@ struct ProfRec {
 };
 void launch_prof_mark(const Ctrl *ctrl, ProfRec *rec, int post, int ph,
                       hipStream_t st);
+
+// ------------------------------------------------------------ many RHS
+// With many right-hand sides sharing A (the replicated operator I_rep (x) A)
+// the products run over interleaved vectors -- entry j of right-hand side s
+// at j * rep + s -- so one read of each stored entry serves every
+// right-hand side and the gathered values of one entry are contiguous.
+// Vectors stay right-hand-side-major elsewhere; the transposes convert.
+constexpr int64_t REP_MM_MIN = 16;
+// out[r * rep + s] = sum_e A.val[e] * in[A.idx[e] * rep + s] over the stored
+// rows r < A.brows; part (nullable): per-workgroup sums of out^2, returns
+// their count.  ph >= 0: skipped once the CG of that phase is done.
+template <typename T>
+int launch_rep_mm(const Csr<T> &A, const T *in, T *out, double *part,
+                  Ctrl *ctrl, int ph, int respect_done, hipStream_t st);
+// in[s * len + i] -> out[i * rep + s]
+template <typename T>
+void launch_rep_tin(const T *in, T *out, int64_t len, int64_t rep, Ctrl *ctrl,
+                    int ph, int respect_done, hipStream_t st);
+// in[i * rep + s] -> out[s * len + i]; with x: x += alpha_ph * out (the old
+// value) first, alpha_ph = Ctrl::cg_alpha[ph] (the row CG's pending update)
+template <typename T>
+void launch_rep_tout(const T *in, T *out, T *x, int64_t len, int64_t rep,
+                     Ctrl *ctrl, int ph, int respect_done, hipStream_t st);
 
 }  // namespace rg

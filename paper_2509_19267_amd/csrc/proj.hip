@@ -976,8 +976,8 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
               T *__restrict__ z, int64_t m, T *__restrict__ sres,
               T *__restrict__ p, T *__restrict__ phat,
               double *__restrict__ part, const double *__restrict__ plong,
-              int64_t nlong, double tol, int par, int gridm, Ctrl *ctrl,
-              int respect_done) {
+              int64_t nlong, double tol, int par, int gridm,
+              const T *__restrict__ pre, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   if (ld_agent(&ctrl->cg_done[0])) return;
   __shared__ double sh[SC_NT / WAVE];
@@ -1000,11 +1000,15 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
     if (mine) {
       int64_t bc, ro;
       gsplit(At, (int64_t)U[a], bc, ro);
-      const T *qv = q + ro;
-      const int64_t e0 = At.ptr[bc], e1 = At.ptr[bc + 1];
-      if (nlong && e1 - e0 > At.long_limit) mine = false;   // sc_long_narrow
-      else
-        for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * qv[At.idx[e]];
+      if (pre) {   // many right-hand sides: A^T q formed interleaved
+        if (lg == 0) acc = pre[bc * At.rep + (int64_t)U[a] / At.brows];
+      } else {
+        const T *qv = q + ro;
+        const int64_t e0 = At.ptr[bc], e1 = At.ptr[bc + 1];
+        if (nlong && e1 - e0 > At.long_limit) mine = false;   // sc_long_narrow
+        else
+          for (int64_t e = e0 + lg; e < e1; e += G) acc += At.val[e] * qv[At.idx[e]];
+      }
     }
     acc = group_sum<G>(acc);
     if (mine && lg == 0) {
@@ -1354,7 +1358,8 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
               T *__restrict__ zz, T *__restrict__ p, T *__restrict__ v,
               T *__restrict__ phat, double *__restrict__ part,
               const double *__restrict__ plong, int64_t nlong, double tol,
-              int par, int gridm, Ctrl *ctrl, int respect_done) {
+              int par, int gridm, const T *__restrict__ pre, Ctrl *ctrl,
+              int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
   if (ld_agent(&ctrl->cg_done[1])) return;
   __shared__ double sh[SC_NT / WAVE];
@@ -1370,11 +1375,15 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
     if (mine) {
       int64_t brw, co;
       gsplit(A, (int64_t)J[a], brw, co);
-      const T *uv = u + co;
-      const int64_t e0 = A.ptr[brw], e1 = A.ptr[brw + 1];
-      if (nlong && e1 - e0 > A.long_limit) mine = false;   // sc_long_narrow
-      else
-        for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * uv[A.idx[e]];
+      if (pre) {   // many right-hand sides: A u formed interleaved
+        if (lg == 0) acc = pre[brw * A.rep + (int64_t)J[a] / A.brows];
+      } else {
+        const T *uv = u + co;
+        const int64_t e0 = A.ptr[brw], e1 = A.ptr[brw + 1];
+        if (nlong && e1 - e0 > A.long_limit) mine = false;   // sc_long_narrow
+        else
+          for (int64_t e = e0 + lg; e < e1; e += G) acc += A.val[e] * uv[A.idx[e]];
+      }
     }
     acc = group_sum<G>(acc);
     if (mine && lg == 0) {
@@ -1518,7 +1527,24 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
   const bool narrow_grid = par && nbnf > SC_MAXB && (int64_t)nbnf <= w.part_cap;
   const unsigned nbu = std::min<unsigned>(
       (unsigned)((cap + SC_NT - 1) / SC_NT), SC_MAXB);
+  // many right-hand sides: both products over interleaved vectors
+  const bool mm = csr.rep >= REP_MM_MIN && w.t0 != nullptr;
   for (int s = 0; s < max_steps; ++s) {
+    if (mm) {
+      // q = A phat for every right-hand side, ||q||^2 -> alpha; then A^T q
+      launch_rep_tin<T>(w.phat, w.t0, csr.bcols, csr.rep, ctrl, 0,
+                        respect_done, st);
+      const int nbm = launch_rep_mm<T>(csr, w.t0, w.t1, w.part, ctrl, 0,
+                                       respect_done, st);
+      hipLaunchKernelGGL(sc_wide_col_fin<T>, dim3(1), dim3(1024), 0, st,
+                         (const double *)w.part, (int64_t)nbm,
+                         (const double *)nullptr, (int64_t)0, ctrl,
+                         respect_done);
+      launch_rep_tout<T>(w.t1, w.wide, (T *)nullptr, csr.brows, csr.rep, ctrl,
+                         0, respect_done, st);
+      launch_rep_mm<T>(csc, w.t1, w.t2, (double *)nullptr, ctrl, 0,
+                       respect_done, st);
+    } else {
     if (nlw)
       hipLaunchKernelGGL(sc_long_wide<T>, dim3((unsigned)nlw), dim3(SC_NT), 0,
                          st, csr, w.phat, w.wide, (T *)nullptr, w.plong, ctrl,
@@ -1537,6 +1563,7 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
                                                 w.wide, w.part, w.plong, nlw,
                                                 ctrl, respect_done));
     }
+    }
     if (nln)
       hipLaunchKernelGGL(sc_long_narrow<T>, dim3((unsigned)nln), dim3(SC_NT),
                          0, st, csc, w.pos, w.wide, w.res, w.p, w.plong, ctrl,
@@ -1547,7 +1574,9 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
                                    dim3(SC_NT), 0, st, csc, U, count_dev,
                                    w.wide, z, csr.rows, w.res, w.p, w.phat,
                                    w.part, w.plong, nln, tol, par,
-                                   narrow_grid ? 1 : 0, ctrl, respect_done));
+                                   narrow_grid ? 1 : 0,
+                                   mm ? (const T *)w.t2 : (const T *)nullptr,
+                                   ctrl, respect_done));
     if (narrow_grid)
       hipLaunchKernelGGL(sc_narrow_col_fin, dim3(1), dim3(1024), 0, st,
                          (const double *)w.part, (int64_t)nbnf,
@@ -1582,7 +1611,20 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
   const bool narrow_grid = par && nbnf > SC_MAXB && (int64_t)nbnf <= w.part_cap;
   const unsigned nbu = std::min<unsigned>(
       (unsigned)((cap + SC_NT - 1) / SC_NT), SC_MAXB);
+  const bool mm = csr.rep >= REP_MM_MIN && w.t0 != nullptr;
   for (int s = 0; s < max_steps; ++s) {
+    if (mm) {
+      // u = A^T phat for every right-hand side (the pending x += alpha u
+      // applied as u is replaced), then A u
+      launch_rep_tin<T>(w.phat, w.t0, csr.brows, csr.rep, ctrl, 1,
+                        respect_done, st);
+      launch_rep_mm<T>(csc, w.t0, w.t1, (double *)nullptr, ctrl, 1,
+                       respect_done, st);
+      launch_rep_tout<T>(w.t1, w.wide, x, csc.brows, csr.rep, ctrl, 1,
+                         respect_done, st);
+      launch_rep_mm<T>(csr, w.t1, w.t2, (double *)nullptr, ctrl, 1,
+                       respect_done, st);
+    } else {
     if (nlw)
       hipLaunchKernelGGL(sc_long_wide<T>, dim3((unsigned)nlw), dim3(SC_NT), 0,
                          st, csc, w.phat, w.wide, x, w.plong, ctrl, 1,
@@ -1591,6 +1633,7 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                                               dim3(SC_NT), 0, st, csc, w.phat,
                                               w.wide, x, nlw, ctrl,
                                               respect_done));
+    }
     if (nln)
       hipLaunchKernelGGL(sc_long_narrow<T>, dim3((unsigned)nln), dim3(SC_NT),
                          0, st, csr, w.pos, w.wide, w.v + cap, w.p, w.plong,
@@ -1601,8 +1644,9 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                                    dim3(SC_NT), 0, st, csr, J, count_dev,
                                    w.wide, rho, w.res, w.v, w.p,
                                    w.v + cap, w.phat, w.part, w.plong, nln,
-                                   tol, par, narrow_grid ? 1 : 0, ctrl,
-                                   respect_done));
+                                   tol, par, narrow_grid ? 1 : 0,
+                                   mm ? (const T *)w.t2 : (const T *)nullptr,
+                                   ctrl, respect_done));
     if (narrow_grid)
       hipLaunchKernelGGL(sc_narrow_row_fin, dim3(1), dim3(1024), 0, st,
                          (const double *)w.part, (int64_t)nbnf,

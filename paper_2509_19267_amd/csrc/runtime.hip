@@ -372,6 +372,15 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       plan(a, transpose ? h->csc_mp : h->csr_mp);
       plan(at, transpose ? h->csr_mp : h->csc_mp);
     }
+    // many right-hand sides: three interleaved buffers shared by the full
+    // passes (input, product) and the CG steps (direction, two products)
+    T *rb[3] = {nullptr, nullptr, nullptr};
+    if (h->rep >= REP_MM_MIN) {
+      const int64_t len = std::max(a.brows, a.bcols) * h->rep;
+      for (int i = 0; i < 3; ++i) rb[i] = P.alloc<T>(len, false);
+      a.rep_in = at.rep_in = rb[0];
+      a.rep_out = at.rep_out = rb[1];
+    }
     e.csr = a;
     e.csc = at;
     for (int ph = 0; ph < 2; ++ph) {
@@ -386,6 +395,9 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
       sc.part = P.alloc<double>(nb);
       sc.part_cap = nb;
       sc.split = (h->p.flags & RGDBEK_FLAG_CG_SPLIT) ? 1 : 0;
+      sc.t0 = rb[0];
+      sc.t1 = rb[1];
+      sc.t2 = rb[2];
       // long segments (one replica of A): block positions, -1 outside
       if (h->rep == 1 && (a.nlong || at.nlong)) {
         const int64_t d = ph == 0 ? e.n : e.m;
@@ -394,13 +406,12 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
         sc.plong = P.alloc<double>(std::max(a.nlong, at.nlong) + 64);
       }
     }
-    // block-restricted copies for the CG's wide products (one replica of
-    // A; the many-right-hand-side operator keeps the full passes)
-    // Entry capacity of the copies: all of A for one stored matrix; for the
-    // many-RHS operator, per right-hand side the entries of its k longest
-    // columns (rows), times the right-hand sides.
+    // block-restricted copies for the CG's wide products.  Entry capacity
+    // of the copies: all of A for one stored matrix; for a few right-hand
+    // sides, per right-hand side the entries of its k longest columns
+    // (rows), times the right-hand sides.
     int64_t capc = h->nnz, capr = h->nnz;
-    if (h->rep > 1) {
+    if (h->rep > 1 && h->rep < REP_MM_MIN) {
       auto topk = [&](const int64_t *ptr_dev, int64_t len, int64_t k) {
         std::vector<int64_t> pp(len + 1), ln(len);
         HIPCHK(hipMemcpy(pp.data(), ptr_dev, sizeof(int64_t) * (len + 1),
@@ -421,8 +432,11 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
                            transpose ? h->bn : h->bm, krs);
     }
     const double sub_bytes = (double)(capc + capr) * (4.0 + sizeof(T));
+    // (not for many right-hand sides past REP_MM_MIN: their products read
+    // A once for all right-hand sides, a copy per right-hand side would not)
     if (!(h->p.flags & RGDBEK_FLAG_SPARSE_FULL) &&
-        (h->rep == 1 || sub_bytes <= 48.0 * (1ull << 30))) {
+        (h->rep == 1 ||
+         (h->rep < REP_MM_MIN && sub_bytes <= 48.0 * (1ull << 30)))) {
       auto sub = [&](SubWork &w, const Csr<T> &M, int64_t cap, int64_t dcol) {
         w.cap = cap;
         w.ptr = P.alloc<int64_t>(M.rows + 2);

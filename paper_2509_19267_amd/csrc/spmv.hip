@@ -253,9 +253,64 @@ int64_t segdot_max_parts(int64_t rows, int64_t nnz, int64_t nchunk,
   return seg > mer ? seg : mer;
 }
 
+// Full passes of many right-hand sides (A.rep >= REP_MM_MIN): the vector
+// is interleaved, the product formed for all right-hand sides at once
+// (launch_rep_mm), and this epilogue turns the interleaved result back to
+// right-hand-side-major order through a 64 x 64 LDS tile while it applies
+// the pass's epilogue to every (right-hand side, stored row).  Partials: one
+// pair per workgroup.
+template <typename T, int EPI>
+__global__ void __launch_bounds__(SEG_NT)
+rep_epi_kernel(Csr<T> A, SegArgs<T> a, const T *__restrict__ prod, Ctrl *ctrl,
+               int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  __shared__ T tile[WAVE][WAVE + 1];
+  __shared__ double sh[SEG_NT / WAVE];
+  const int64_t R = A.rep, len = A.brows;
+  const int64_t i0 = (int64_t)blockIdx.x * WAVE, s0 = (int64_t)blockIdx.y * WAVE;
+  const int tx = threadIdx.x & (WAVE - 1), ty = threadIdx.x / WAVE;
+  for (int r = ty; r < WAVE; r += SEG_NT / WAVE) {
+    const int64_t i = i0 + r, s = s0 + tx;
+    tile[r][tx] = (i < len && s < R) ? prod[i * R + s] : (T)0;
+  }
+  __syncthreads();
+  double pb = 0.0, pr = 0.0;
+  for (int r = ty; r < WAVE; r += SEG_NT / WAVE) {
+    const int64_t s = s0 + r, i = i0 + tx;
+    if (s < R && i < len) {
+      const int64_t g = s * len + i;
+      seg_epilogue<T>(EPI, a, g, g, tile[tx][r], pb, pr);
+    }
+  }
+  if (EPI == EPI_ROWRES) {
+    pb = block_sum<SEG_NT>(pb, sh);
+    pr = block_sum<SEG_NT>(pr, sh);
+    if (threadIdx.x == 0) {
+      const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+      a.part[2 * b] = pb;
+      a.part[2 * b + 1] = pr;
+    }
+  }
+}
+
+template <typename T, int EPI>
+static int rep_dispatch(const Csr<T> &A, const SegArgs<T> &a, Ctrl *ctrl,
+                        int respect_done, hipStream_t st) {
+  launch_rep_tin<T>(a.v, A.rep_in, A.bcols, A.rep, ctrl, -1, respect_done, st);
+  launch_rep_mm<T>(A, A.rep_in, A.rep_out, nullptr, ctrl, -1, respect_done, st);
+  const int64_t gx = (A.brows + WAVE - 1) / WAVE, gy = (A.rep + WAVE - 1) / WAVE;
+  if (gx <= 0 || gy <= 0) return 0;
+  hipLaunchKernelGGL((rep_epi_kernel<T, EPI>), dim3((unsigned)gx, (unsigned)gy),
+                     dim3(SEG_NT), 0, st, A, a, (const T *)A.rep_out, ctrl,
+                     respect_done);
+  return (int)(gx * gy);
+}
+
 template <typename T, int EPI>
 static int segdot_dispatch(const Csr<T> &A, const SegArgs<T> &a, Ctrl *ctrl,
                            int respect_done, hipStream_t st) {
+  if (!a.list && A.rep >= REP_MM_MIN && A.rep_in && EPI != EPI_LIST_STORE)
+    return rep_dispatch<T, EPI>(A, a, ctrl, respect_done, st);
   if (!a.list && A.rep == 1 && A.mp_rs &&
       (EPI == EPI_STORE || EPI == EPI_COLRES || EPI == EPI_ROWRES))
     return merge_dispatch<T, EPI>(A, a, ctrl, respect_done, st);

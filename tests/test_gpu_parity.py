@@ -595,22 +595,30 @@ def test_batch_rejects_coupled_rows(rg):
 
 
 # ------------------------------------------------------------ many RHS
-def test_multirhs_trajectory_per_rhs(rg):
-    p = workloads.sparse_powerlaw(3000, 1500, mean_len=10, max_len=100, seed=31)
+# R = 6 takes the per-right-hand-side products; 20 and 70 the interleaved
+# ones (one group of 64 lanes with idle lanes; a full group and a ragged
+# one).  One CG runs over the block-diagonal system of all right-hand
+# sides, so its spectrum is the union of theirs: the power-law matrix (some
+# row blocks singular) needs about 2000 steps per row projection at 20
+# right-hand sides, and the 70-RHS case takes a well-conditioned matrix.
+@pytest.mark.parametrize("R", [6, 20, 70])
+def test_multirhs_trajectory_per_rhs(rg, R):
+    if R < 70:
+        a = workloads.sparse_powerlaw(3000, 1500, mean_len=10, max_len=100,
+                                      seed=31).a
+    else:
+        a = workloads.sparse_uniform(1200, 400, density=0.03, seed=32).a
+    m, n = a.shape
     rng = np.random.default_rng(1)
-    R = 6
-    xs = rng.standard_normal((R, 1500))
-    bs = np.stack([p.a @ x for x in xs])
-    # one CG runs over the block-diagonal Gram of all right-hand sides; its
-    # spectrum is the union of theirs (some power-law row blocks are
-    # singular), so exact projections take more steps than one system's
-    s = rg.MultiRhsSolver(csr_tensors(p.a), p.a.shape, R, eta=0.1,
-                          stop="none", max_iter=3, inner_max=1500,
-                          graph_iters=1)
+    xs = rng.standard_normal((R, n))
+    bs = np.stack([a @ x for x in xs])
+    s = rg.MultiRhsSolver(csr_tensors(a), a.shape, R, eta=0.1,
+                          stop="none", max_iter=3,
+                          inner_max=1500 if R < 16 else 4096, graph_iters=1)
     x, info = s.solve(dev(bs.ravel()))
-    x = x.cpu().numpy().reshape(R, 1500)
+    x = x.cpu().numpy().reshape(R, n)
     for r in range(R):
-        xo, _, _ = rgdbek(p.a, bs[r], eta=0.1, max_iter=3, sys=r)
+        xo, _, _ = rgdbek(a, bs[r], eta=0.1, max_iter=3, sys=r)
         print(f"rhs {r} rel={rel(x[r], xo):.2e}", flush=True)
         assert rel(x[r], xo) <= TRAJ_TOL
     s.close()
@@ -623,9 +631,10 @@ def tikhonov_blur(npix, mu):
     return sp.vstack([a, np.sqrt(mu) * sp.identity(n)]).tocsr()
 
 
+@pytest.mark.parametrize("R", [8, 20])
 @pytest.mark.parametrize("precision", ["fp64", "mixed_f32"])
-def test_multirhs_blur_tikhonov_solution(rg, precision):
-    npix, R, mu = 32, 8, 1e-2
+def test_multirhs_blur_tikhonov_solution(rg, precision, R):
+    npix, mu = 32, 1e-2
     aa = tikhonov_blur(npix, mu)
     if precision == "mixed_f32":
         aa = rounded_f32(aa)      # FP32 storage: solve the rounded system
@@ -649,12 +658,13 @@ def test_multirhs_blur_tikhonov_solution(rg, precision):
     s.close()
 
 
-def test_multirhs_gradient_layer(rg):
+@pytest.mark.parametrize("R", [3, 17])
+def test_multirhs_gradient_layer(rg, R):
     # differentiable deblurring layer: x_s = A^+ b_s for every right-hand
     # side, loss L = sum_s <c_s, x_s>; dL/db and dL/dA (pattern, summed over
     # right-hand sides) against the pinv reference and central differences
     from oracle.refsol import grad_reference
-    npix, R, mu = 16, 3, 1e-2
+    npix, mu = 16, 1e-2
     aa = tikhonov_blur(npix, mu)
     m, n = aa.shape
     rng = np.random.default_rng(7)
@@ -690,6 +700,31 @@ def test_multirhs_gradient_layer(rg):
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - v.grad[e].item()) <= 1e-6 * max(1.0, abs(fd))
     s.close()
+
+
+@pytest.mark.parametrize("R", [5, 20, 70])
+def test_multirhs_apply(rg, R):
+    # (A x_s, A^T z_s) for every right-hand side in one residual pass, FP64
+    # and (on a mixed handle) FP32, against the products done one by one
+    p = workloads.sparse_powerlaw(2000, 900, mean_len=12, max_len=300, seed=33)
+    a = p.a
+    m, n = a.shape
+    rng = np.random.default_rng(2)
+    xs = rng.standard_normal((R, n))
+    zs = rng.standard_normal((R, m))
+    for prec, form, tol in (("f64", "fp64", 1e-13), ("f32", "mixed_f32", 1e-5)):
+        rp, ci, v = csr_tensors(a)
+        s = rg.MultiRhsSolver((rp, ci, v), (m, n), R, eta=0.1, precision=form)
+        dt = torch.float64 if prec == "f64" else torch.float32
+        ax, atz = s.apply(dev(xs.ravel()).to(dt), dev(zs.ravel()).to(dt),
+                          precision=prec)
+        torch.cuda.synchronize()
+        ax = ax.double().cpu().numpy().reshape(R, m)
+        atz = atz.double().cpu().numpy().reshape(R, n)
+        for r in range(R):
+            assert rel(ax[r], a @ xs[r]) <= tol, (prec, r)
+            assert rel(atz[r], a.T @ zs[r]) <= tol, (prec, r)
+        s.close()
 
 
 # ------------------------------------------------------------ GDBEK sets
