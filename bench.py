@@ -857,9 +857,39 @@ def c4_deblur(npix=512, nrhs=64, mu=1e-2, tol=1e-8, eta=0.1, itol=0.1,
                      "metric_max": float(max(met)),
                      "create_s": round(create, 3)}
         log(f"c4 {form}: {out[form]}")
-    del csr, b
+    # the differentiable layer x_s = [A; sI]^+ b_s (FP64 values: the same
+    # FP32-exact matrix), L = sum_s <c_s, x_s>: forward, then the backward's
+    # adjoint solve on A^T, second solve lam = A^+ w and pattern gradient
+    cs = np.random.default_rng(11).standard_normal((nrhs, n))
+    v64 = torch.as_tensor(workloads.to_csr_arrays(aug)[2]).cuda()
+    vg = v64.clone().requires_grad_(True)
+    bt = b.clone().requires_grad_(True)
+    s = rg.MultiRhsSolver((csr[0], csr[1], v64), (m, n), nrhs, eta=eta,
+                          stop="res_ext", tol=tol, max_iter=max_iter,
+                          inner_tol=itol, inner_max=imax, precision="fp64",
+                          stream=st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = rg.solve(s, vg, bt, least_squares=True)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    (x * torch.as_tensor(cs.ravel()).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    s.close()
+    out["differentiable_fp64"] = {
+        "forward_ms": round(1e3 * t_f, 1),
+        "forward_backward_ms": round(1e3 * t_fb, 1),
+        "backward_over_forward": round((t_fb - t_f) / t_f, 3),
+        "loss": "sum_s <c_s, x_s>, c ~ N(0, 1) (seed 11)"}
+    log(f"c4 differentiable: {out['differentiable_fp64']}")
+    grads = {"x": x.detach().cpu().numpy().reshape(nrhs, n).T,
+             "db": bt.grad.cpu().numpy().reshape(nrhs, m).T,
+             "dv": vg.grad.cpu().numpy(), "c": cs.T}
+    del csr, b, x, vg, bt, v64
     torch.cuda.empty_cache()
-    return out, {"t": t, "s": s_reg, "b_img": b_img, "sols": sols}
+    return out, {"t": t, "s": s_reg, "b_img": b_img, "sols": sols,
+                 "aug": aug, "grads": grads}
 
 
 def c5_batch(count=256, tol=1e-8, subset=32, tune_now=False):
@@ -1240,6 +1270,31 @@ def cpu_baseline_full(sel, ctx, budget_s=20.0):
                                 np.linalg.norm(x_mu, axis=0)))
                 for f, x in c["sols"].items()}
         out["c4_rel_err_vs_closed_form_max"] = errs
+        # the layer's gradients against the closed-form adjoint:
+        # lam = (A^T A + s^2 I)^{-1} c, w = [A; sI] lam = dL/db, and
+        # dL/dA = sum_s r_s lam_s^T - w_s x_s^T on 4096 sampled entries
+        from oracle.refsol import tikhonov_kron_lam
+        g, aug = c["grads"], c["aug"]
+        nn = aug.shape[1]
+        lam = tikhonov_kron_lam(c["t"], g["c"], c["s"])
+        w = np.asarray(aug @ lam)
+        bb = np.zeros((aug.shape[0], x_mu.shape[1]))
+        bb[:nn] = c["b_img"]
+        r = bb - np.asarray(aug @ x_mu)
+        ac = aug.tocsr()
+        ac.sort_indices()
+        rows = np.repeat(np.arange(ac.shape[0]), np.diff(ac.indptr))
+        pick = np.random.default_rng(5).choice(ac.nnz, 4096, replace=False)
+        i, j = rows[pick], ac.indices[pick]
+        da = np.einsum("ks,ks->k", r[i], lam[j]) - np.einsum("ks,ks->k", w[i], x_mu[j])
+        out["c4_differentiable_vs_closed_form"] = {
+            "x_rel_err_max": float(np.max(np.linalg.norm(g["x"] - x_mu, axis=0) /
+                                          np.linalg.norm(x_mu, axis=0))),
+            "db_rel_err": float(np.linalg.norm(g["db"] - w) / np.linalg.norm(w)),
+            "dA_sampled_rel_err": float(np.linalg.norm(g["dv"][pick] - da) /
+                                        np.linalg.norm(da)),
+            "dA_samples": 4096}
+        log(f"c4 gradient check: {out['c4_differentiable_vs_closed_form']}")
         # the oracle's own iterations (exact projections: LSQR on blocks of
         # 52,429 rows x 262,144 columns) run far beyond the sample budget at
         # this size, and already at 96 x 96 (over 2 minutes each, LSQR on

@@ -20,7 +20,10 @@ Deblurring with Tikhonov rows (Section 6's deblurring problem, solved as
 the least-squares system [A; s I] x ~= [b; 0]): for a separable blur
 A = T kron T with symmetric T = Q diag(lam) Q^T the normal equations
 (A^T A + s^2 I) x = A^T b diagonalise in the basis Q kron Q, so the
-solution is written out directly (``tikhonov_kron``).
+solution is written out directly (``tikhonov_kron``).  The same basis
+gives the adjoint quantities of the differentiable layer: for a loss with
+dL/dx = c, lam = (A^T A + s^2 I)^{-1} c (``tikhonov_kron_lam``), from which
+w = [A; s I] lam = dL/db and dL/dA = r lam^T - w x^T follow as above.
 
 Test infrastructure only (see the package docstring).
 """
@@ -100,4 +103,25 @@ def tikhonov_kron(t, b_img, s):
         bimg = np.ascontiguousarray(bm[:, c]).reshape(p, p)
         y = q.T @ bimg @ q
         out[:, c] = (q @ (f * y) @ q.T).ravel()
+    return out[:, 0] if single else out
+
+
+def tikhonov_kron_lam(t, c_img, s):
+    """lam = ((T kron T)^T (T kron T) + s^2 I)^{-1} c for symmetric T and
+    one or more vectors c (columns of c_img, row-major image order): in the
+    basis Q kron Q the matrix is diagonal with entries (lam_i lam_j)^2 + s^2,
+    so lam = Q (G o (Q^T C Q)) Q^T with G_ij = 1 / ((lam_i lam_j)^2 + s^2)."""
+    t = np.asarray(t, dtype=np.float64)
+    ev, q = np.linalg.eigh(t)
+    p = t.shape[0]
+    ll = np.outer(ev, ev)
+    g = 1.0 / (ll * ll + s * s)
+    c_img = np.asarray(c_img, dtype=np.float64)
+    single = c_img.ndim == 1
+    cm = c_img.reshape(p * p, -1)
+    out = np.empty_like(cm)
+    for k in range(cm.shape[1]):
+        cimg = np.ascontiguousarray(cm[:, k]).reshape(p, p)
+        y = q.T @ cimg @ q
+        out[:, k] = (q @ (g * y) @ q.T).ravel()
     return out[:, 0] if single else out

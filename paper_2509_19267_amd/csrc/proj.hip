@@ -1518,17 +1518,19 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
   const unsigned nbg = seg_blocks<T>(csr.rows, csr.group);
   const bool wide_grid = nbg >= SC_WIDE_GRID_MIN * SC_WIDE_MAXB &&
                          (int64_t)nbg <= w.part_cap;
-  unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csc.group), SC_MAXB);
+  // many right-hand sides: both products over interleaved vectors, and the
+  // listed product reads its value from them (one lane per listed column)
+  const bool mm = csr.rep >= REP_MM_MIN && w.t0 != nullptr;
+  const int gn = mm ? 1 : csc.group;
+  unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, gn), SC_MAXB);
   if (nbn < 64) nbn = 64;
   const int par = (w.split || cap > SC_SERIAL_MAX) ? 1 : 0;
   // large blocks: the listed product over a full grid, reduced by a
   // separate launch (no grid-stride walk, no last-workgroup ticket)
-  const unsigned nbnf = seg_blocks<T>(cap, csc.group);
+  const unsigned nbnf = seg_blocks<T>(cap, gn);
   const bool narrow_grid = par && nbnf > SC_MAXB && (int64_t)nbnf <= w.part_cap;
   const unsigned nbu = std::min<unsigned>(
       (unsigned)((cap + SC_NT - 1) / SC_NT), SC_MAXB);
-  // many right-hand sides: both products over interleaved vectors
-  const bool mm = csr.rep >= REP_MM_MIN && w.t0 != nullptr;
   for (int s = 0; s < max_steps; ++s) {
     if (mm) {
       // q = A phat for every right-hand side, ||q||^2 -> alpha; then A^T q
@@ -1568,7 +1570,7 @@ void launch_sparse_colproj(const Csr<T> &csr, const Csr<T> &csc,
       hipLaunchKernelGGL(sc_long_narrow<T>, dim3((unsigned)nln), dim3(SC_NT),
                          0, st, csc, w.pos, w.wide, w.res, w.p, w.plong, ctrl,
                          0, respect_done);
-    RG_SWITCH_G(csc.group,
+    RG_SWITCH_G(gn,
                 hipLaunchKernelGGL((sc_narrow_col<T, GG>),
                                    dim3(narrow_grid ? nbnf : nbn),
                                    dim3(SC_NT), 0, st, csc, U, count_dev,
@@ -1605,13 +1607,14 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
                      respect_done);
   // w.v doubles as the Jacobi-scaled residual buffer zz during steps
   const unsigned nbw = seg_blocks<T>(csc.rows, csc.group);
-  const unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, csr.group), SC_MAXB);
+  const bool mm = csr.rep >= REP_MM_MIN && w.t0 != nullptr;
+  const int gn = mm ? 1 : csr.group;
+  const unsigned nbn = std::min<unsigned>(seg_blocks<T>(cap, gn), SC_MAXB);
   const int par = (w.split || cap > SC_SERIAL_MAX) ? 1 : 0;
-  const unsigned nbnf = seg_blocks<T>(cap, csr.group);
+  const unsigned nbnf = seg_blocks<T>(cap, gn);
   const bool narrow_grid = par && nbnf > SC_MAXB && (int64_t)nbnf <= w.part_cap;
   const unsigned nbu = std::min<unsigned>(
       (unsigned)((cap + SC_NT - 1) / SC_NT), SC_MAXB);
-  const bool mm = csr.rep >= REP_MM_MIN && w.t0 != nullptr;
   for (int s = 0; s < max_steps; ++s) {
     if (mm) {
       // u = A^T phat for every right-hand side (the pending x += alpha u
@@ -1638,7 +1641,7 @@ void launch_sparse_rowproj(const Csr<T> &csr, const Csr<T> &csc,
       hipLaunchKernelGGL(sc_long_narrow<T>, dim3((unsigned)nln), dim3(SC_NT),
                          0, st, csr, w.pos, w.wide, w.v + cap, w.p, w.plong,
                          ctrl, 1, respect_done);
-    RG_SWITCH_G(csr.group,
+    RG_SWITCH_G(gn,
                 hipLaunchKernelGGL((sc_narrow_row<T, GG>),
                                    dim3(narrow_grid ? nbnf : nbn),
                                    dim3(SC_NT), 0, st, csr, J, count_dev,

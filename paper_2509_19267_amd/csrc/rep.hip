@@ -17,6 +17,10 @@ namespace rg {
 
 constexpr int REP_NT = 256;            // 4 waves: 4 stored rows per workgroup
 constexpr int REP_ROWS = REP_NT / WAVE;
+// gathers in flight per lane (measured on the 512^2 blur, 64 right-hand
+// sides: 8 gain 16% over 4 in FP32, nothing in FP64)
+template <typename T> struct REP_UNR { static constexpr int n = 4; };
+template <> struct REP_UNR<float> { static constexpr int n = 8; };
 
 __device__ __forceinline__ int bcast(int v, int j) {
   return __builtin_amdgcn_readlane(v, j);
@@ -62,16 +66,14 @@ rep_mm_kernel(Csr<T> A, const T *__restrict__ in, T *__restrict__ out,
       }
       const int nc = (int)(e1 - c0 < WAVE ? e1 - c0 : WAVE);
       int j = 0;
-      // four gathers in flight, added in entry order
-      for (; j + 4 <= nc; j += 4) {
-        const int i0 = bcast(ix, j), i1 = bcast(ix, j + 1);
-        const int i2 = bcast(ix, j + 2), i3 = bcast(ix, j + 3);
-        const T g0 = col[(int64_t)i0 * R], g1 = col[(int64_t)i1 * R];
-        const T g2 = col[(int64_t)i2 * R], g3 = col[(int64_t)i3 * R];
-        acc += bcast(v, j) * g0;
-        acc += bcast(v, j + 1) * g1;
-        acc += bcast(v, j + 2) * g2;
-        acc += bcast(v, j + 3) * g3;
+      // UNR gathers in flight, added in entry order
+      for (; j + REP_UNR<T>::n <= nc; j += REP_UNR<T>::n) {
+        T g[REP_UNR<T>::n];
+#pragma unroll
+        for (int u = 0; u < REP_UNR<T>::n; ++u)
+          g[u] = col[(int64_t)bcast(ix, j + u) * R];
+#pragma unroll
+        for (int u = 0; u < REP_UNR<T>::n; ++u) acc += bcast(v, j + u) * g[u];
       }
       for (; j < nc; ++j) acc += bcast(v, j) * col[(int64_t)bcast(ix, j) * R];
     }

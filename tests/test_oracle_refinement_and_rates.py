@@ -166,3 +166,30 @@ def test_tikhonov_kron_closed_form_against_lstsq():
     # without the regulariser the answer moves well beyond the tolerance
     assert (np.linalg.norm(tikhonov_kron(t, b[:, 0], 0.0) - want[:, 0])
             > 1e-3 * np.linalg.norm(want[:, 0]))
+
+
+def test_tikhonov_kron_lam_against_pinv_gradient():
+    """The closed-form adjoint of the deblurring layer: lam and, from it,
+    w = dL/db and dL/dA = r lam^T - w x^T against the dense pinv reference
+    of the implicit gradient (8 x 8 image, loss gradient dL/dx = c)."""
+    import workloads
+    from oracle.refsol import grad_reference, tikhonov_kron, tikhonov_kron_lam
+    aug, t, s = workloads.blur_tikhonov(npix=8, mu=1e-2)
+    n = 64
+    ad = aug.toarray()
+    rng = np.random.default_rng(4)
+    b = np.concatenate([rng.standard_normal(n), np.zeros(n)])
+    c = rng.standard_normal(n)
+    lam = tikhonov_kron_lam(t, c, s)
+    x = tikhonov_kron(t, b[:n], s)
+    w = ad @ lam
+    r = b - ad @ x
+    da = np.outer(r, lam) - np.outer(w, x)
+    da_want, w_want = grad_reference(ad, b, c)
+    assert np.linalg.norm(w - w_want) <= 1e-11 * np.linalg.norm(w_want)
+    assert np.linalg.norm(da - da_want) <= 1e-11 * np.linalg.norm(da_want)
+    # the normal equations of lam (a missing s^2 or a transposed factor
+    # fails them)
+    a = ad[:n]
+    ne = a.T @ (a @ lam) + s * s * lam - c
+    assert np.linalg.norm(ne) <= 1e-12 * np.linalg.norm(c)
