@@ -157,8 +157,17 @@ __device__ __forceinline__ bool last_block(unsigned *ticket) {
   return is_last != 0;
 }
 
+// Flags tested once at a kernel's start (Ctrl::done, the CG's done flag of
+// a phase), written only by earlier launches of the stream: kernel
+// boundaries order and publish those writes, so a plain load suffices.  It
+// is uniform and takes the scalar cache, and the many workgroups of a
+// launch with nothing left to do (a captured CG step after the CG has met
+// its tolerance) leave without each waiting on an L2 round trip.
 __device__ __forceinline__ bool ctrl_done(const Ctrl *c) {
-  return ld_agent(&c->done) != 0;
+  return c->done != 0;
+}
+__device__ __forceinline__ bool cg_done_at_start(const Ctrl *c, int ph) {
+  return c->cg_done[ph] != 0;
 }
 
 // Grid barrier of a persistent launch (every workgroup resident): arrivals

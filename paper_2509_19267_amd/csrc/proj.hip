@@ -867,7 +867,7 @@ sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
             double *__restrict__ part, const double *__restrict__ plong,
             int64_t nlong, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[0])) return;
+  if (cg_done_at_start(ctrl, 0)) return;
   __shared__ double sh[SC_NT / WAVE];
   constexpr int SPB = SC_NT / G;
   const int lg = threadIdx.x & (G - 1);
@@ -921,7 +921,7 @@ sc_wide_col_grid(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
                  double *__restrict__ part, int64_t nlong, Ctrl *ctrl,
                  int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[0])) return;
+  if (cg_done_at_start(ctrl, 0)) return;
   __shared__ double sh[SC_NT / WAVE];
   constexpr int SPB = SC_NT / G;
   const int lg = threadIdx.x & (G - 1);
@@ -953,7 +953,7 @@ sc_wide_col_fin(const double *__restrict__ part, int64_t nb,
                 const double *__restrict__ plong, int64_t nlong, Ctrl *ctrl,
                 int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[0])) return;
+  if (cg_done_at_start(ctrl, 0)) return;
   __shared__ double sh[1024 / WAVE];
   double tot = 0.0, tl = 0.0;
   for (int64_t b = threadIdx.x; b < nb; b += 1024) tot += part[b];
@@ -979,7 +979,7 @@ sc_narrow_col(Csr<T> At, const int32_t *__restrict__ U,
               int64_t nlong, double tol, int par, int gridm,
               const T *__restrict__ pre, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[0])) return;
+  if (cg_done_at_start(ctrl, 0)) return;
   __shared__ double sh[SC_NT / WAVE];
   const double alpha = ctrl->cg_alpha[0];
   const int64_t c = *cnt;
@@ -1134,7 +1134,7 @@ sc_narrow_col_fin(const double *__restrict__ part, int64_t nb,
                   const double *__restrict__ plong, int64_t nlong, double tol,
                   Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[0])) return;
+  if (cg_done_at_start(ctrl, 0)) return;
   __shared__ double sh[1024 / WAVE];
   double tot = 0.0, tl = 0.0;
   for (int64_t b = threadIdx.x; b < nb; b += 1024) tot += part[b];
@@ -1154,7 +1154,7 @@ sc_narrow_row_fin(const double *__restrict__ part, int64_t nb,
                   const double *__restrict__ plong, int64_t nlong, Ctrl *ctrl,
                   int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[1])) return;
+  if (cg_done_at_start(ctrl, 1)) return;
   __shared__ double sh[1024 / WAVE];
   double tot = 0.0, tl = 0.0;
   for (int64_t b = threadIdx.x; b < nb; b += 1024) tot += part[b];
@@ -1269,7 +1269,7 @@ sc_long_wide(Csr<T> A, const T *__restrict__ phat, T *__restrict__ out,
              T *__restrict__ x, double *__restrict__ plong, Ctrl *ctrl,
              int ph, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[ph])) return;
+  if (cg_done_at_start(ctrl, ph)) return;
   __shared__ double sh[SC_NT / WAVE];
   const int64_t r = A.longs[blockIdx.x];
   const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
@@ -1294,7 +1294,7 @@ sc_long_narrow(Csr<T> A, const int32_t *__restrict__ pos,
                const T *__restrict__ p, double *__restrict__ plong,
                Ctrl *ctrl, int ph, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[ph])) return;
+  if (cg_done_at_start(ctrl, ph)) return;
   __shared__ double sh[SC_NT / WAVE];
   const int64_t r = A.longs[blockIdx.x];
   const int32_t a = pos[r];
@@ -1326,7 +1326,7 @@ __global__ void __launch_bounds__(SC_NT)
 sc_wide_row(Csr<T> At, const T *__restrict__ phat, T *__restrict__ u,
             T *__restrict__ x, int64_t nlong, Ctrl *ctrl, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[1])) return;
+  if (cg_done_at_start(ctrl, 1)) return;
   const double alpha = ctrl->cg_alpha[1];
   constexpr int SPB = SC_NT / G;
   const int lg = threadIdx.x & (G - 1);
@@ -1361,7 +1361,7 @@ sc_narrow_row(Csr<T> A, const int32_t *__restrict__ J,
               int par, int gridm, const T *__restrict__ pre, Ctrl *ctrl,
               int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ld_agent(&ctrl->cg_done[1])) return;
+  if (cg_done_at_start(ctrl, 1)) return;
   __shared__ double sh[SC_NT / WAVE];
   const int64_t c = *cnt;
   constexpr int SPB = SC_NT / G;

@@ -45,7 +45,7 @@ rep_mm_kernel(Csr<T> A, const T *__restrict__ in, T *__restrict__ out,
               double *__restrict__ part, Ctrl *ctrl, int ph,
               int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ph >= 0 && ld_agent(&ctrl->cg_done[ph])) return;
+  if (ph >= 0 && cg_done_at_start(ctrl, ph)) return;
   __shared__ double sh[REP_NT / WAVE];
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t R = A.rep;
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(REP_NT)
 rep_tin_kernel(const T *__restrict__ in, T *__restrict__ out, int64_t len,
                int64_t R, Ctrl *ctrl, int ph, int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ph >= 0 && ld_agent(&ctrl->cg_done[ph])) return;
+  if (ph >= 0 && cg_done_at_start(ctrl, ph)) return;
   __shared__ T tile[WAVE][WAVE + 1];
   const int64_t i0 = (int64_t)blockIdx.x * WAVE, s0 = (int64_t)blockIdx.y * WAVE;
   const int tx = threadIdx.x & (WAVE - 1), ty = threadIdx.x / WAVE;
@@ -125,7 +125,7 @@ rep_tout_kernel(const T *__restrict__ in, T *__restrict__ out,
                 T *__restrict__ x, int64_t len, int64_t R, Ctrl *ctrl, int ph,
                 int respect_done) {
   if (respect_done && ctrl_done(ctrl)) return;
-  if (ph >= 0 && ld_agent(&ctrl->cg_done[ph])) return;
+  if (ph >= 0 && cg_done_at_start(ctrl, ph)) return;
   __shared__ T tile[WAVE][WAVE + 1];
   const double alpha = (x && ph >= 0) ? ctrl->cg_alpha[ph] : 0.0;
   const int64_t i0 = (int64_t)blockIdx.x * WAVE, s0 = (int64_t)blockIdx.y * WAVE;
