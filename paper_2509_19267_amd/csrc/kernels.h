@@ -142,7 +142,14 @@ struct Csr {                 // CSR (or CSC viewed as CSR of the transpose)
   // Interleaved scratch of the many-right-hand-side products (rep >=
   // REP_MM_MIN): max(brows, bcols) * rep entries each, input and output.
   T *rep_in = nullptr, *rep_out = nullptr;
+  // Row ends when rows are not contiguous (the block copies of one stored
+  // matrix keep A's row starts): row r spans [ptr[r], pend[r]).
+  const int64_t *pend = nullptr;
 };
+template <typename T>
+__device__ __forceinline__ int64_t seg_end(const Csr<T> &A, int64_t r) {
+  return A.pend ? A.pend[r] : A.ptr[r + 1];
+}
 
 // slot of a full sweep -> global row, stored row, column offset
 template <typename T>

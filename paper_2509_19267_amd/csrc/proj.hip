@@ -883,7 +883,7 @@ sc_wide_col(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
     if (mine) {
       vrow(A, slot, s, br, co);
       const T *ph = phat + co;
-      const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
+      const int64_t e0 = A.ptr[br], e1 = seg_end(A, br);
       if (nlong && (A.long_flag ? A.long_flag[br] != 0 : e1 - e0 > A.long_limit))
         mine = false;   // sc_long_wide
       else
@@ -933,7 +933,7 @@ sc_wide_col_grid(Csr<T> A, const T *__restrict__ phat, T *__restrict__ q,
   if (mine) {
     vrow(A, slot, s, br, co);
     const T *ph = phat + co;
-    const int64_t e0 = A.ptr[br], e1 = A.ptr[br + 1];
+    const int64_t e0 = A.ptr[br], e1 = seg_end(A, br);
     if (nlong && (A.long_flag ? A.long_flag[br] != 0 : e1 - e0 > A.long_limit))
       mine = false;   // sc_long_wide
     else
@@ -1272,7 +1272,7 @@ sc_long_wide(Csr<T> A, const T *__restrict__ phat, T *__restrict__ out,
   if (cg_done_at_start(ctrl, ph)) return;
   __shared__ double sh[SC_NT / WAVE];
   const int64_t r = A.longs[blockIdx.x];
-  const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
+  const int64_t e0 = A.ptr[r], e1 = seg_end(A, r);
   T acc = 0;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += SC_NT)
     acc += A.val[e] * phat[A.idx[e]];
@@ -1337,7 +1337,7 @@ sc_wide_row(Csr<T> At, const T *__restrict__ phat, T *__restrict__ u,
   if (mine) {
     vrow(At, slot, s, br, co);
     const T *ph = phat + co;
-    const int64_t e0 = At.ptr[br], e1 = At.ptr[br + 1];
+    const int64_t e0 = At.ptr[br], e1 = seg_end(At, br);
     if (nlong && (At.long_flag ? At.long_flag[br] != 0 : e1 - e0 > At.long_limit))
       mine = false;   // sc_long_wide
     else
@@ -1817,14 +1817,21 @@ template void launch_sparse_block_update<float>(
 // in the CG products) stay long in the copy.  The sums drop only zero terms
 // and stay deterministic; their grouping across lanes differs from the full
 // pass's, so the two agree to rounding.
+// One stored matrix: the copy keeps A's row starts ("gapped"), so one pass
+// suffices:
 //   mark:   mask[list_a] = 1
-//   count:  cnt_r = #{e in row r : mask[idx_e]}            (G lanes per row)
-// For the replicated operator I_rep (x) A of many right-hand sides the copy
-// is a plain matrix over the virtual rows and columns: each right-hand side
-// keeps the entries of its own block.
-//   scan:   ptr = exclusive prefix sum of cnt             (three launches)
-//   fill:   each row's marked entries, in order, to ptr_r (ballot ranks)
+//   fill:   each row's marked entries, in order, from A.ptr_r (ballot
+//           ranks); end_r = A.ptr_r + their count
 //   unmark: mask[list_a] = 0
+// For the replicated operator I_rep (x) A of a few right-hand sides the copy
+// is a compact matrix over the virtual rows and columns (each right-hand
+// side keeps the entries of its own block; the capacity is the k longest
+// columns' entries per right-hand side, not A's):
+//   mark
+//   count:  cnt_r = #{e in row r : mask[idx_e]}            (G lanes per row)
+//   scan:   ptr = exclusive prefix sum of cnt             (three launches)
+//   fill:   each row's marked entries, in order, to ptr_r
+//   unmark
 constexpr int SB_NT = 256;
 constexpr int SB_TILE = 2048;          // scan elements per workgroup
 
@@ -1928,12 +1935,14 @@ sub_scan_c(const int64_t *__restrict__ v, int64_t n,
   }
 }
 
+// ptr == nullptr: the gapped copy of one stored matrix -- row r's entries
+// start at A.ptr[r] and end[r] receives their end (no count or scan)
 template <typename T, int G>
 __global__ void __launch_bounds__(SB_NT)
 sub_fill(Csr<T> A, const int32_t *__restrict__ mask,
          const int64_t *__restrict__ ptr, int32_t *__restrict__ idx,
          T *__restrict__ val, const uint8_t *__restrict__ long_flag,
-         Ctrl *ctrl) {
+         int64_t *__restrict__ end, Ctrl *ctrl) {
   if (ctrl_done(ctrl)) return;
   constexpr int SPB = SB_NT / G;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -1944,7 +1953,7 @@ sub_fill(Csr<T> A, const int32_t *__restrict__ mask,
   int64_t br = 0, co = 0;   // stored row and column offset (replicated A)
   if (live) gsplit(A, r, br, co);
   const int64_t e0 = live ? A.ptr[br] : 0, e1 = live ? A.ptr[br + 1] : 0;
-  int64_t pos = live ? ptr[r] : 0;
+  int64_t pos = live ? (ptr ? ptr[r] : e0) : 0;
   // every lane of a wave runs the same trip count (ballots need the whole
   // wave): the longest segment of the wave's groups
   int64_t len = e1 - e0;
@@ -1969,6 +1978,7 @@ sub_fill(Csr<T> A, const int32_t *__restrict__ mask,
     }
     pos += __popcll(mine);
   }
+  if (!ptr && live && lg == 0) end[r] = pos;
 }
 
 // long rows (A.longs): one workgroup each, in storage order
@@ -1990,14 +2000,14 @@ template <typename T>
 __global__ void __launch_bounds__(SB_NT)
 sub_fill_long(Csr<T> A, const int32_t *__restrict__ mask,
               const int64_t *__restrict__ ptr, int32_t *__restrict__ idx,
-              T *__restrict__ val, Ctrl *ctrl) {
+              T *__restrict__ val, int64_t *__restrict__ end, Ctrl *ctrl) {
   if (ctrl_done(ctrl)) return;
   __shared__ int64_t wsum[SB_NT / WAVE];
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = threadIdx.x / WAVE;
   const int64_t r = A.longs[blockIdx.x];
   const int64_t e0 = A.ptr[r], e1 = A.ptr[r + 1];
-  int64_t pos = ptr[r];
+  int64_t pos = ptr ? ptr[r] : e0;
   for (int64_t c = e0; c < e1; c += SB_NT) {
     const int64_t e = c + threadIdx.x;
     const bool in = e < e1;
@@ -2019,6 +2029,7 @@ sub_fill_long(Csr<T> A, const int32_t *__restrict__ mask,
     pos += tot;
     __syncthreads();
   }
+  if (!ptr && threadIdx.x == 0) end[r] = pos;
 }
 
 int64_t sub_scan_tiles(int64_t n) { return (n + SB_TILE - 1) / SB_TILE; }
@@ -2050,6 +2061,29 @@ Csr<T> launch_sub_matrix(const Csr<T> &A, const int32_t *list,
   const int G = A.group;
   const unsigned nb = (unsigned)((rows + 1 + SB_NT / G - 1) / (SB_NT / G));
   const uint8_t *lf = (A.nlong && A.rep == 1) ? w.long_flag : nullptr;
+  if (A.rep == 1) {
+    // one stored matrix: the gapped copy, each row's block entries at the
+    // start of its own span of A (row ends in w.cnt), in one pass
+    RG_SWITCH_G(G, hipLaunchKernelGGL((sub_fill<T, GG>), dim3(nb), dim3(SB_NT),
+                                      0, st, A, w.mask, (const int64_t *)nullptr,
+                                      w.idx, (T *)w.val, lf, w.cnt, ctrl));
+    if (lf)
+      hipLaunchKernelGGL(sub_fill_long<T>, dim3((unsigned)A.nlong), dim3(SB_NT),
+                         0, st, A, w.mask, (const int64_t *)nullptr, w.idx,
+                         (T *)w.val, w.cnt, ctrl);
+    hipLaunchKernelGGL(sub_mark, dim3(gm), dim3(SB_NT), 0, st, list, count_dev,
+                       w.mask, 0, ctrl);
+    Csr<T> B = A;
+    B.idx = w.idx;
+    B.val = (const T *)w.val;
+    B.pend = w.cnt;
+    B.group = w.group;
+    // A's long rows stay long segments (one workgroup each) in the copy
+    B.long_flag = w.long_flag;
+    B.mp_rs = nullptr;     // no merge plan: row-split passes only
+    B.mp_nchunk = 0;
+    return B;
+  }
   RG_SWITCH_G(G, hipLaunchKernelGGL((sub_count<T, GG>), dim3(nb), dim3(SB_NT),
                                     0, st, A, w.mask, w.cnt, lf, ctrl));
   if (lf)
@@ -2062,11 +2096,13 @@ Csr<T> launch_sub_matrix(const Csr<T> &A, const int32_t *list,
   hipLaunchKernelGGL(sub_scan_c, dim3((unsigned)nt), dim3(SB_NT), 0, st, w.cnt,
                      rows + 1, w.tile, w.ptr, ctrl);
   RG_SWITCH_G(G, hipLaunchKernelGGL((sub_fill<T, GG>), dim3(nb), dim3(SB_NT),
-                                    0, st, A, w.mask, w.ptr, w.idx, (T *)w.val,
-                                    lf, ctrl));
+                                    0, st, A, w.mask, (const int64_t *)w.ptr,
+                                    w.idx, (T *)w.val, lf, (int64_t *)nullptr,
+                                    ctrl));
   if (lf)
     hipLaunchKernelGGL(sub_fill_long<T>, dim3((unsigned)A.nlong), dim3(SB_NT),
-                       0, st, A, w.mask, w.ptr, w.idx, (T *)w.val, ctrl);
+                       0, st, A, w.mask, (const int64_t *)w.ptr, w.idx,
+                       (T *)w.val, (int64_t *)nullptr, ctrl);
   hipLaunchKernelGGL(sub_mark, dim3(gm), dim3(SB_NT), 0, st, list, count_dev,
                      w.mask, 0, ctrl);
   Csr<T> B = A;
@@ -2075,20 +2111,15 @@ Csr<T> launch_sub_matrix(const Csr<T> &A, const int32_t *list,
   B.val = (const T *)w.val;
   B.nnz = w.cap;
   B.group = w.group;
-  if (A.rep == 1) {
-    // A's long rows stay long segments (one workgroup each) in the copy
-    B.long_flag = w.long_flag;
-  } else {
-    // the replicated operator I_rep (x) A: the copy is a plain matrix over
-    // the virtual rows and columns (column indices already offset)
-    B.rep = 1;
-    B.brows = A.rows;
-    B.bcols = A.cols;
-    B.longs = nullptr;
-    B.nlong = 0;
-    B.long_limit = 0;
-    B.long_flag = nullptr;
-  }
+  // the replicated operator I_rep (x) A: the copy is a plain matrix over
+  // the virtual rows and columns (column indices already offset)
+  B.rep = 1;
+  B.brows = A.rows;
+  B.bcols = A.cols;
+  B.longs = nullptr;
+  B.nlong = 0;
+  B.long_limit = 0;
+  B.long_flag = nullptr;
   B.mp_rs = nullptr;     // no merge plan: row-split passes only
   B.mp_nchunk = 0;
   return B;

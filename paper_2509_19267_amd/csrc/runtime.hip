@@ -437,6 +437,7 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
     if (!(h->p.flags & RGDBEK_FLAG_SPARSE_FULL) &&
         (h->rep == 1 ||
          (h->rep < REP_MM_MIN && sub_bytes <= 48.0 * (1ull << 30)))) {
+      double share = 1.0;
       auto sub = [&](SubWork &w, const Csr<T> &M, int64_t cap, int64_t dcol) {
         w.cap = cap;
         w.ptr = P.alloc<int64_t>(M.rows + 2);
@@ -449,12 +450,13 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
           w.long_flag = P.alloc<uint8_t>(M.rows + 64);
           launch_mark_long<T>(M, w.long_flag, h->st);
         }
-        // the copy's rows are shorter, but keep A's lanes per row: the
-        // lanes of a row load their entries' gathers in parallel, and a
-        // row of moderate length would otherwise walk them one by one
-        w.group = M.group;
+        // lanes per row of the copy from its expected row length (the
+        // block's share of each row's entries)
+        w.group = pick_group(M.rows ? (double)h->nnz / (double)M.rows * share : 1.0);
       };
+      share = e.n ? (double)e.kc / (double)e.n : 1.0;
       sub(e.subc, a, capc, e.n);
+      share = e.m ? (double)e.kr / (double)e.m : 1.0;
       sub(e.subr, at, capr, e.m);
     }
     // Small single systems: the Gram matrices of all columns and all rows,
