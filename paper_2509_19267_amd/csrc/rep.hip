@@ -39,7 +39,9 @@ __device__ __forceinline__ double bcast(double v, int j) {
 // the group of 64).  Lanes past rep gather from right-hand side 0 (in
 // bounds) and store nothing.  Every lane of the wave runs the entry loop
 // (row and bounds are wave-uniform), as v_readlane needs.
-template <typename T>
+// RC: the right-hand-side count when fixed at compile time (64, one full
+// group: the gather stride is a shift), 0 when taken from A.rep.
+template <typename T, int RC>
 __global__ void __launch_bounds__(REP_NT)
 rep_mm_kernel(Csr<T> A, const T *__restrict__ in, T *__restrict__ out,
               double *__restrict__ part, Ctrl *ctrl, int ph,
@@ -48,7 +50,7 @@ rep_mm_kernel(Csr<T> A, const T *__restrict__ in, T *__restrict__ out,
   if (ph >= 0 && cg_done_at_start(ctrl, ph)) return;
   __shared__ double sh[REP_NT / WAVE];
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t R = A.rep;
+  const int64_t R = RC > 0 ? (int64_t)RC : A.rep;
   const int64_t s = (int64_t)blockIdx.y * WAVE + lane;
   const bool live = s < R;
   const int64_t row = (int64_t)blockIdx.x * REP_ROWS + threadIdx.x / WAVE;
@@ -92,9 +94,14 @@ int launch_rep_mm(const Csr<T> &A, const T *in, T *out, double *part,
   const int64_t gx = (A.brows + REP_ROWS - 1) / REP_ROWS;
   const int64_t gy = (A.rep + WAVE - 1) / WAVE;
   if (gx <= 0 || gy <= 0) return 0;
-  hipLaunchKernelGGL(rep_mm_kernel<T>, dim3((unsigned)gx, (unsigned)gy),
-                     dim3(REP_NT), 0, st, A, in, out, part, ctrl, ph,
-                     respect_done);
+  if (A.rep == WAVE)
+    hipLaunchKernelGGL((rep_mm_kernel<T, WAVE>), dim3((unsigned)gx, (unsigned)gy),
+                       dim3(REP_NT), 0, st, A, in, out, part, ctrl, ph,
+                       respect_done);
+  else
+    hipLaunchKernelGGL((rep_mm_kernel<T, 0>), dim3((unsigned)gx, (unsigned)gy),
+                       dim3(REP_NT), 0, st, A, in, out, part, ctrl, ph,
+                       respect_done);
   return (int)(gx * gy);
 }
 

@@ -195,8 +195,8 @@ def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
 
 
 def tune_sparse(make, b, x_ref, *, key, tol=1e-8, log=print, reps=1,
-                etas=(0.05, 0.1, 0.2), inner=((0.3, 4), (0.1, 8), (0.1, 16),
-                                              (0.03, 16)),
+                etas=(0.05, 0.1, 0.2),
+                inner=((0.5, 2), (0.3, 4), (0.1, 8), (0.1, 16), (0.03, 16)),
                 graph_iters=(4, 8, 16), pass_drops=()):
     """Tune a sparse solve (single system, batch or many right-hand sides):
     `make(eta=, inner_tol=, inner_max=, graph_iters=[, pass_drop=])` builds a
