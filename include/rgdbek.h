@@ -225,10 +225,14 @@ rgdbek_status rgdbek_create_batched(const rgdbek_matrix *A, int64_t nsys,
  * s < nrhs.  A is stored once; the batch behaves as the block-diagonal
  * system I_nrhs (x) A with one system per right-hand side (own draws,
  * generator stream, iteration counter and stop test, as for
- * rgdbek_create_batched), and every pass over A serves all right-hand sides
- * (consecutive reads of a stored row belong to different right-hand sides,
- * so A is fetched from HBM about once per pass).  Vectors are right-hand-side
- * major: b[s*m + i], x[s*n + j].  rgdbek_grad_pattern then sums the pattern
+ * rgdbek_create_batched), and every pass over A serves all right-hand sides.
+ * From 16 right-hand sides on, the passes and the CG products run over
+ * interleaved copies of the vectors (entry j of right-hand side s at
+ * j*nrhs + s), each stored entry read once for all right-hand sides; the
+ * handle then holds three such buffers per precision, 3 * max(m, n) * nrhs
+ * values.  Below 16, consecutive reads of a stored row belong to different
+ * right-hand sides.  Vectors at the boundary are right-hand-side major:
+ * b[s*m + i], x[s*n + j].  rgdbek_grad_pattern then sums the pattern
  * gradient over the right-hand sides. */
 rgdbek_status rgdbek_create_multirhs(const rgdbek_matrix *A, int64_t nrhs,
                                      const rgdbek_params *p, void *stream,
