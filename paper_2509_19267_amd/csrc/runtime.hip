@@ -45,7 +45,7 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 int pick_group(double mean_len) {
   int g = 1;
-  while (g < 64 && g < mean_len * 0.75) g <<= 1;
+  while (g < 64 && g < mean_len * 0.5) g <<= 1;
   return g;
 }
 
