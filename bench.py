@@ -772,7 +772,7 @@ def full_configs(args):
     if "c3" in sel:
         res["c3"] = c3_powerlaw(tune_now="c3" in tn)
     if "c4" in sel:
-        res["c4"], ctx["c4"] = c4_deblur()
+        res["c4"], ctx["c4"] = c4_deblur(tune_now="c4" in tn)
     if "c5" in sel:
         res["c5"] = c5_batch(tune_now="c5" in tn)
     cpu = None if args.no_cpu_baseline else cpu_baseline_full(sel, ctx)
@@ -865,7 +865,8 @@ def c3_powerlaw(tol=1e-8, tune_now=False, tune_tol=1e-4):
 
 
 def c4_deblur(npix=512, nrhs=64, mu=1e-2, tol=1e-8, eta=0.1, itol=0.1,
-              imax=16, max_iter=5000):
+              imax=16, max_iter=5000, tune_now=False, tune_rhs=16,
+              tune_tol=1e-4):
     """Deblurring as a differentiable layer: the 512 x 512 Gaussian blur
     (sigma 2, 15 x 15 stencil, zero boundary) with Tikhonov rows [A; s I]
     (s^2 = mu), 64 right-hand sides from smooth random fields plus 1% noise,
@@ -875,7 +876,10 @@ def c4_deblur(npix=512, nrhs=64, mu=1e-2, tol=1e-8, eta=0.1, itol=0.1,
     form (adjoint solve on A^T, then the pattern gradient) on the same
     handle type; the solutions are returned for the accuracy check against
     the closed-form regularised solution (made on the host with the CPU
-    baseline)."""
+    baseline).  Block fraction and inner settings per form come from the
+    tuner cache (tuned on the first tune_rhs right-hand sides, the same
+    interleaved path, timed to tune_tol), eta / itol / imax when nothing is
+    cached."""
     import torch
     import paper_2509_19267_amd as rg
     import workloads
@@ -892,14 +896,27 @@ def c4_deblur(npix=512, nrhs=64, mu=1e-2, tol=1e-8, eta=0.1, itol=0.1,
     st = torch.cuda.Stream()
     out = {"workload": f"deblur_tikhonov_{npix}x{npix}_nrhs{nrhs}",
            "rows": int(m), "cols": int(n), "nnz": int(aug.nnz), "mu": mu,
-           "stop": "res_ext", "tol": tol, "eta": eta, "inner_tol": itol,
-           "inner_max": imax}
+           "stop": "res_ext", "tol": tol}
+    tb = torch.as_tensor(bb[:tune_rhs].ravel()).cuda()
+    chs = {}
+    for form in ["fp64", "mixed_f32"]:
+        def make(form=form, **kw):
+            return rg.MultiRhsSolver(csr, (m, n), tune_rhs, stop="res_ext",
+                                     tol=tune_tol, max_iter=max_iter,
+                                     precision=form, stream=st, **kw)
+        chs[form] = sparse_choice(f"multirhs:deblur_{npix}x{npix}:{form}",
+                                  tune_now, make, tb, None,
+                                  dict(eta=eta, inner_tol=itol, inner_max=imax,
+                                       graph_iters=8), tol=tune_tol,
+                                  etas=(0.3, 0.5))   # 0.1-0.3: best at 0.3
+    del tb
     sols = {}
     for form in ["fp64", "mixed_f32"]:
+        kw = {k: chs[form][k] for k in SPARSE_KEYS if k in chs[form]}
         tc = time.perf_counter()
-        s = rg.MultiRhsSolver(csr, (m, n), nrhs, eta=eta, stop="res_ext",
-                              tol=tol, max_iter=max_iter, inner_tol=itol,
-                              inner_max=imax, precision=form, stream=st)
+        s = rg.MultiRhsSolver(csr, (m, n), nrhs, stop="res_ext", tol=tol,
+                              max_iter=max_iter, precision=form, stream=st,
+                              **kw)
         torch.cuda.synchronize()
         create = time.perf_counter() - tc
         torch.cuda.synchronize()
@@ -914,8 +931,44 @@ def c4_deblur(npix=512, nrhs=64, mu=1e-2, tol=1e-8, eta=0.1, itol=0.1,
                      "outer": int(info["outer_iterations"]),
                      "converged_rhs": int(sum(bool(c) for c in conv)),
                      "metric_max": float(max(met)),
-                     "create_s": round(create, 3)}
+                     "create_s": round(create, 3), "choice": kw}
         log(f"c4 {form}: {out[form]}")
+    # the interleaved residual pass pair alone (rgdbek_apply: transpose,
+    # product and epilogue for A x and for A^T z over all right-hand sides),
+    # HIP events on the handle's stream
+    s = rg.MultiRhsSolver(csr, (m, n), nrhs, eta=eta, precision="mixed_f32",
+                          stream=st)
+    rates = {}
+    for prec, dt, vb in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        xv = torch.randn(n * nrhs, dtype=dt, device="cuda")
+        zv = torch.randn(m * nrhs, dtype=dt, device="cuda")
+        ax = torch.empty(m * nrhs, dtype=dt, device="cuda")
+        atz = torch.empty(n * nrhs, dtype=dt, device="cuda")
+        for _ in range(3):
+            s.apply(xv, zv, ax, atz, precision=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(10):
+            s.apply(xv, zv, ax, atz, precision=prec)
+        e1.record(st)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / 10
+        nz = int(aug.nnz)
+        # the operation's bytes: A once per pass, each pass reading its
+        # input vectors and writing its output once (the interleaved
+        # staging copies are the implementation's, not counted)
+        alg = (2 * nz * (vb + 4) + 8 * (m + 1) + 8 * (n + 1)
+               + 2 * vb * nrhs * (m + n))
+        rates[prec] = {"us_per_pair": round(us, 1), "alg_bytes": alg,
+                       "GB/s": round(alg / us / 1e3, 1),
+                       "frac": round(alg / us / 1e3 / PEAK_HBM_GBS, 4),
+                       "gather_GB/s": round(2 * nz * nrhs * vb / us / 1e3, 1)}
+        del xv, zv, ax, atz
+    s.close()
+    out["residual_pass_pair"] = rates
+    log(f"c4 pass pair: {rates}")
     # the differentiable layer x_s = [A; sI]^+ b_s (FP64 values: the same
     # FP32-exact matrix), L = sum_s <c_s, x_s>: forward, then the backward's
     # adjoint solve on A^T, second solve lam = A^+ w and pattern gradient
@@ -923,10 +976,10 @@ def c4_deblur(npix=512, nrhs=64, mu=1e-2, tol=1e-8, eta=0.1, itol=0.1,
     v64 = torch.as_tensor(workloads.to_csr_arrays(aug)[2]).cuda()
     vg = v64.clone().requires_grad_(True)
     bt = b.clone().requires_grad_(True)
-    s = rg.MultiRhsSolver((csr[0], csr[1], v64), (m, n), nrhs, eta=eta,
+    kw = {k: chs["fp64"][k] for k in SPARSE_KEYS if k in chs["fp64"]}
+    s = rg.MultiRhsSolver((csr[0], csr[1], v64), (m, n), nrhs,
                           stop="res_ext", tol=tol, max_iter=max_iter,
-                          inner_tol=itol, inner_max=imax, precision="fp64",
-                          stream=st)
+                          precision="fp64", stream=st, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     x = rg.solve(s, vg, bt, least_squares=True)

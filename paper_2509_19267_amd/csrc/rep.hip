@@ -88,9 +88,72 @@ rep_mm_kernel(Csr<T> A, const T *__restrict__ in, T *__restrict__ out,
   }
 }
 
+// At most 32 right-hand sides: a wave takes 64/GR stored rows, GR lanes
+// each (lane = right-hand side), so that few right-hand sides do not leave
+// most lanes idle.  Each lane loads its row's entries itself (the lanes of
+// a group read the same address) and gathers GR contiguous values per
+// entry.
+template <typename T, int GR>
+__global__ void __launch_bounds__(REP_NT)
+rep_mm_group_kernel(Csr<T> A, const T *__restrict__ in, T *__restrict__ out,
+                    double *__restrict__ part, Ctrl *ctrl, int ph,
+                    int respect_done) {
+  if (respect_done && ctrl_done(ctrl)) return;
+  if (ph >= 0 && cg_done_at_start(ctrl, ph)) return;
+  __shared__ double sh[REP_NT / WAVE];
+  constexpr int RPW = WAVE / GR;          // stored rows per wave
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int ls = lane % GR;
+  const int64_t R = A.rep;                // R <= GR
+  const bool live = ls < R;
+  const int64_t row = ((int64_t)blockIdx.x * REP_ROWS + threadIdx.x / WAVE) * RPW +
+                      lane / GR;
+  T acc = (T)0;
+  if (row < A.brows) {
+    const T *col = in + (live ? ls : 0);
+    const int64_t e0 = A.ptr[row], e1 = A.ptr[row + 1];
+    int64_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      int32_t ix[4];
+      T v[4], g[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ix[u] = A.idx[e + u];
+        v[u] = A.val[e + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) g[u] = col[(int64_t)ix[u] * R];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += v[u] * g[u];
+    }
+    for (; e < e1; ++e) acc += A.val[e] * col[(int64_t)A.idx[e] * R];
+    if (live) out[row * R + ls] = acc;
+  }
+  if (part) {
+    const double q = (row < A.brows && live) ? (double)acc * (double)acc : 0.0;
+    const double t = block_sum<REP_NT>(q, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  }
+}
+
 template <typename T>
 int launch_rep_mm(const Csr<T> &A, const T *in, T *out, double *part,
                   Ctrl *ctrl, int ph, int respect_done, hipStream_t st) {
+  if (A.rep <= 32) {
+    const int gr = A.rep <= 16 ? 16 : 32;
+    const int64_t rows_per_block = (int64_t)REP_ROWS * (WAVE / gr);
+    const int64_t gx = (A.brows + rows_per_block - 1) / rows_per_block;
+    if (gx <= 0) return 0;
+    if (gr == 16)
+      hipLaunchKernelGGL((rep_mm_group_kernel<T, 16>), dim3((unsigned)gx),
+                         dim3(REP_NT), 0, st, A, in, out, part, ctrl, ph,
+                         respect_done);
+    else
+      hipLaunchKernelGGL((rep_mm_group_kernel<T, 32>), dim3((unsigned)gx),
+                         dim3(REP_NT), 0, st, A, in, out, part, ctrl, ph,
+                         respect_done);
+    return (int)gx;
+  }
   const int64_t gx = (A.brows + REP_ROWS - 1) / REP_ROWS;
   const int64_t gy = (A.rep + WAVE - 1) / WAVE;
   if (gx <= 0 || gy <= 0) return 0;

@@ -702,7 +702,7 @@ def test_multirhs_gradient_layer(rg, R):
     s.close()
 
 
-@pytest.mark.parametrize("R", [5, 20, 64, 70])
+@pytest.mark.parametrize("R", [5, 16, 20, 64, 70])
 def test_multirhs_apply(rg, R):
     # (A x_s, A^T z_s) for every right-hand side in one residual pass, FP64
     # and (on a mixed handle) FP32, against the products done one by one
