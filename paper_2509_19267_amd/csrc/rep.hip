@@ -7,9 +7,10 @@
 // and 64 right-hand sides, one per lane: the row's entries are loaded once
 // by the wave and broadcast lane by lane (v_readlane), and the values the
 // lanes gather for one entry are 64 contiguous elements (one 512-byte run
-// in FP64).  The right-hand-side-major layout of the rest of the solver
-// would make each lane gather from a different vector, and each stored
-// entry would be read once per right-hand side.
+// in FP64).  With at most 32 right-hand sides a wave takes 2 or 4 rows, 32
+// or 16 lanes each.  The right-hand-side-major layout of the rest of the
+// solver would make each lane gather from a different vector, and each
+// stored entry would be read once per right-hand side.
 #include "common.h"
 #include "kernels.h"
 
