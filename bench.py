@@ -69,6 +69,9 @@ def parse():
                     "many-right-hand-side passes and two mixed iterations "
                     "on the 512^2 deblurring operator with 64 right-hand "
                     "sides")
+    ap.add_argument("--probe-batch", action="store_true",
+                    help="profiler-run program: the 256 batched Laplacian "
+                    "systems, residual passes and 40 tuned FP64 iterations")
     ap.add_argument("--probe-solve", action="store_true",
                     help="counter probe: the 1 GiB device copy (calibration), "
                          "then one solve per form at the tuned settings")
@@ -227,6 +230,46 @@ def probe_multirhs():
     s.close()
     print(json.dumps({"probe": "done", "m": m, "n": n, "nnz": int(aug.nnz),
                       "nrhs": nrhs}))
+
+
+def probe_batch(iters=40):
+    """Short program for profiler runs of the batched path: the 256 uneven
+    Laplacian systems (FP32-exact values, FP64 handle), three batched
+    residual pass pairs (rgdbek_apply), then `iters` FP64 iterations at the
+    cached tuned settings (stop none, graphs on)."""
+    import torch
+    import paper_2509_19267_amd as rg
+    from paper_2509_19267_amd import block_diagonal, tune
+    import workloads
+    ps = workloads.laplacian_batch(count=256, n_min=2000, n_max=200000, seed=0)
+    mats = []
+    for p in ps:
+        a = p.a.copy()
+        a.data = a.data.astype(np.float32).astype(np.float64)
+        mats.append(a)
+    rp, ci, v, ro, co = block_diagonal(mats)
+    csr = (torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(),
+           torch.as_tensor(v).cuda())
+    b = torch.as_tensor(np.concatenate([a @ p.x_star
+                                        for a, p in zip(mats, ps)])).cuda()
+    ch = tune._load().get("batch:laplacian_256:fp64") or {}
+    kw = {k: ch[k] for k in SPARSE_KEYS if k in ch}
+    s = rg.BatchSolver(csr, ro, co, stop="none", max_iter=iters, **kw)
+    m, n = int(ro[-1]), int(co[-1])
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    z = torch.randn(m, dtype=torch.float64, device="cuda")
+    ax = torch.empty(m, dtype=torch.float64, device="cuda")
+    atz = torch.empty(n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        s.apply(x, z, ax, atz)
+    torch.cuda.synchronize()
+    log("batched pass pair: 3 launches")
+    s.solve(b)
+    torch.cuda.synchronize()
+    log(f"batched solve: {iters} iterations, {kw}")
+    s.close()
+    print(json.dumps({"probe": "done", "systems": 256, "m": m, "n": n,
+                      "nnz": int(len(v)), "choice": kw}))
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dense_fused_pass_20000x5000_hbm.md")
@@ -434,6 +477,9 @@ def main():
         return
     if args.probe_multirhs:
         probe_multirhs()
+        return
+    if args.probe_batch:
+        probe_batch()
         return
     if args.probe_solve:
         probe_solve(args)
