@@ -1099,11 +1099,11 @@ def c5_batch(count=256, tol=1e-8, subset=32, tune_now=False):
             return rg.BatchSolver(c, sro, sco, stop="err_ref", tol=tol,
                                   max_iter=100000, precision=form, stream=st,
                                   **kw)
-        # (the first sweep over 0.05-0.2 was fastest at 0.2)
+        # (earlier sweeps: over 0.05-0.2 fastest at 0.2, over 0.2-0.5 at 0.5)
         chs[form] = sparse_choice(f"batch:laplacian_{count}:{form}", tune_now,
                                   make, sb, sx, dict(eta=0.1, inner_tol=0.1,
                                                      inner_max=16, graph_iters=8),
-                                  etas=(0.2, 0.3, 0.5))
+                                  etas=(0.5, 0.7, 1.0))
     del sub64, sb, sx
     for form, c in [("fp64", csr64),
                     ("mixed_f32", (csr64[0], csr64[1], csr64[2].to(torch.float32)))]:
