@@ -874,6 +874,7 @@ def c3_powerlaw(tol=1e-8, tune_now=False, tune_tol=1e-4):
                            lambda **kw: make(tol=tune_tol, **kw), b, xs,
                            dict(eta=0.2, inner_tol=0.1, inner_max=16,
                                 graph_iters=8), tol=tune_tol,
+                           # (FP64 swept again over 0.5-1.0: best at 0.5)
                            etas=(0.2, 0.3, 0.5))
         chs[form] = ch
         kw = {k: ch[k] for k in SPARSE_KEYS if k in ch}
