@@ -451,8 +451,9 @@ void build_engine(rgdbek_ctx *h, Engine<T> &e, bool transpose) {
           launch_mark_long<T>(M, w.long_flag, h->st);
         }
         // lanes per row of the copy from its expected row length (the
-        // block's share of each row's entries)
-        w.group = pick_group(M.rows ? (double)h->nnz / (double)M.rows * share : 1.0);
+        // block's share of each stored row's entries)
+        w.group = pick_group(M.brows ? (double)h->nnz / (double)M.brows * share
+                                     : 1.0);
       };
       share = e.n ? (double)e.kc / (double)e.n : 1.0;
       sub(e.subc, a, capc, e.n);
