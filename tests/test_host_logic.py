@@ -49,3 +49,40 @@ def test_bench_defaults(monkeypatch):
     a = bench.parse()
     assert a.gpus == 1 and a.steps >= 1 and a.warmup >= 0
     assert (a.m, a.n, a.tol) == (20000, 5000, 1e-8)
+
+
+def test_deblur_cpu_leg_checks_against_closed_form():
+    # the deblurring workload's CPU leg compares solutions and gradients
+    # with the Kronecker closed forms: fed the dense least-squares solutions
+    # and the dense pinv gradients of a 16 x 16 instance it must report
+    # agreement to rounding
+    import numpy as np
+    import workloads
+    from oracle.refsol import grad_reference
+    aug, t, s = workloads.blur_tikhonov(npix=16, mu=1e-2)
+    n, nrhs = 256, 2
+    rng = np.random.default_rng(0)
+    b_img = rng.standard_normal((n, nrhs))
+    cs = rng.standard_normal((nrhs, n))
+    ad = aug.toarray()
+    ac = aug.tocsr()
+    ac.sort_indices()
+    rows = np.repeat(np.arange(ac.shape[0]), np.diff(ac.indptr))
+    xs, dbs, dv = [], [], np.zeros(aug.nnz)
+    for r in range(nrhs):
+        bb = np.concatenate([b_img[:, r], np.zeros(n)])
+        xs.append(np.linalg.lstsq(ad, bb, rcond=None)[0])
+        da, w = grad_reference(ad, bb, cs[r])
+        dbs.append(w)
+        dv += da[rows, ac.indices]
+    ctx = {"c4": {"t": t, "s": s, "b_img": b_img,
+                  "sols": {"fp64": np.array(xs).T}, "aug": aug,
+                  "grads": {"x": np.array(xs).T, "db": np.array(dbs).T,
+                            "dv": dv, "c": cs.T}}}
+    out = bench.cpu_baseline_full(["c4"], ctx, budget_s=0.2)
+    assert out["c4_rel_err_vs_closed_form_max"]["fp64"] <= 1e-10
+    g = out["c4_differentiable_vs_closed_form"]
+    assert g["x_rel_err_max"] <= 1e-10
+    assert g["db_rel_err"] <= 1e-10
+    assert g["dA_sampled_rel_err"] <= 1e-10
+    assert out["c4"]["iterations"] >= 1
