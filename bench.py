@@ -832,11 +832,12 @@ def sparse_choice(key, tune_now, make, b, xs, default, tol=1e-8,
                   etas=(0.05, 0.1, 0.2)):
     """Tuned settings of a sparse workload (eta, inner tolerance and step
     cap, iterations per graph, mixed pass drop) from the tuner cache, tuned
-    now if asked (block fractions from `etas`)."""
+    now if asked (block fractions from `etas`, extended up the tuner's
+    ladder while the largest one tried wins)."""
     from paper_2509_19267_amd import tune
     if tune_now:
         return tune.tune_sparse(make, b, xs, key=key, log=log, tol=tol,
-                                etas=etas,
+                                etas=etas, extend=True,
                                 pass_drops=(1e-3, 1e-4, 1e-5)
                                 if key.endswith("mixed_f32") else ())
     return tune._load().get(key) or dict(default)

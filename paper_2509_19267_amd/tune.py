@@ -194,19 +194,37 @@ def tune_dense(a, b, x_ref, *, stream=None, tol=1e-8, log=print,
     return ch
 
 
+# block fractions the sparse tuner may extend its grid to, in order
+ETA_LADDER = (0.05, 0.1, 0.2, 0.3, 0.5, 0.7, 1.0)
+
+
+def next_eta(eta):
+    """The ladder's next block fraction above eta (None at the top)."""
+    for e in ETA_LADDER:
+        if e > eta + 1e-12:
+            return e
+    return None
+
+
 def tune_sparse(make, b, x_ref, *, key, tol=1e-8, log=print, reps=1,
                 etas=(0.05, 0.1, 0.2),
                 inner=((0.5, 2), (0.3, 4), (0.1, 8), (0.1, 16), (0.03, 16)),
-                graph_iters=(4, 8, 16), pass_drops=()):
+                graph_iters=(4, 8, 16), pass_drops=(), extend=False):
     """Tune a sparse solve (single system, batch or many right-hand sides):
     `make(eta=, inner_tol=, inner_max=, graph_iters=[, pass_drop=])` builds a
-    handle with stop ERR_REF at tol; each setting is timed over `reps`
-    solves after one warm-up solve (graph capture).  Block fraction and
-    inner settings first, then the iterations per captured graph, then (for
-    the mixed form) the drop that ends a refinement pass, each at the best
-    of the earlier stages; the fastest converging choice is cached under
-    `key` and returned."""
+    handle (the caller picks its stop test and tol); each setting is timed
+    over `reps` solves after one warm-up solve (graph capture).  Block
+    fraction and inner settings first -- with `extend`, while the largest
+    block fraction tried is the fastest, the next one of ETA_LADDER is tried
+    too -- then the iterations per captured graph, then (for the mixed form)
+    the drop that ends a refinement pass, each at the best of the earlier
+    stages; the fastest converging choice is cached under `key` and
+    returned."""
     import torch
+
+    def sync():
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
 
     def run(ch, best):
         try:
@@ -218,10 +236,10 @@ def tune_sparse(make, b, x_ref, *, key, tol=1e-8, log=print, reps=1,
             s.solve(b, x_ref=x_ref)
             ts, ok, its = [], True, 0
             for _ in range(reps):
-                torch.cuda.synchronize()
+                sync()
                 t0 = time.perf_counter()
                 _, info = s.solve(b, x_ref=x_ref)
-                torch.cuda.synchronize()
+                sync()
                 ts.append(time.perf_counter() - t0)
                 ok = ok and bool(info["converged"])
                 its = info["iterations"]
@@ -234,21 +252,36 @@ def tune_sparse(make, b, x_ref, *, key, tol=1e-8, log=print, reps=1,
         return best
 
     best = None
-    for eta in etas:
+    tried = []
+
+    def sweep(eta, best):
+        tried.append(eta)
         for itol, imax in inner:
             best = run(dict(eta=eta, inner_tol=itol, inner_max=imax,
                             graph_iters=8), best)
+        return best
+
+    for eta in etas:
+        best = sweep(eta, best)
+    while extend and best is not None and best[1]["eta"] >= max(tried):
+        nxt = next_eta(max(tried))
+        if nxt is None:
+            break
+        best = sweep(nxt, best)
     if best is None:
         raise RuntimeError(f"no configuration of {key} converged")
+    best[1]["etas_tried"] = sorted(tried)
     base = {k: best[1][k] for k in ("eta", "inner_tol", "inner_max")}
     for gi in graph_iters:
         if gi != 8:
             best = run(dict(base, graph_iters=gi), best)
+    best[1]["etas_tried"] = sorted(tried)
     if pass_drops:
         base = {k: best[1][k] for k in ("eta", "inner_tol", "inner_max",
                                         "graph_iters")}
         for pd in pass_drops:
             best = run(dict(base, pass_drop=pd), best)
+    best[1]["etas_tried"] = sorted(tried)
     c = _load()
     c[key] = best[1]
     try:

@@ -86,3 +86,32 @@ def test_deblur_cpu_leg_checks_against_closed_form():
     assert g["db_rel_err"] <= 1e-10
     assert g["dA_sampled_rel_err"] <= 1e-10
     assert out["c4"]["iterations"] >= 1
+
+
+def test_sparse_tuner_extends_its_block_fraction_grid(tmp_path, monkeypatch):
+    # a stand-in handle whose solve time is smallest at eta = 0.7: started
+    # on (0.2, 0.3, 0.5), the tuner must climb the ladder to 0.7, try 1.0,
+    # and keep 0.7; without `extend` it stops at the grid's edge
+    import time as _time
+    monkeypatch.setattr(tune, "CACHE", str(tmp_path / "t.json"))
+
+    class Fake:
+        def __init__(self, eta, inner_tol, inner_max, graph_iters, **_):
+            self.eta = eta
+
+        def solve(self, b, x_ref=None):
+            _time.sleep(0.002 + 0.01 * abs(self.eta - 0.7))
+            return None, {"converged": True, "iterations": 10}
+
+        def close(self):
+            pass
+
+    got = tune.tune_sparse(Fake, None, None, key="fake", log=lambda *_: None,
+                           etas=(0.2, 0.3, 0.5), graph_iters=(8,),
+                           extend=True)
+    assert got["eta"] == 0.7
+    assert got["etas_tried"] == [0.2, 0.3, 0.5, 0.7, 1.0]
+    got = tune.tune_sparse(Fake, None, None, key="fake2", log=lambda *_: None,
+                           etas=(0.2, 0.3, 0.5), graph_iters=(8,))
+    assert got["eta"] == 0.5 and got["etas_tried"] == [0.2, 0.3, 0.5]
+    assert tune.next_eta(1.0) is None and tune.next_eta(0.5) == 0.7
