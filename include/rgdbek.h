@@ -157,9 +157,10 @@ enum { RGDBEK_FLAG_GRAPH = 1, RGDBEK_FLAG_GRAM_AAT = 2,
 /* RGDBEK_FLAG_SPARSE_FULL: the matrix-free sparse block projections stream
  * all of A in every CG step (as a product with a vector that is zero off the
  * block) instead of a copy of the block's own entries made once per
- * iteration (the default for one stored matrix; the many-right-hand-side
- * operator always streams A).  The same sums, grouped differently across
- * lanes: results agree to rounding. */
+ * iteration (the default for one stored matrix and for fewer than 16
+ * right-hand sides; from 16 on, the many-right-hand-side products read A
+ * once for all right-hand sides and make no copies).  The same sums,
+ * grouped differently across lanes: results agree to rounding. */
 /* RGDBEK_FLAG_PROFILE times every step of every iteration with HIP events on
  * the handle's stream (the launches are then issued one by one, not from
  * captured graphs, so a profiled solve runs a little slower than a plain
